@@ -1,0 +1,95 @@
+"""ctypes wrapper over the oracle's C code (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+from . import build as _build
+
+GM1 = 0.4     # gamma - 1 as the binary64 literal nearest 0.4
+EPS_D = 0.25  # dissipation coefficient (dyadic)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.OUT):
+            _build.build()
+        L = ct.CDLL(_build.OUT)
+        P = ct.c_void_p
+        L.oracle_lf2d_flux.argtypes = [P, P, P, P, ct.c_double, ct.c_double,
+                                       ct.c_double, ct.c_double, P]
+        L.oracle_lf2d_flux.restype = None
+        L.oracle_edge_loop.argtypes = [ct.c_int64, P, P, P, P, P, ct.c_double,
+                                       ct.c_double, P]
+        L.oracle_edge_loop.restype = None
+        L.oracle_edge_fluxes.argtypes = L.oracle_edge_loop.argtypes
+        L.oracle_edge_fluxes.restype = None
+        L.oracle_first_fit.argtypes = [ct.c_int64, P, P, ct.c_int64, ct.c_int32,
+                                       P, P, P, P, P]
+        L.oracle_first_fit.restype = ct.c_int32
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ct.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def flux(xa, xb, qL, qR, adtL, adtR, gm1=GM1, eps=EPS_D) -> np.ndarray:
+    """Flux of one edge, from L into R."""
+    xa = _c(xa, np.float64); xb = _c(xb, np.float64)
+    qL = _c(qL, np.float64); qR = _c(qR, np.float64)
+    f = np.zeros(4)
+    lib().oracle_lf2d_flux(_p(xa), _p(xb), _p(qL), _p(qR), float(adtL),
+                           float(adtR), float(gm1), float(eps), _p(f))
+    return f
+
+
+def edge_loop(e2n, e2c, x, q, adt, gm1=GM1, eps=EPS_D, res=None) -> np.ndarray:
+    """res[C][4] after the sequential loop (starting from res, default 0)."""
+    e2n = _c(e2n, np.int32); e2c = _c(e2c, np.int32)
+    x = _c(x, np.float64); q = _c(q, np.float64); adt = _c(adt, np.float64)
+    C = q.shape[0]
+    out = np.zeros((C, 4)) if res is None else _c(res, np.float64).copy()
+    lib().oracle_edge_loop(e2n.shape[0], _p(e2n), _p(e2c), _p(x), _p(q),
+                           _p(adt), float(gm1), float(eps), _p(out))
+    return out
+
+
+def edge_fluxes(e2n, e2c, x, q, adt, gm1=GM1, eps=EPS_D) -> np.ndarray:
+    e2n = _c(e2n, np.int32); e2c = _c(e2c, np.int32)
+    x = _c(x, np.float64); q = _c(q, np.float64); adt = _c(adt, np.float64)
+    f = np.zeros((e2n.shape[0], 4))
+    lib().oracle_edge_fluxes(e2n.shape[0], _p(e2n), _p(e2c), _p(x), _p(q),
+                             _p(adt), float(gm1), float(eps), _p(f))
+    return f
+
+
+def first_fit(off, pts, npts: int, max_colours: int = 1 << 20):
+    """First-fit greedy colours for elements writing pts[off[i]:off[i+1]].
+
+    Returns (colour[n] int32, ncolours) or (None, -1) past max_colours.
+    """
+    off = _c(off, np.int64); pts = _c(pts, np.int32)
+    n = off.shape[0] - 1
+    colour = np.full(n, -1, np.int32)
+    head = np.empty(max(npts, 1), np.int64)
+    nl = max(int(off[-1]), 1)
+    link = np.empty(nl, np.int64)
+    ucol = np.empty(nl, np.int32)
+    stamp = np.empty(max_colours + 1, np.int64)
+    nc = lib().oracle_first_fit(n, _p(off), _p(pts), npts, max_colours,
+                                _p(colour), _p(head), _p(link), _p(ucol),
+                                _p(stamp))
+    if nc < 0:
+        return None, -1
+    return colour, int(nc)
