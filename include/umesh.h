@@ -1,0 +1,335 @@
+/*
+ * umesh.h -- race-free indirect-increment mesh loops on AMD MI355X (gfx950).
+ *
+ * C ABI of libumesh.so.  Plain integers, host pointers and device pointers
+ * only; no C++ or framework types cross it.  Every entry point returns a
+ * um_status; no exception crosses the boundary.  On failure the message of
+ * the failing call is available from um_last_error() on the same thread.
+ *
+ * Model (Sulyok et al., "Locality optimized unstructured mesh algorithms on
+ * GPUs", Section 1.1.1 "Unstructured meshes"): a mesh is a collection of
+ * sets (elements numbered 0..size-1), maps (fixed-arity tables from every
+ * element of a from-set to elements of a to-set, one level of indirection)
+ * and dats (dim values per element of a set).  A loop runs an elemental
+ * kernel over every element of an iteration set, reading data directly or
+ * through one map, and may increment data on the to-set of a map, so that
+ * several iterations update the same point.  The result must not depend on
+ * the processing order beyond rounding.
+ *
+ * Execution strategies (Section 2.1 and 2.2):
+ *   UM_STRAT_ATOMIC        one launch, increments with device atomics;
+ *   UM_STRAT_GLOBAL_COLOUR elements coloured so no two of one colour write
+ *                          the same point, one launch per colour;
+ *   UM_STRAT_HIER          two-layer (hierarchical) colouring: elements are
+ *                          grouped in blocks, blocks coloured so concurrent
+ *                          blocks never write the same point (one launch per
+ *                          block colour), each block stages its indirect data
+ *                          and its increments in LDS, and elements inside a
+ *                          block are coloured so that increments into LDS are
+ *                          applied one colour at a time (Algorithm 1).
+ * Reordering (Section 2.3): Cuthill-McKee style renumbering of points and a
+ * lexicographic sort of elements (Section 2.3.1), partition-based element
+ * blocks (Section 2.3.2) and grouping of points by the set of blocks that
+ * access them (Section 2.3.2, cache-line heuristic).
+ *
+ * Threading: a um_ctx and its plans are not thread-safe; use one context
+ * per host thread.  Device work is enqueued on the caller's HIP stream and
+ * never synchronised by the library except where stated.
+ */
+#ifndef UMESH_H
+#define UMESH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define UMESH_ABI_VERSION 1
+
+typedef struct um_ctx_s *um_ctx;
+typedef struct um_plan_s *um_plan;
+
+typedef enum {
+    UM_OK = 0,
+    UM_ERR_ARG = -1,         /* null pointer, bad enum, bad size            */
+    UM_ERR_RANGE = -2,       /* map entry outside its to-set, bad id        */
+    UM_ERR_ARITY = -3,       /* argument pattern does not fit the kernel    */
+    UM_ERR_COLOURS = -4,     /* block colours exceed max_block_colours      */
+    UM_ERR_LDS = -5,         /* staging exceeds the LDS limit, no fallback  */
+    UM_ERR_HIP = -6,         /* a HIP runtime call failed                   */
+    UM_ERR_STATE = -7,       /* call not valid in the current state         */
+    UM_ERR_NOMEM = -8,       /* host or device allocation failed            */
+    UM_ERR_UNSUPPORTED = -9  /* valid request the library does not provide  */
+} um_status;
+
+typedef enum { UM_F64 = 0, UM_F32 = 1 } um_dtype;
+/* AoS: element-major [n][dim].  SoA: component-major [dim][n]
+ * (Section 2.1.1 "Array-of-Structures (AoS) vs Structure-of-Arrays"). */
+typedef enum { UM_AOS = 0, UM_SOA = 1 } um_layout;
+typedef enum { UM_READ = 0, UM_WRITE = 1, UM_RW = 2, UM_INC = 3 } um_access;
+typedef enum {
+    UM_STRAT_ATOMIC = 0,
+    UM_STRAT_GLOBAL_COLOUR = 1,
+    UM_STRAT_HIER = 2
+} um_strategy;
+typedef enum {
+    UM_REORDER_NONE = 0,
+    UM_REORDER_RCM = 1,       /* reverse Cuthill-McKee numbering of points   */
+    UM_REORDER_GPS = 2,       /* forward Cuthill-McKee (level order) numbering */
+    UM_REORDER_PARTITION = 3  /* partition elements into blocks, renumber    */
+} um_reorder;
+/* What a hierarchical block stages in LDS (Section 2.2; increments-only
+ * staging is the fallback the paper needed when the staged data did not fit
+ * in on-chip memory, Section 3.1.5). */
+typedef enum { UM_STAGE_ALL = 0, UM_STAGE_INC_ONLY = 1 } um_staging;
+/* How increments inside a block are serialised: colour rounds separated by
+ * workgroup barriers (Algorithm 1), or LDS floating-point atomics without
+ * thread colours (an extension; order inside a block is not fixed). */
+typedef enum { UM_TC_BARRIER = 0, UM_TC_LDS_ATOMIC = 1 } um_tcmode;
+
+/* Elemental kernels compiled into the library (no run-time code generation).
+ *
+ * UM_K_EDGE_FLUX_LF2D -- 2D finite-volume edge flux (the Airfoil res_calc
+ * access pattern of Section 3.1.1: per edge, read 2 coordinates on each of 2
+ * nodes, read 4 conserved values and 1 time-step value on each of 2 cells,
+ * increment 4 residual values on both cells).  Required args, in order:
+ *   0: x   dim 2 via edge->node map slot 0, UM_READ
+ *   1: x   dim 2 via edge->node map slot 1, UM_READ
+ *   2: q   dim 4 via edge->cell map slot 0, UM_READ
+ *   3: q   dim 4 via edge->cell map slot 1, UM_READ
+ *   4: adt dim 1 via edge->cell map slot 0, UM_READ
+ *   5: adt dim 1 via edge->cell map slot 1, UM_READ
+ *   6: res dim 4 via edge->cell map slot 0, UM_INC
+ *   7: res dim 4 via edge->cell map slot 1, UM_INC
+ * Both maps have arity 2 and the iteration set as from-set; x, q, adt and
+ * res are UM_F64 (or x, q, adt UM_F32 with res UM_F64 once provided).
+ * params = {gm1, eps}.  Per edge, with n = (y_b - y_a, x_a - x_b):
+ *   per side s: ri = 1/q0, u = q1 ri, v = q2 ri,
+ *               p = gm1 (q3 - 0.5 (q1 u + q2 v)), U = u n_x + v n_y,
+ *               F = (q0 U, q1 U + p n_x, q2 U + p n_y, (q3 + p) U)
+ *   mu = eps 0.5 (adt_L + adt_R)
+ *   f  = 0.5 (F_L + F_R) + 0.5 mu (q_L - q_R)
+ *   res[L] += f, res[R] -= f.
+ */
+typedef enum { UM_K_EDGE_FLUX_LF2D = 0 } um_kernel;
+
+/* One loop argument: dat `dat` accessed through slot `idx` of map `map`
+ * (map = -1: direct access on the iteration set) with access mode `acc`. */
+typedef struct {
+    int32_t dat;
+    int32_t map;
+    int32_t idx;
+    int32_t acc; /* um_access */
+} um_arg;
+
+typedef struct {
+    int32_t mode;          /* um_reorder                                     */
+    int32_t driving_map;   /* map whose to-set is renumbered (RCM/GPS) and
+                              whose from-set is partitioned (PARTITION)      */
+    int32_t block_size;    /* PARTITION: maximum elements per block, 1..1024 */
+    int32_t point_reorder; /* PARTITION: 1 = group points of every to-set by
+                              accessing-block signature, 0 = keep order      */
+    int32_t coord_map;     /* PARTITION, optional: map from the partitioned set
+                              whose to-set carries `coords`; -1 = none, then
+                              a graph-distance embedding is used instead     */
+    int32_t coord_dim;     /* 1..3                                           */
+    const double *coords;  /* host [size(to-set of coord_map)][coord_dim],
+                              current numbering; read during the call only   */
+    int32_t reserved[2];
+} um_reorder_opts;
+
+typedef struct {
+    int32_t strategy;          /* um_strategy                                */
+    int32_t block_size;        /* HIER: elements per block = workgroup size,
+                                  64..1024; others: workgroup size, 64..1024 */
+    int32_t staging;           /* um_staging (HIER)                          */
+    int32_t tcmode;            /* um_tcmode (HIER)                           */
+    int32_t max_block_colours; /* HIER: 0 means 256 (Section 3.1.5 limit)      */
+    int32_t lds_limit_bytes;   /* HIER: 0 means the device's per-workgroup
+                                  limit (163840 on gfx950; 65536 host-only)  */
+    int32_t allow_fallback;    /* HIER: 1 = STAGE_ALL over the LDS limit falls
+                                  back to STAGE_INC_ONLY instead of failing  */
+    int32_t reserved[5];
+} um_plan_opts;
+
+typedef struct {
+    int32_t strategy;
+    int32_t staging;             /* staging actually used (after fallback)   */
+    int32_t block_size;
+    int32_t n_blocks;            /* HIER                                     */
+    int32_t n_block_colours;     /* HIER                                     */
+    int32_t n_global_colours;    /* GLOBAL_COLOUR                            */
+    int32_t max_thread_colours;  /* HIER                                     */
+    int32_t n_launches;          /* kernel launches per um_loop_exec         */
+    double avg_thread_colours;   /* HIER, mean over blocks                   */
+    double reuse_factor;         /* HIER: sum over blocks of arity*|B| over
+                                    sum of staged points, driving INC map    */
+    int64_t n_elements;
+    int64_t staged_points;       /* HIER: total staged points, all maps      */
+    int64_t lds_bytes_max;       /* HIER: largest per-block LDS footprint    */
+    int64_t plan_device_bytes;   /* device memory owned by the plan          */
+    double build_seconds;        /* host wall time of um_plan_build          */
+    int64_t reserved[4];
+} um_plan_stats;
+
+/* Plan contents that can be copied out for verification (um_plan_export). */
+typedef enum {
+    UM_EXP_BLOCK_OFFSETS = 0,   /* int32[n_blocks+1]: element ranges, block id order */
+    UM_EXP_BLOCK_COLOURS = 1,   /* int32[n_blocks]                                   */
+    UM_EXP_THREAD_COLOURS = 2,  /* int32[n_elements]: thread colour per element     */
+    UM_EXP_SLOT_ELEMENTS = 3,   /* int32[n_elements]: element executed at each slot;
+                                   slots are grouped by block in launch order        */
+    UM_EXP_GLOBAL_COLOURS = 4,  /* int32[n_elements]: global colour per element      */
+    UM_EXP_STAGED_OFFSETS_A = 5,/* int32[n_blocks+1]: staged points of the first
+                                   indirect map (edge->node for LF2D), block id order */
+    UM_EXP_STAGED_POINTS_A = 6, /* int32[...]: those points                          */
+    UM_EXP_STAGED_OFFSETS_B = 7,/* as above for the INC map (edge->cell for LF2D)    */
+    UM_EXP_STAGED_POINTS_B = 8,
+    UM_EXP_LOCAL_INDEX = 9,     /* int32[n_elements][4]: per slot, local staged index
+                                   of (B slot 0, B slot 1, A slot 0, A slot 1)        */
+    UM_EXP_BLOCK_ORDER = 10     /* int32[n_blocks]: block id at each launch position  */
+} um_export_field;
+
+/* ---------------------------------------------------------------- context */
+
+/* ABI version compiled into the library (UMESH_ABI_VERSION). */
+int32_t um_abi_version(void);
+
+/* Message of the last failing call on this thread ("" if none).  The
+ * pointer stays valid until the next failing call on this thread. */
+const char *um_last_error(void);
+
+/* Create a context on HIP device `device` (>= 0), or a host-only context
+ * (device = -1) that can declare meshes, reorder and build plans but not
+ * execute or touch device memory.  *out receives the handle.
+ * Errors: UM_ERR_ARG (null out, device < -1), UM_ERR_HIP (device unusable). */
+um_status um_create(int32_t device, um_ctx *out);
+
+/* Destroy a context and every plan built from it (device memory released
+ * after a device synchronisation).  NULL is accepted. */
+um_status um_destroy(um_ctx ctx);
+
+/* ------------------------------------------------------------ declaration */
+
+/* Declare a set of `size` elements (size >= 0).  `name` (may be NULL) is
+ * copied.  *set_id receives the id (0, 1, ... in declaration order). */
+um_status um_decl_set(um_ctx ctx, int64_t size, const char *name, int32_t *set_id);
+
+/* Declare a map from every element of `from_set` to `arity` elements of
+ * `to_set` (Section 1.1.1, fixed arity).  host_table is int32
+ * [size(from_set)][arity], row-major, in the sets' current numbering; it is
+ * copied and validated.  Errors: UM_ERR_RANGE if an entry is outside
+ * 0..size(to_set)-1, UM_ERR_ARG for a bad set id or arity outside 1..16. */
+um_status um_decl_map(um_ctx ctx, int32_t from_set, int32_t to_set, int32_t arity,
+                      const int32_t *host_table, int32_t *map_id);
+
+/* Declare a dat of `dim` (1..16) values of type `dtype` per element of
+ * `set`, stored at device address `device_ptr` with `layout`, in the sets'
+ * current numbering.  The memory stays owned by the caller and must outlive
+ * all work that uses it.  device_ptr may be NULL on a host-only context. */
+um_status um_decl_dat(um_ctx ctx, int32_t set, int32_t dim, int32_t dtype, int32_t layout,
+                      void *device_ptr, int32_t *dat_id);
+
+/* Point an existing dat at another device buffer of the same shape. */
+um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr);
+
+/* ------------------------------------------------------------- reordering */
+
+/* Renumber the mesh (Section 2.3).  Must be called before any dat or plan
+ * exists (UM_ERR_STATE otherwise); may be called repeatedly, the
+ * renumberings compose.
+ *   RCM / GPS: the to-set of driving_map is renumbered by a Cuthill-McKee
+ *     traversal of the graph in which the points of each element form a
+ *     clique, from a pseudo-peripheral start (RCM reverses the sequence);
+ *     the from-set is sorted lexicographically by its elements' sorted new
+ *     point ids; every other to-set of a map from that from-set takes
+ *     first-touch order over the sorted elements.
+ *   PARTITION: the from-set of driving_map is split into contiguous blocks
+ *     of at most block_size elements that share as little data as possible
+ *     (recursive bisection along the longest extent of element coordinates:
+ *     the mean of the element's points' `coords` through coord_map, or, if
+ *     no coordinates are given, graph-distance coordinates from BFS
+ *     landmarks on the driving map's point graph); every split keeps each
+ *     side at most (its share of blocks) * block_size elements, so all
+ *     blocks end up at most block_size.  Elements are renumbered block by
+ *     block, keeping their previous relative order inside a block.  With point_reorder, every to-set of a map from the from-set
+ *     is renumbered by (number of accessing blocks, list of accessing
+ *     blocks), ties keeping the previous order.  The blocks are remembered
+ *     and used by HIER plans with the same block_size.
+ * Every map is rewritten into the new numbering. */
+um_status um_reorder_mesh(um_ctx ctx, const um_reorder_opts *opts);
+
+/* Copy the cumulative renumbering of `set` into host int32[size]:
+ * host_new2old[k] = the original (declaration-time) id of current id k. */
+um_status um_get_perm(um_ctx ctx, int32_t set, int32_t *host_new2old);
+
+/* Copy the current table of `map` into host int32[from_size][arity]. */
+um_status um_get_map(um_ctx ctx, int32_t map, int32_t *host_out);
+
+/* Block partition of `set` from the last PARTITION reorder: *n_blocks
+ * receives the count; if host_off is not NULL it receives int32
+ * [n_blocks+1] offsets (capacity in elements).  *block_size receives the
+ * size it was built for (0 if the set has no partition). */
+um_status um_get_blocks(um_ctx ctx, int32_t set, int32_t *block_size, int32_t *n_blocks,
+                        int32_t *host_off, int64_t capacity);
+
+/* Device gather/scatter of a dat between the original numbering and the
+ * current one.  direction 0: dst[k] = src[new2old[k]] (original -> current);
+ * direction 1: dst[new2old[k]] = src[k] (current -> original).  src and dst
+ * are distinct device buffers of size(set)*dim values with the given dtype
+ * and layout.  Asynchronous on `stream` (a hipStream_t; NULL = default). */
+um_status um_permute_dat(um_ctx ctx, int32_t set, int32_t direction, const void *src, void *dst,
+                         int32_t dim, int32_t dtype, int32_t layout, void *stream);
+
+/* ----------------------------------------------------------------- plans */
+
+/* Build an execution plan for `kernel` over `iter_set` with `args` (see
+ * um_kernel for the pattern each kernel requires).  Host work (colourings,
+ * blocks, staged lists, local index maps) plus one upload, after which the
+ * call synchronises on its own upload.  The plan owns its device memory.
+ * Errors: UM_ERR_ARITY (argument pattern), UM_ERR_ARG (bad options),
+ * UM_ERR_COLOURS (HIER: block colours > max_block_colours; the paper's
+ * library could not run such meshes either, Section 3.1.5), UM_ERR_LDS (HIER:
+ * a block's staging exceeds lds_limit_bytes and no fallback is allowed). */
+um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t nargs,
+                        int32_t iter_set, const um_plan_opts *opts, um_plan *out);
+
+um_status um_plan_stats_get(um_plan plan, um_plan_stats *out);
+
+/* Copy plan contents to host memory for verification.  *n_out receives the
+ * number of int32 values of the field; if host_out is not NULL and capacity
+ * suffices they are copied, otherwise UM_ERR_ARG after setting *n_out. */
+um_status um_plan_export(um_plan plan, int32_t field, int32_t *host_out, int64_t capacity,
+                         int64_t *n_out);
+
+um_status um_plan_destroy(um_plan plan);
+
+/* Execute the loop once on `stream` (hipStream_t, NULL = default stream),
+ * incrementing the INC dats (they are not cleared).  Asynchronous; the
+ * dats bound to the plan's args must stay valid until the work completes.
+ * params: kernel constants (LF2D: {gm1, eps}).  Errors: UM_ERR_STATE on a
+ * host-only context or a dat without device memory, UM_ERR_HIP on launch
+ * failure. */
+um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void *stream);
+
+/* Timing of the plan's launches: when enabled, um_loop_exec records a HIP
+ * event pair around every kernel launch; um_plan_timing waits for them and
+ * returns the summed kernel time in ms and the number of launches timed
+ * since the last reset, then resets. */
+um_status um_plan_set_timing(um_plan plan, int32_t enable);
+um_status um_plan_timing(um_plan plan, double *ms_total, int64_t *n_launches);
+
+/* Verification entry point: evaluate the elemental flux of every element of
+ * the iteration set (current numbering) with floating-point contraction
+ * disabled, writing f[n_elements][4] (UM_F64, element-major) to the device
+ * buffer f_out.  Used to compare per-edge values bit for bit with a
+ * sequential evaluation of the same formula.  Asynchronous on `stream`. */
+um_status um_debug_fluxes(um_plan plan, const double *params, int32_t nparams, void *f_out,
+                          void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UMESH_H */

@@ -1,0 +1,636 @@
+// C ABI of libumesh: contexts, declarations, reordering, plans, execution.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.hpp"
+#include "launch.hpp"
+
+struct um_ctx_s : um::Ctx {};
+struct um_plan_s : um::Plan {};
+
+namespace um {
+
+namespace {
+thread_local std::string g_err;
+
+#define UM_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) fail(UM_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Makes the context's device current for the scope, restoring the previous.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (dev < 0) return;
+        UM_HIP(hipGetDevice(&prev));
+        if (prev != dev) UM_HIP(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) hipSetDevice(prev);
+    }
+};
+
+template <typename F>
+um_status guarded(F &&f) {
+    try {
+        f();
+        return UM_OK;
+    } catch (const Error &e) {
+        g_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return UM_ERR_NOMEM;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return UM_ERR_ARG;
+    }
+}
+
+Ctx &need(um_ctx c) {
+    if (!c) fail(UM_ERR_ARG, "null context");
+    return *c;
+}
+Plan &need(um_plan p) {
+    if (!p) fail(UM_ERR_ARG, "null plan");
+    return *p;
+}
+
+template <typename T>
+T *upload(const std::vector<T> &v, int64_t &bytes) {
+    if (v.empty()) return nullptr;
+    T *d = nullptr;
+    if (hipMalloc(&d, sizeof(T) * v.size()) != hipSuccess)
+        fail(UM_ERR_NOMEM, "device allocation of %zu bytes failed", sizeof(T) * v.size());
+    bytes += int64_t(sizeof(T) * v.size());
+    UM_HIP(hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return d;
+}
+
+void free_device_plan(Plan &p) {
+    void *bufs[5] = {p.dp.emap, p.dp.binfo, p.dp.stg_c, p.dp.stg_n, p.dp.loc};
+    for (void *b : bufs)
+        if (b) hipFree(b);
+    p.dp = DevicePlan{};
+    for (void *e : p.events) hipEventDestroy(static_cast<hipEvent_t>(e));
+    p.events.clear();
+}
+
+// LF2D argument pattern (umesh.h, UM_K_EDGE_FLUX_LF2D).
+EdgeArgs check_lf2d_args(const Ctx &ctx, const um_arg *args, int32_t nargs, int32_t iter) {
+    if (nargs != 8 || !args) fail(UM_ERR_ARITY, "edge flux kernel takes 8 args, got %d", nargs);
+    struct Want { int dim, slot, acc; const char *name; };
+    const Want want[8] = {{2, 0, UM_READ, "x"},   {2, 1, UM_READ, "x"},  {4, 0, UM_READ, "q"},
+                          {4, 1, UM_READ, "q"},   {1, 0, UM_READ, "adt"}, {1, 1, UM_READ, "adt"},
+                          {4, 0, UM_INC, "res"},  {4, 1, UM_INC, "res"}};
+    for (int i = 0; i < 8; ++i) {
+        const um_arg &a = args[i];
+        if (a.dat < 0 || a.dat >= int32_t(ctx.dats.size()))
+            fail(UM_ERR_RANGE, "arg %d: dat %d does not exist", i, a.dat);
+        if (a.map < 0 || a.map >= int32_t(ctx.maps.size()))
+            fail(UM_ERR_ARITY, "arg %d: must be accessed through a map", i);
+        const Dat &d = ctx.dats[a.dat];
+        const Map &m = ctx.maps[a.map];
+        if (m.from != iter) fail(UM_ERR_ARITY, "arg %d: map does not start at the iteration set", i);
+        if (m.arity != 2) fail(UM_ERR_ARITY, "arg %d: map arity %d, need 2", i, m.arity);
+        if (m.to != d.set) fail(UM_ERR_ARITY, "arg %d: dat %s is not on the map's to-set", i, want[i].name);
+        if (d.dim != want[i].dim)
+            fail(UM_ERR_ARITY, "arg %d: %s needs dim %d, dat has %d", i, want[i].name, want[i].dim, d.dim);
+        if (a.idx != want[i].slot) fail(UM_ERR_ARITY, "arg %d: needs map slot %d", i, want[i].slot);
+        if (a.acc != want[i].acc) fail(UM_ERR_ARITY, "arg %d: wrong access mode for %s", i, want[i].name);
+    }
+    EdgeArgs ea;
+    ea.map_n = args[0].map;
+    ea.map_c = args[2].map;
+    ea.dat_x = args[0].dat;
+    ea.dat_q = args[2].dat;
+    ea.dat_adt = args[4].dat;
+    ea.dat_res = args[6].dat;
+    for (int i = 0; i < 8; i += 2)
+        if (args[i + 1].dat != args[i].dat || args[i + 1].map != args[i].map)
+            fail(UM_ERR_ARITY, "args %d and %d must use the same dat and map", i, i + 1);
+    if (args[4].map != ea.map_c || args[6].map != ea.map_c)
+        fail(UM_ERR_ARITY, "q, adt and res must use the same edge->cell map");
+    if (ea.map_n == ea.map_c) fail(UM_ERR_ARITY, "x must use the edge->node map");
+    const int ids[4] = {ea.dat_x, ea.dat_q, ea.dat_adt, ea.dat_res};
+    ea.layout = ctx.dats[ea.dat_q].layout;
+    for (int id : ids) {
+        const Dat &d = ctx.dats[id];
+        if (d.dtype != UM_F64)
+            fail(UM_ERR_UNSUPPORTED, "edge flux kernel: only UM_F64 dats are provided");
+        if (d.layout != ea.layout)
+            fail(UM_ERR_UNSUPPORTED, "edge flux kernel: x, q, adt and res must share one layout");
+    }
+    ea.dtype = UM_F64;
+    return ea;
+}
+
+LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *stream) {
+    const Ctx &ctx = *p.ctx;
+    if (ctx.device < 0) fail(UM_ERR_STATE, "host-only context cannot execute");
+    if (nparams != 2 || !params) fail(UM_ERR_ARG, "edge flux kernel takes params {gm1, eps}");
+    LaunchArgs la{};
+    la.stream = static_cast<hipStream_t>(stream);
+    la.layout = p.ea.layout;
+    la.staging = p.hp.staging;
+    la.tcmode = p.hp.tcmode;
+    la.block_size = p.hp.block_size;
+    la.binfo = p.dp.binfo;
+    la.stg_c = p.dp.stg_c;
+    la.stg_n = p.dp.stg_n;
+    la.loc = p.dp.loc;
+    la.emap = p.dp.emap;
+    const Dat &x = ctx.dats[p.ea.dat_x], &q = ctx.dats[p.ea.dat_q];
+    const Dat &adt = ctx.dats[p.ea.dat_adt], &res = ctx.dats[p.ea.dat_res];
+    const int64_t E = ctx.sets[p.iter_set].size;
+    if (E > 0 && (!x.ptr || !q.ptr || !adt.ptr || !res.ptr))
+        fail(UM_ERR_STATE, "a dat of the loop has no device memory");
+    la.x = static_cast<const double *>(x.ptr);
+    la.q = static_cast<const double *>(q.ptr);
+    la.adt = static_cast<const double *>(adt.ptr);
+    la.res = static_cast<double *>(res.ptr);
+    la.N = ctx.sets[x.set].size;
+    la.C = ctx.sets[q.set].size;
+    la.gm1 = params[0];
+    la.eps = params[1];
+    return la;
+}
+
+}  // namespace
+
+void fail(um_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Error{code, buf};
+}
+
+}  // namespace um
+
+using namespace um;
+
+extern "C" {
+
+int32_t um_abi_version(void) { return UMESH_ABI_VERSION; }
+
+const char *um_last_error(void) { return g_err.c_str(); }
+
+um_status um_create(int32_t device, um_ctx *out) {
+    return guarded([&] {
+        if (!out) fail(UM_ERR_ARG, "null output handle");
+        *out = nullptr;
+        if (device < -1) fail(UM_ERR_ARG, "device %d", device);
+        auto *c = new um_ctx_s();
+        c->device = device;
+        if (device >= 0) {
+            int n = 0;
+            if (hipGetDeviceCount(&n) != hipSuccess || device >= n) {
+                delete c;
+                fail(UM_ERR_HIP, "HIP device %d not available (%d devices)", device, n);
+            }
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+                delete c;
+                fail(UM_ERR_HIP, "cannot query HIP device %d", device);
+            }
+            c->lds_limit = int32_t(prop.sharedMemPerBlock);
+        }
+        *out = c;
+    });
+}
+
+um_status um_destroy(um_ctx ctx) {
+    return guarded([&] {
+        if (!ctx) return;
+        DeviceGuard g(ctx->device);
+        if (ctx->device >= 0) hipDeviceSynchronize();
+        for (Plan *p : ctx->plans) {
+            free_device_plan(*p);
+            delete static_cast<um_plan_s *>(p);
+        }
+        for (int32_t *d : ctx->d_new2orig)
+            if (d) hipFree(d);
+        for (int32_t *d : ctx->d_orig2new)
+            if (d) hipFree(d);
+        delete ctx;
+    });
+}
+
+um_status um_decl_set(um_ctx ctx, int64_t size, const char *name, int32_t *set_id) {
+    return guarded([&] {
+        Ctx &c = need(ctx);
+        if (!set_id) fail(UM_ERR_ARG, "null set_id");
+        if (size < 0 || size > INT32_MAX) fail(UM_ERR_ARG, "set size %lld", (long long)size);
+        Set s;
+        s.size = size;
+        s.name = name ? name : "";
+        s.new2orig.resize(size);
+        for (int64_t k = 0; k < size; ++k) s.new2orig[k] = int32_t(k);
+        c.sets.push_back(std::move(s));
+        c.d_new2orig.push_back(nullptr);
+        c.d_orig2new.push_back(nullptr);
+        *set_id = int32_t(c.sets.size()) - 1;
+    });
+}
+
+um_status um_decl_map(um_ctx ctx, int32_t from_set, int32_t to_set, int32_t arity,
+                      const int32_t *host_table, int32_t *map_id) {
+    return guarded([&] {
+        Ctx &c = need(ctx);
+        if (!map_id) fail(UM_ERR_ARG, "null map_id");
+        const int32_t ns = int32_t(c.sets.size());
+        if (from_set < 0 || from_set >= ns || to_set < 0 || to_set >= ns)
+            fail(UM_ERR_ARG, "bad set id (%d, %d)", from_set, to_set);
+        if (arity < 1 || arity > 16) fail(UM_ERR_ARG, "arity %d outside 1..16", arity);
+        const int64_t n = c.sets[from_set].size * arity, to_n = c.sets[to_set].size;
+        if (n > 0 && !host_table) fail(UM_ERR_ARG, "null map table");
+        for (int64_t i = 0; i < n; ++i)
+            if (host_table[i] < 0 || host_table[i] >= to_n)
+                fail(UM_ERR_RANGE, "map entry %lld (element %lld, slot %lld) = %d outside 0..%lld",
+                     (long long)i, (long long)(i / arity), (long long)(i % arity), host_table[i],
+                     (long long)to_n - 1);
+        Map m;
+        m.from = from_set;
+        m.to = to_set;
+        m.arity = arity;
+        m.table.assign(host_table, host_table + n);
+        c.maps.push_back(std::move(m));
+        *map_id = int32_t(c.maps.size()) - 1;
+    });
+}
+
+um_status um_decl_dat(um_ctx ctx, int32_t set, int32_t dim, int32_t dtype, int32_t layout,
+                      void *device_ptr, int32_t *dat_id) {
+    return guarded([&] {
+        Ctx &c = need(ctx);
+        if (!dat_id) fail(UM_ERR_ARG, "null dat_id");
+        if (set < 0 || set >= int32_t(c.sets.size())) fail(UM_ERR_ARG, "bad set id %d", set);
+        if (dim < 1 || dim > 16) fail(UM_ERR_ARG, "dim %d outside 1..16", dim);
+        if (dtype != UM_F64 && dtype != UM_F32) fail(UM_ERR_ARG, "bad dtype %d", dtype);
+        if (layout != UM_AOS && layout != UM_SOA) fail(UM_ERR_ARG, "bad layout %d", layout);
+        Dat d;
+        d.set = set;
+        d.dim = dim;
+        d.dtype = dtype;
+        d.layout = layout;
+        d.ptr = device_ptr;
+        c.dats.push_back(d);
+        *dat_id = int32_t(c.dats.size()) - 1;
+    });
+}
+
+um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr) {
+    return guarded([&] {
+        Ctx &c = need(ctx);
+        if (dat < 0 || dat >= int32_t(c.dats.size())) fail(UM_ERR_ARG, "bad dat id %d", dat);
+        c.dats[dat].ptr = device_ptr;
+    });
+}
+
+um_status um_reorder_mesh(um_ctx ctx, const um_reorder_opts *opts) {
+    return guarded([&] {
+        Ctx &c = need(ctx);
+        if (!opts) fail(UM_ERR_ARG, "null options");
+        if (!c.dats.empty() || !c.plans.empty())
+            fail(UM_ERR_STATE, "reorder before declaring dats or building plans");
+        reorder_mesh(c, *opts);
+        // device copies of permutations are stale now
+        DeviceGuard g(c.device);
+        for (size_t s = 0; s < c.sets.size(); ++s) {
+            if (c.d_new2orig[s]) hipFree(c.d_new2orig[s]);
+            if (c.d_orig2new[s]) hipFree(c.d_orig2new[s]);
+            c.d_new2orig[s] = c.d_orig2new[s] = nullptr;
+        }
+    });
+}
+
+um_status um_get_perm(um_ctx ctx, int32_t set, int32_t *out) {
+    return guarded([&] {
+        Ctx &c = need(ctx);
+        if (set < 0 || set >= int32_t(c.sets.size()) || !out) fail(UM_ERR_ARG, "bad set or output");
+        std::copy(c.sets[set].new2orig.begin(), c.sets[set].new2orig.end(), out);
+    });
+}
+
+um_status um_get_map(um_ctx ctx, int32_t map, int32_t *out) {
+    return guarded([&] {
+        Ctx &c = need(ctx);
+        if (map < 0 || map >= int32_t(c.maps.size()) || !out) fail(UM_ERR_ARG, "bad map or output");
+        std::copy(c.maps[map].table.begin(), c.maps[map].table.end(), out);
+    });
+}
+
+um_status um_get_blocks(um_ctx ctx, int32_t set, int32_t *block_size, int32_t *n_blocks,
+                        int32_t *host_off, int64_t capacity) {
+    return guarded([&] {
+        Ctx &c = need(ctx);
+        if (set < 0 || set >= int32_t(c.sets.size()) || !n_blocks || !block_size)
+            fail(UM_ERR_ARG, "bad set or output");
+        const Set &s = c.sets[set];
+        *block_size = s.part_block_size;
+        *n_blocks = s.part_off.empty() ? 0 : int32_t(s.part_off.size()) - 1;
+        if (host_off) {
+            if (capacity < int64_t(s.part_off.size())) fail(UM_ERR_ARG, "capacity too small");
+            std::copy(s.part_off.begin(), s.part_off.end(), host_off);
+        }
+    });
+}
+
+um_status um_permute_dat(um_ctx ctx, int32_t set, int32_t direction, const void *src, void *dst,
+                         int32_t dim, int32_t dtype, int32_t layout, void *stream) {
+    return guarded([&] {
+        Ctx &c = need(ctx);
+        if (c.device < 0) fail(UM_ERR_STATE, "host-only context has no device");
+        if (set < 0 || set >= int32_t(c.sets.size())) fail(UM_ERR_ARG, "bad set id %d", set);
+        if (direction != 0 && direction != 1) fail(UM_ERR_ARG, "direction must be 0 or 1");
+        if (dim < 1 || dim > 16 || (dtype != UM_F64 && dtype != UM_F32) ||
+            (layout != UM_AOS && layout != UM_SOA))
+            fail(UM_ERR_ARG, "bad dim/dtype/layout");
+        const Set &s = c.sets[set];
+        if (s.size == 0) return;
+        if (!src || !dst || src == dst) fail(UM_ERR_ARG, "src and dst must be distinct buffers");
+        DeviceGuard g(c.device);
+        int32_t *&d_n2o = c.d_new2orig[set];
+        int32_t *&d_o2n = c.d_orig2new[set];
+        if (!d_n2o) {
+            std::vector<int32_t> inv(s.size);
+            for (int64_t k = 0; k < s.size; ++k) inv[s.new2orig[k]] = int32_t(k);
+            int64_t bytes = 0;
+            d_n2o = upload(s.new2orig, bytes);
+            d_o2n = upload(inv, bytes);
+        }
+        // direction 0: dst[k] = src[new2orig[k]]; 1: dst[j] = src[orig2new[j]]
+        UM_HIP(permute_gather(src, dst, direction == 0 ? d_n2o : d_o2n, s.size, dim, dtype, layout,
+                              static_cast<hipStream_t>(stream)));
+    });
+}
+
+um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t nargs,
+                        int32_t iter_set, const um_plan_opts *opts, um_plan *out) {
+    return guarded([&] {
+        Ctx &c = need(ctx);
+        if (!out || !opts) fail(UM_ERR_ARG, "null options or output");
+        *out = nullptr;
+        if (kernel != UM_K_EDGE_FLUX_LF2D) fail(UM_ERR_UNSUPPORTED, "unknown kernel %d", kernel);
+        if (iter_set < 0 || iter_set >= int32_t(c.sets.size())) fail(UM_ERR_ARG, "bad iteration set");
+        const um_plan_opts &o = *opts;
+        if (o.strategy < UM_STRAT_ATOMIC || o.strategy > UM_STRAT_HIER)
+            fail(UM_ERR_ARG, "bad strategy %d", o.strategy);
+        if (o.block_size < 64 || o.block_size > 1024)
+            fail(UM_ERR_ARG, "block_size %d outside 64..1024", o.block_size);
+        if (o.staging != UM_STAGE_ALL && o.staging != UM_STAGE_INC_ONLY)
+            fail(UM_ERR_ARG, "bad staging %d", o.staging);
+        if (o.tcmode != UM_TC_BARRIER && o.tcmode != UM_TC_LDS_ATOMIC)
+            fail(UM_ERR_ARG, "bad tcmode %d", o.tcmode);
+        if (o.max_block_colours < 0 || o.lds_limit_bytes < 0) fail(UM_ERR_ARG, "negative limit");
+        const auto t0 = std::chrono::steady_clock::now();
+        EdgeArgs ea = check_lf2d_args(c, args, nargs, iter_set);
+        auto *p = new um_plan_s();
+        p->ctx = &c;
+        p->kernel = kernel;
+        p->iter_set = iter_set;
+        p->ea = ea;
+        try {
+            build_host_plan(c, ea, iter_set, o, p->hp);
+            if (c.device >= 0) {
+                DeviceGuard g(c.device);
+                int64_t bytes = 0;
+                p->dp.emap = upload(p->hp.emap, bytes);
+                p->dp.binfo = upload(p->hp.binfo, bytes);
+                p->dp.stg_c = upload(p->hp.stg_c, bytes);
+                p->dp.stg_n = upload(p->hp.stg_n, bytes);
+                p->dp.loc = upload(p->hp.loc, bytes);
+                p->dp.bytes = bytes;
+                UM_HIP(hipDeviceSynchronize());
+            }
+        } catch (...) {
+            DeviceGuard g(c.device);
+            free_device_plan(*p);
+            delete p;
+            throw;
+        }
+        p->build_seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        c.plans.push_back(p);
+        *out = p;
+    });
+}
+
+um_status um_plan_stats_get(um_plan plan, um_plan_stats *out) {
+    return guarded([&] {
+        Plan &p = need(plan);
+        if (!out) fail(UM_ERR_ARG, "null output");
+        std::memset(out, 0, sizeof *out);
+        const HostPlan &hp = p.hp;
+        out->strategy = hp.strategy;
+        out->staging = hp.staging;
+        out->block_size = hp.block_size;
+        out->n_elements = hp.n_elem;
+        out->plan_device_bytes = p.dp.bytes;
+        out->build_seconds = p.build_seconds;
+        if (hp.strategy == UM_STRAT_HIER) {
+            out->n_blocks = int32_t(hp.blk_colour.size());
+            out->n_block_colours = int32_t(hp.bcol_off.size()) - 1;
+            out->max_thread_colours = hp.max_tcol;
+            out->avg_thread_colours = hp.avg_tcol;
+            out->reuse_factor = hp.reuse;
+            out->staged_points = hp.staged_total;
+            out->lds_bytes_max = hp.lds_max;
+            out->n_launches = 0;
+            for (int32_t c = 0; c + 1 < int32_t(hp.bcol_off.size()); ++c)
+                out->n_launches += hp.bcol_off[c + 1] > hp.bcol_off[c];
+        } else if (hp.strategy == UM_STRAT_GLOBAL_COLOUR) {
+            out->n_global_colours = int32_t(hp.colour_off.size()) - 1;
+            out->n_launches = out->n_global_colours;
+        } else {
+            out->n_launches = hp.n_elem > 0;
+        }
+    });
+}
+
+um_status um_plan_export(um_plan plan, int32_t field, int32_t *host_out, int64_t capacity,
+                         int64_t *n_out) {
+    return guarded([&] {
+        Plan &p = need(plan);
+        if (!n_out) fail(UM_ERR_ARG, "null n_out");
+        const HostPlan &hp = p.hp;
+        const Ctx &c = *p.ctx;
+        std::vector<int32_t> tmp;
+        const std::vector<int32_t> *v = &tmp;
+        const bool hier = hp.strategy == UM_STRAT_HIER;
+        auto staged = [&](bool cells, bool offsets) {
+            // block id order
+            const int32_t nb = int32_t(hp.blk_order.size());
+            std::vector<int32_t> pos_of(nb);
+            for (int32_t pos = 0; pos < nb; ++pos) pos_of[hp.blk_order[pos]] = pos;
+            tmp.clear();
+            if (offsets) tmp.push_back(0);
+            for (int32_t b = 0; b < nb; ++b) {
+                const int32_t pos = pos_of[b];
+                const int32_t s0 = cells ? hp.binfo[pos].cell_off : hp.binfo[pos].node_off;
+                const int32_t s1 = cells ? hp.binfo[pos + 1].cell_off : hp.binfo[pos + 1].node_off;
+                if (offsets)
+                    tmp.push_back(tmp.back() + (s1 - s0));
+                else
+                    for (int32_t i = s0; i < s1; ++i)
+                        tmp.push_back(cells ? hp.stg_c[i] : hp.stg_n[i]);
+            }
+        };
+        switch (field) {
+        case UM_EXP_BLOCK_OFFSETS: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); v = &hp.blk_off; break;
+        case UM_EXP_BLOCK_COLOURS: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); v = &hp.blk_colour; break;
+        case UM_EXP_THREAD_COLOURS: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); v = &hp.tcol; break;
+        case UM_EXP_BLOCK_ORDER: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); v = &hp.blk_order; break;
+        case UM_EXP_SLOT_ELEMENTS:
+            if (hp.strategy == UM_STRAT_ATOMIC) fail(UM_ERR_STATE, "atomic plans run elements in order");
+            v = &hp.slot_elem;
+            break;
+        case UM_EXP_GLOBAL_COLOURS:
+            if (hp.strategy != UM_STRAT_GLOBAL_COLOUR) fail(UM_ERR_STATE, "not a GLOBAL_COLOUR plan");
+            v = &hp.elem_colour;
+            break;
+        case UM_EXP_STAGED_OFFSETS_A: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); staged(false, true); break;
+        case UM_EXP_STAGED_POINTS_A: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); staged(false, false); break;
+        case UM_EXP_STAGED_OFFSETS_B: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); staged(true, true); break;
+        case UM_EXP_STAGED_POINTS_B: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); staged(true, false); break;
+        case UM_EXP_LOCAL_INDEX:
+            if (!hier) fail(UM_ERR_STATE, "not a HIER plan");
+            tmp.resize(4 * hp.n_elem);
+            for (int64_t s = 0; s < hp.n_elem; ++s) {
+                const uint32_t w0 = hp.loc[2 * s], w1 = hp.loc[2 * s + 1];
+                tmp[4 * s] = int32_t(w0 & 0x7FFu);
+                tmp[4 * s + 1] = int32_t((w0 >> 16) & 0x7FFu);
+                tmp[4 * s + 2] = int32_t(w1 & 0xFFFFu);
+                tmp[4 * s + 3] = int32_t(w1 >> 16);
+            }
+            break;
+        default: fail(UM_ERR_ARG, "unknown export field %d", field);
+        }
+        (void)c;
+        *n_out = int64_t(v->size());
+        if (host_out) {
+            if (capacity < *n_out) fail(UM_ERR_ARG, "capacity %lld < %lld", (long long)capacity, (long long)*n_out);
+            std::copy(v->begin(), v->end(), host_out);
+        }
+    });
+}
+
+um_status um_plan_destroy(um_plan plan) {
+    return guarded([&] {
+        if (!plan) return;
+        Ctx &c = *plan->ctx;
+        DeviceGuard g(c.device);
+        if (c.device >= 0) hipDeviceSynchronize();
+        free_device_plan(*plan);
+        c.plans.erase(std::remove(c.plans.begin(), c.plans.end(), static_cast<Plan *>(plan)),
+                      c.plans.end());
+        delete plan;
+    });
+}
+
+um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void *stream) {
+    return guarded([&] {
+        Plan &p = need(plan);
+        LaunchArgs la = launch_args(p, params, nparams, stream);
+        const HostPlan &hp = p.hp;
+        if (hp.n_elem == 0) return;
+        DeviceGuard g(p.ctx->device);
+        auto one = [&](int which, int32_t b, int32_t e, int64_t lds) {
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (p.timing) {
+                const size_t need_ev = 2 * size_t(p.pending_pairs + 1);
+                while (p.events.size() < need_ev) {
+                    hipEvent_t h;
+                    UM_HIP(hipEventCreate(&h));
+                    p.events.push_back(h);
+                }
+                e0 = static_cast<hipEvent_t>(p.events[2 * p.pending_pairs]);
+                e1 = static_cast<hipEvent_t>(p.events[2 * p.pending_pairs + 1]);
+                UM_HIP(hipEventRecord(e0, la.stream));
+            }
+            UM_HIP(lf2d_launch_one(la, which, b, e, lds));
+            if (p.timing) {
+                UM_HIP(hipEventRecord(e1, la.stream));
+                ++p.pending_pairs;
+            }
+        };
+        if (hp.strategy == UM_STRAT_HIER) {
+            for (int32_t c = 0; c + 1 < int32_t(hp.bcol_off.size()); ++c)
+                if (hp.bcol_off[c + 1] > hp.bcol_off[c])
+                    one(LAUNCH_HIER, hp.bcol_off[c], hp.bcol_off[c + 1], hp.lds_per_colour[c]);
+        } else if (hp.strategy == UM_STRAT_GLOBAL_COLOUR) {
+            for (int32_t c = 0; c + 1 < int32_t(hp.colour_off.size()); ++c)
+                if (hp.colour_off[c + 1] > hp.colour_off[c])
+                    one(LAUNCH_GCOL, hp.colour_off[c], hp.colour_off[c + 1], 0);
+        } else {
+            one(LAUNCH_ATOMIC, 0, int32_t(hp.n_elem), 0);
+        }
+    });
+}
+
+um_status um_plan_set_timing(um_plan plan, int32_t enable) {
+    return guarded([&] { need(plan).timing = enable != 0; });
+}
+
+um_status um_plan_timing(um_plan plan, double *ms_total, int64_t *n_launches) {
+    return guarded([&] {
+        Plan &p = need(plan);
+        if (!ms_total || !n_launches) fail(UM_ERR_ARG, "null output");
+        DeviceGuard g(p.ctx->device);
+        double ms = 0.0;
+        for (int64_t i = 0; i < p.pending_pairs; ++i) {
+            hipEvent_t e0 = static_cast<hipEvent_t>(p.events[2 * i]);
+            hipEvent_t e1 = static_cast<hipEvent_t>(p.events[2 * i + 1]);
+            UM_HIP(hipEventSynchronize(e1));
+            float t = 0.f;
+            UM_HIP(hipEventElapsedTime(&t, e0, e1));
+            ms += t;
+        }
+        *ms_total = ms;
+        *n_launches = p.pending_pairs;
+        p.pending_pairs = 0;
+    });
+}
+
+um_status um_debug_fluxes(um_plan plan, const double *params, int32_t nparams, void *f_out,
+                          void *stream) {
+    return guarded([&] {
+        Plan &p = need(plan);
+        LaunchArgs la = launch_args(p, params, nparams, stream);
+        const Ctx &c = *p.ctx;
+        const int64_t E = c.sets[p.iter_set].size;
+        if (E == 0) return;
+        if (!f_out) fail(UM_ERR_ARG, "null output buffer");
+        DeviceGuard g(c.device);
+        std::vector<int32_t> em(4 * E);
+        const Map &mc = c.maps[p.ea.map_c], &mn = c.maps[p.ea.map_n];
+        for (int64_t e = 0; e < E; ++e) {
+            em[4 * e] = mc.table[2 * e];
+            em[4 * e + 1] = mc.table[2 * e + 1];
+            em[4 * e + 2] = mn.table[2 * e];
+            em[4 * e + 3] = mn.table[2 * e + 1];
+        }
+        int64_t bytes = 0;
+        int32_t *d_em = upload(em, bytes);
+        la.emap = d_em;
+        la.out = static_cast<double *>(f_out);
+        la.block_size = 256;
+        hipError_t err = lf2d_launch_one(la, LAUNCH_DEBUG, 0, int32_t(E), 0);
+        hipError_t err2 = hipStreamSynchronize(la.stream);
+        hipFree(d_em);
+        if (err != hipSuccess || err2 != hipSuccess)
+            fail(UM_ERR_HIP, "debug flux launch: %s", hipGetErrorString(err != hipSuccess ? err : err2));
+    });
+}
+
+}  // extern "C"

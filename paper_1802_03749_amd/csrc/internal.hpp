@@ -1,0 +1,145 @@
+// Library-internal declarations of libumesh (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "umesh.h"
+
+namespace um {
+
+// Thrown inside the library, converted to a um_status at the ABI boundary.
+struct Error {
+    um_status code;
+    std::string msg;
+};
+[[noreturn]] void fail(um_status code, const char *fmt, ...);
+
+struct Set {
+    int64_t size = 0;
+    std::string name;
+    std::vector<int32_t> new2orig;   // cumulative renumbering
+    int32_t part_block_size = 0;     // blocks from the last PARTITION reorder
+    std::vector<int32_t> part_off;   // [n_blocks + 1]
+};
+
+struct Map {
+    int32_t from = 0, to = 0, arity = 0;
+    std::vector<int32_t> table;      // [size(from)][arity]
+};
+
+struct Dat {
+    int32_t set = 0, dim = 0, dtype = UM_F64, layout = UM_AOS;
+    void *ptr = nullptr;
+};
+
+struct Plan;
+
+struct Ctx {
+    int32_t device = -1;             // -1: host-only
+    int32_t lds_limit = 65536;       // per-workgroup LDS limit in bytes
+    std::vector<Set> sets;
+    std::vector<Map> maps;
+    std::vector<Dat> dats;
+    std::vector<Plan *> plans;
+    // device copies of the cumulative permutations, uploaded on demand
+    std::vector<int32_t *> d_new2orig;
+    std::vector<int32_t *> d_orig2new;
+};
+
+// ------------------------------------------------------------ reordering
+// All return new->old permutations (new id k holds old id perm[k]).
+
+// Cuthill-McKee numbering of the to-set of `m` over the graph in which the
+// points of each element form a clique; reverse = RCM.
+std::vector<int32_t> cuthill_mckee(const Map &m, int64_t n_points, bool reverse);
+// Elements sorted by their sorted point ids (lexicographic), ties by old id.
+std::vector<int32_t> lexicographic_elements(const Map &m);
+// Points numbered in order of first appearance over the elements (in table
+// order) and slots; untouched points follow in ascending id.
+std::vector<int32_t> first_touch(const Map &m, int64_t n_points);
+// Partition the from-set of `drv` into blocks of <= block_size elements;
+// returns the element order (block by block) and fills block offsets.
+std::vector<int32_t> partition_elements(const Ctx &ctx, int32_t drv, int32_t block_size,
+                                        int32_t coord_map, int32_t coord_dim,
+                                        const double *coords, std::vector<int32_t> &block_off);
+// Points of to-set `set` sorted by (number of accessing blocks, list of
+// accessing blocks), stable; elements of `from` are in block order.
+std::vector<int32_t> signature_order(const Ctx &ctx, int32_t from, int32_t set,
+                                     const std::vector<int32_t> &block_of_elem);
+// Renumber `set` by new->old `perm`: rewrites every map from or into it.
+void apply_set_perm(Ctx &ctx, int32_t set, const std::vector<int32_t> &perm);
+
+void reorder_mesh(Ctx &ctx, const um_reorder_opts &o);
+
+// --------------------------------------------------------------- planning
+// Elements of the LF2D edge loop in packed form: L, R cells and a, b nodes.
+struct EdgeArgs {
+    int32_t map_n = -1, map_c = -1;              // edge->node, edge->cell
+    int32_t dat_x = -1, dat_q = -1, dat_adt = -1, dat_res = -1;
+    int32_t dtype = UM_F64, layout = UM_AOS;
+};
+
+// Per-block layout of a hierarchical plan, in launch order.
+struct BlockInfo {
+    int32_t slot_off;   // first slot of the block
+    int32_t cell_off;   // first staged cell (into stg_c)
+    int32_t node_off;   // first staged node (into stg_n)
+    int32_t ncol;       // thread colours used by the block
+};
+
+struct HostPlan {
+    int32_t strategy = 0, staging = 0, tcmode = 0, block_size = 0;
+    int64_t n_elem = 0;
+    // GLOBAL_COLOUR / ATOMIC: packed (L, R, a, b) per slot, slot order
+    std::vector<int32_t> emap;                 // [n_slots][4]
+    std::vector<int32_t> colour_off;           // GLOBAL: [ncol + 1] slot ranges
+    std::vector<int32_t> elem_colour;          // GLOBAL: colour per element
+    // HIER
+    std::vector<int32_t> blk_off;              // block id order: element ranges
+    std::vector<int32_t> blk_colour;           // block id order
+    std::vector<int32_t> blk_order;            // launch position -> block id
+    std::vector<int32_t> bcol_off;             // [nbcol + 1] launch position ranges
+    std::vector<BlockInfo> binfo;              // [nb + 1] launch order (+ sentinel)
+    std::vector<int32_t> stg_c, stg_n;         // launch order
+    std::vector<uint32_t> loc;                 // [n_slots][2]: (lL|lR<<16 | col<<11), (nA|nB<<16)
+    std::vector<int32_t> slot_elem;            // slot -> element
+    std::vector<int32_t> tcol;                 // element -> thread colour
+    std::vector<int64_t> lds_per_colour;       // max LDS bytes per block colour
+    int32_t max_tcol = 0;
+    double avg_tcol = 0.0, reuse = 0.0;
+    int64_t lds_max = 0, staged_total = 0;
+};
+
+void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
+                     const um_plan_opts &o, HostPlan &hp);
+
+// LDS bytes a block needs for the given counts.
+int64_t lf2d_lds_bytes(int32_t staging, int32_t dtype, int64_t n_cells, int64_t n_nodes);
+
+// ----------------------------------------------------------------- device
+struct DevicePlan {
+    int32_t *emap = nullptr;                   // int4 per slot
+    BlockInfo *binfo = nullptr;
+    int32_t *stg_c = nullptr, *stg_n = nullptr;
+    uint32_t *loc = nullptr;
+    int64_t bytes = 0;
+};
+
+struct Plan {
+    Ctx *ctx = nullptr;
+    int32_t kernel = 0;
+    int32_t iter_set = 0;
+    EdgeArgs ea;
+    HostPlan hp;
+    DevicePlan dp;
+    double build_seconds = 0.0;
+    bool timing = false;
+    std::vector<void *> events;                // hipEvent_t pairs
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+    int64_t pending_pairs = 0;
+};
+
+}  // namespace um

@@ -1,0 +1,368 @@
+// gfx950 kernels of the 2D edge-flux indirect-increment loop.
+//
+//  hier_kernel   two-layer colouring (paper Section 2.2, Algorithm 1): one
+//                workgroup per block, one lane per edge.  The block's staged
+//                cells and nodes are gathered into LDS (structure-of-arrays
+//                inside LDS), the residuals of the staged cells are preloaded
+//                as the increment accumulators, every lane computes its
+//                edge's flux into registers, increments are applied to LDS
+//                one thread colour at a time with a workgroup barrier after
+//                each colour, and the accumulators are stored back once.
+//                Blocks of one block colour write disjoint cells, so a launch
+//                per block colour needs no atomics.
+//  gcol_kernel   global colouring baseline (Section 2.1): one launch per
+//                colour, gather through the int32 maps, plain read-modify-
+//                write of res.
+//  atomic_kernel atomics baseline (Section 2.1): one launch, hardware FP64
+//                atomic adds on res.
+//  debug_kernel  per-edge fluxes with floating-point contraction disabled.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "launch.hpp"
+
+namespace um {
+namespace {
+
+// Flux through an edge from cell L into cell R (formula in umesh.h).
+#define UM_LF2D_FLUX_BODY                                                      \
+    const double nx = xb1 - xa1;                                               \
+    const double ny = xa0 - xb0;                                               \
+    double FL[4], FR[4];                                                       \
+    {                                                                          \
+        const double ri = 1.0 / qL[0];                                         \
+        const double u = qL[1] * ri;                                           \
+        const double v = qL[2] * ri;                                           \
+        const double p = gm1 * (qL[3] - 0.5 * (qL[1] * u + qL[2] * v));       \
+        const double U = u * nx + v * ny;                                      \
+        FL[0] = qL[0] * U;                                                     \
+        FL[1] = qL[1] * U + p * nx;                                            \
+        FL[2] = qL[2] * U + p * ny;                                            \
+        FL[3] = (qL[3] + p) * U;                                               \
+    }                                                                          \
+    {                                                                          \
+        const double ri = 1.0 / qR[0];                                         \
+        const double u = qR[1] * ri;                                           \
+        const double v = qR[2] * ri;                                           \
+        const double p = gm1 * (qR[3] - 0.5 * (qR[1] * u + qR[2] * v));       \
+        const double U = u * nx + v * ny;                                      \
+        FR[0] = qR[0] * U;                                                     \
+        FR[1] = qR[1] * U + p * nx;                                            \
+        FR[2] = qR[2] * U + p * ny;                                            \
+        FR[3] = (qR[3] + p) * U;                                               \
+    }                                                                          \
+    const double mu = eps * 0.5 * (adtL + adtR);                               \
+    _Pragma("unroll") for (int k = 0; k < 4; ++k)                              \
+        f[k] = 0.5 * (FL[k] + FR[k]) + 0.5 * mu * (qL[k] - qR[k]);
+
+__device__ __forceinline__ void lf2d_flux(double xa0, double xa1, double xb0, double xb1,
+                                          const double qL[4], const double qR[4], double adtL,
+                                          double adtR, double gm1, double eps, double f[4]) {
+    UM_LF2D_FLUX_BODY
+}
+
+__device__ __forceinline__ void lf2d_flux_nocontract(double xa0, double xa1, double xb0,
+                                                     double xb1, const double qL[4],
+                                                     const double qR[4], double adtL,
+                                                     double adtR, double gm1, double eps,
+                                                     double f[4]) {
+#pragma clang fp contract(off)
+    UM_LF2D_FLUX_BODY
+}
+
+// Element g of a dim-4 / dim-2 / dim-1 FP64 dat in AoS ([n][dim]) or SoA
+// ([dim][n]) layout.
+template <int LAYOUT>
+__device__ __forceinline__ void load4(const double *__restrict__ a, int64_t n, int64_t g,
+                                      double v[4]) {
+    if constexpr (LAYOUT == UM_AOS) {
+        const double2 *p = reinterpret_cast<const double2 *>(a + 4 * g);
+        const double2 lo = p[0], hi = p[1];
+        v[0] = lo.x; v[1] = lo.y; v[2] = hi.x; v[3] = hi.y;
+    } else {
+        v[0] = a[g]; v[1] = a[n + g]; v[2] = a[2 * n + g]; v[3] = a[3 * n + g];
+    }
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void store4(double *__restrict__ a, int64_t n, int64_t g,
+                                       const double v[4]) {
+    if constexpr (LAYOUT == UM_AOS) {
+        double2 *p = reinterpret_cast<double2 *>(a + 4 * g);
+        p[0] = make_double2(v[0], v[1]);
+        p[1] = make_double2(v[2], v[3]);
+    } else {
+        a[g] = v[0]; a[n + g] = v[1]; a[2 * n + g] = v[2]; a[3 * n + g] = v[3];
+    }
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void load2(const double *__restrict__ a, int64_t n, int64_t g,
+                                      double &v0, double &v1) {
+    if constexpr (LAYOUT == UM_AOS) {
+        const double2 t = reinterpret_cast<const double2 *>(a)[g];
+        v0 = t.x; v1 = t.y;
+    } else {
+        v0 = a[g]; v1 = a[n + g];
+    }
+}
+
+struct Dats {
+    const double *__restrict__ x;
+    const double *__restrict__ q;
+    const double *__restrict__ adt;
+    double *__restrict__ res;
+    int64_t N, C;
+};
+
+template <int LAYOUT>
+__device__ __forceinline__ void edge_flux_global(const Dats &d, int L, int R, int a, int b,
+                                                 double gm1, double eps, double f[4]) {
+    double qL[4], qR[4], xa0, xa1, xb0, xb1;
+    load4<LAYOUT>(d.q, d.C, L, qL);
+    load4<LAYOUT>(d.q, d.C, R, qR);
+    load2<LAYOUT>(d.x, d.N, a, xa0, xa1);
+    load2<LAYOUT>(d.x, d.N, b, xb0, xb1);
+    const double adtL = d.adt[L], adtR = d.adt[R];
+    lf2d_flux(xa0, xa1, xb0, xb1, qL, qR, adtL, adtR, gm1, eps, f);
+}
+
+template <int LAYOUT, int STAGING, int TCMODE>
+__global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict__ binfo,
+                                                    const int32_t *__restrict__ stg_c,
+                                                    const int32_t *__restrict__ stg_n,
+                                                    const uint2 *__restrict__ loc, Dats d,
+                                                    double gm1, double eps, int32_t base) {
+    extern __shared__ double lds[];
+    const int32_t pos = base + int32_t(blockIdx.x);
+    const BlockInfo bi = binfo[pos], bn = binfo[pos + 1];
+    const int ne = bn.slot_off - bi.slot_off;
+    const int nc = bn.cell_off - bi.cell_off;
+    const int nn = bn.node_off - bi.node_off;
+    const int32_t *__restrict__ sc = stg_c + bi.cell_off;
+    const int32_t *__restrict__ sn = stg_n + bi.node_off;
+    double *s_inc = lds;            // [4][nc] increment accumulators
+    double *s_q = s_inc + 4 * nc;   // [4][nc]
+    double *s_adt = s_q + 4 * nc;   // [nc]
+    double *s_x = s_adt + nc;       // [2][nn]
+    const int tid = int(threadIdx.x), S = int(blockDim.x);
+
+    // gather: residuals (as accumulators) and, when staging all, q, adt, x
+    for (int t = tid; t < nc; t += S) {
+        const int64_t g = sc[t];
+        double r[4];
+        load4<LAYOUT>(d.res, d.C, g, r);
+        if constexpr (STAGING == UM_STAGE_ALL) {
+            double qv[4];
+            load4<LAYOUT>(d.q, d.C, g, qv);
+            const double a = d.adt[g];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_q[k * nc + t] = qv[k];
+            s_adt[t] = a;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_inc[k * nc + t] = r[k];
+    }
+    if constexpr (STAGING == UM_STAGE_ALL) {
+        for (int t = tid; t < nn; t += S) {
+            double x0, x1;
+            load2<LAYOUT>(d.x, d.N, sn[t], x0, x1);
+            s_x[t] = x0;
+            s_x[nn + t] = x1;
+        }
+    }
+    uint2 w = make_uint2(0, 0);
+    if (tid < ne) w = loc[bi.slot_off + tid];
+    __syncthreads();
+
+    const int lL = int(w.x & 0x7FFu), col = int((w.x >> 11) & 31u), lR = int((w.x >> 16) & 0x7FFu);
+    const int nA = int(w.y & 0xFFFFu), nB = int(w.y >> 16);
+    double f[4] = {0.0, 0.0, 0.0, 0.0};
+    if (tid < ne) {
+        if constexpr (STAGING == UM_STAGE_ALL) {
+            double qL[4], qR[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                qL[k] = s_q[k * nc + lL];
+                qR[k] = s_q[k * nc + lR];
+            }
+            lf2d_flux(s_x[nA], s_x[nn + nA], s_x[nB], s_x[nn + nB], qL, qR, s_adt[lL],
+                      s_adt[lR], gm1, eps, f);
+        } else {
+            edge_flux_global<LAYOUT>(d, sc[lL], sc[lR], sn[nA], sn[nB], gm1, eps, f);
+        }
+    }
+
+    if constexpr (TCMODE == UM_TC_BARRIER) {
+        // layer 2: one thread colour at a time; same-colour lanes never
+        // share a cell, so their LDS read-modify-writes do not race
+        const int ncol = bi.ncol;
+        for (int c = 0; c < ncol; ++c) {
+            if (tid < ne && col == c) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    s_inc[k * nc + lL] += f[k];
+                    s_inc[k * nc + lR] -= f[k];
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        if (tid < ne) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                atomicAdd(&s_inc[k * nc + lL], f[k]);
+                atomicAdd(&s_inc[k * nc + lR], -f[k]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // write back once per staged cell; no other block of this colour
+    // touches these cells
+    for (int t = tid; t < nc; t += S) {
+        double r[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = s_inc[k * nc + t];
+        store4<LAYOUT>(d.res, d.C, sc[t], r);
+    }
+}
+
+template <int LAYOUT>
+__global__ __launch_bounds__(1024) void gcol_kernel(const int4 *__restrict__ emap, int32_t begin,
+                                                   int32_t end, Dats d, double gm1, double eps) {
+    const int32_t s = begin + int32_t(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= end) return;
+    const int4 m = emap[s];  // L, R, a, b
+    double f[4];
+    edge_flux_global<LAYOUT>(d, m.x, m.y, m.z, m.w, gm1, eps, f);
+    double rL[4], rR[4];
+    load4<LAYOUT>(d.res, d.C, m.x, rL);
+    load4<LAYOUT>(d.res, d.C, m.y, rR);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        rL[k] += f[k];
+        rR[k] -= f[k];
+    }
+    store4<LAYOUT>(d.res, d.C, m.x, rL);
+    store4<LAYOUT>(d.res, d.C, m.y, rR);
+}
+
+template <int LAYOUT>
+__global__ __launch_bounds__(1024) void atomic_kernel(const int4 *__restrict__ emap, int32_t n,
+                                                     Dats d, double gm1, double eps) {
+    const int32_t s = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= n) return;
+    const int4 m = emap[s];
+    double f[4];
+    edge_flux_global<LAYOUT>(d, m.x, m.y, m.z, m.w, gm1, eps, f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t iL = LAYOUT == UM_AOS ? 4 * int64_t(m.x) + k : k * d.C + m.x;
+        const int64_t iR = LAYOUT == UM_AOS ? 4 * int64_t(m.y) + k : k * d.C + m.y;
+        unsafeAtomicAdd(&d.res[iL], f[k]);
+        unsafeAtomicAdd(&d.res[iR], -f[k]);
+    }
+}
+
+template <int LAYOUT>
+__global__ __launch_bounds__(1024) void debug_kernel(const int4 *__restrict__ emap, int32_t n,
+                                                    Dats d, double gm1, double eps,
+                                                    double *__restrict__ out) {
+    const int32_t s = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= n) return;
+    const int4 m = emap[s];
+    double qL[4], qR[4], xa0, xa1, xb0, xb1, f[4];
+    load4<LAYOUT>(d.q, d.C, m.x, qL);
+    load4<LAYOUT>(d.q, d.C, m.y, qR);
+    load2<LAYOUT>(d.x, d.N, m.z, xa0, xa1);
+    load2<LAYOUT>(d.x, d.N, m.w, xb0, xb1);
+    lf2d_flux_nocontract(xa0, xa1, xb0, xb1, qL, qR, d.adt[m.x], d.adt[m.y], gm1, eps, f);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[4 * int64_t(s) + k] = f[k];
+}
+
+template <int LAYOUT>
+hipError_t launch_hier(const LaunchArgs &la, int staging, int tcmode, int32_t nblocks,
+                       int32_t base, int64_t lds, Dats d) {
+    dim3 grid(nblocks), block(la.block_size);
+    const BlockInfo *bi = la.binfo;
+    const uint2 *loc = reinterpret_cast<const uint2 *>(la.loc);
+#define UM_HIER_CASE(ST, TC)                                                         \
+    if (staging == ST && tcmode == TC) {                                            \
+        hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC>), grid, block, size_t(lds), \
+                           la.stream, bi, la.stg_c, la.stg_n, loc, d, la.gm1, la.eps,  \
+                           base);                                                   \
+        return hipGetLastError();                                                   \
+    }
+    UM_HIER_CASE(UM_STAGE_ALL, UM_TC_BARRIER)
+    UM_HIER_CASE(UM_STAGE_ALL, UM_TC_LDS_ATOMIC)
+    UM_HIER_CASE(UM_STAGE_INC_ONLY, UM_TC_BARRIER)
+    UM_HIER_CASE(UM_STAGE_INC_ONLY, UM_TC_LDS_ATOMIC)
+#undef UM_HIER_CASE
+    return hipErrorInvalidValue;
+}
+
+template <int LAYOUT>
+void set_lds_attrs() {
+    const int max_lds = 160 * 1024;
+    hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, UM_STAGE_ALL, UM_TC_BARRIER>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, UM_STAGE_ALL, UM_TC_LDS_ATOMIC>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, UM_STAGE_INC_ONLY, UM_TC_BARRIER>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+    hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, UM_STAGE_INC_ONLY, UM_TC_LDS_ATOMIC>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+}
+
+}  // namespace
+
+hipError_t lf2d_launch_one(const LaunchArgs &la, int which, int32_t begin, int32_t end,
+                           int64_t lds) {
+    Dats d{la.x, la.q, la.adt, la.res, la.N, la.C};
+    const int layout = la.layout;
+    if (which == LAUNCH_HIER) {
+        static bool attrs = false;
+        if (!attrs) {
+            set_lds_attrs<UM_AOS>();
+            set_lds_attrs<UM_SOA>();
+            attrs = true;
+        }
+        return layout == UM_AOS
+                   ? launch_hier<UM_AOS>(la, la.staging, la.tcmode, end - begin, begin, lds, d)
+                   : launch_hier<UM_SOA>(la, la.staging, la.tcmode, end - begin, begin, lds, d);
+    }
+    const int32_t n = end - begin;
+    if (n <= 0) return hipSuccess;
+    const int tb = la.block_size;
+    dim3 grid((n + tb - 1) / tb), block(tb);
+    const int4 *em = reinterpret_cast<const int4 *>(la.emap);
+    if (which == LAUNCH_GCOL) {
+        if (layout == UM_AOS)
+            hipLaunchKernelGGL(gcol_kernel<UM_AOS>, grid, block, 0, la.stream, em, begin, end, d,
+                               la.gm1, la.eps);
+        else
+            hipLaunchKernelGGL(gcol_kernel<UM_SOA>, grid, block, 0, la.stream, em, begin, end, d,
+                               la.gm1, la.eps);
+    } else if (which == LAUNCH_ATOMIC) {
+        if (layout == UM_AOS)
+            hipLaunchKernelGGL(atomic_kernel<UM_AOS>, grid, block, 0, la.stream, em, n, d, la.gm1,
+                               la.eps);
+        else
+            hipLaunchKernelGGL(atomic_kernel<UM_SOA>, grid, block, 0, la.stream, em, n, d, la.gm1,
+                               la.eps);
+    } else if (which == LAUNCH_DEBUG) {
+        if (layout == UM_AOS)
+            hipLaunchKernelGGL(debug_kernel<UM_AOS>, grid, block, 0, la.stream, em, n, d, la.gm1,
+                               la.eps, la.out);
+        else
+            hipLaunchKernelGGL(debug_kernel<UM_SOA>, grid, block, 0, la.stream, em, n, d, la.gm1,
+                               la.eps, la.out);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace um

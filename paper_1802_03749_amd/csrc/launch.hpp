@@ -1,0 +1,36 @@
+// Launch descriptors shared by the ABI layer and the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include "internal.hpp"
+
+namespace um {
+
+enum { LAUNCH_HIER = 0, LAUNCH_GCOL = 1, LAUNCH_ATOMIC = 2, LAUNCH_DEBUG = 3 };
+
+struct LaunchArgs {
+    hipStream_t stream;
+    int32_t layout, staging, tcmode, block_size;
+    const BlockInfo *binfo;
+    const int32_t *stg_c, *stg_n;
+    const uint32_t *loc;
+    const int32_t *emap;
+    const double *x, *q, *adt;
+    double *res;
+    int64_t N, C;
+    double gm1, eps;
+    double *out;  // debug fluxes
+};
+
+// One kernel launch of the LF2D loop: HIER covers launch positions
+// [begin, end) of one block colour; GCOL covers slots [begin, end) of one
+// colour; ATOMIC and DEBUG cover elements [0, end - begin).
+hipError_t lf2d_launch_one(const LaunchArgs &la, int which, int32_t begin, int32_t end,
+                           int64_t lds_bytes);
+
+// dst[k] = src[idx[k]] for k < n over dim components (gather).
+hipError_t permute_gather(const void *src, void *dst, const int32_t *idx, int64_t n, int32_t dim,
+                          int32_t dtype, int32_t layout, hipStream_t stream);
+
+}  // namespace um

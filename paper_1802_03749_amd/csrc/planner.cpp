@@ -1,0 +1,271 @@
+// Host-side execution plans for the edge-flux loop: global colouring,
+// two-layer (block + thread) colouring with staged point lists and local
+// index maps (paper Section 2.1 and 2.2, Algorithm 1), LDS sizing.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "internal.hpp"
+
+namespace um {
+
+int64_t lf2d_lds_bytes(int32_t staging, int32_t dtype, int64_t nc, int64_t nn) {
+    const int64_t inc = nc * 4 * 8;  // FP64 increments (res preloaded)
+    if (staging == UM_STAGE_INC_ONLY) return inc;
+    const int64_t w = dtype == UM_F64 ? 8 : 4;
+    return inc + nc * 5 * w + nn * 2 * w;  // q[4], adt per cell; x[2] per node
+}
+
+namespace {
+
+// Stable counting sort of 0..n-1 by small integer keys; returns the order
+// and fills offsets[key] (size nkeys + 1).
+std::vector<int32_t> counting_order(const std::vector<int32_t> &key, int32_t nkeys,
+                                    std::vector<int32_t> &offsets) {
+    offsets.assign(nkeys + 1, 0);
+    for (int32_t k : key) offsets[k + 1]++;
+    for (int32_t c = 0; c < nkeys; ++c) offsets[c + 1] += offsets[c];
+    std::vector<int32_t> fill(offsets.begin(), offsets.end() - 1), order(key.size());
+    for (size_t i = 0; i < key.size(); ++i) order[fill[key[i]]++] = int32_t(i);
+    return order;
+}
+
+// Global first-fit colouring of elements writing cells (L, R): every cell
+// keeps a bit set of the colours already written there.
+int32_t global_colours(const Map &mc, int64_t C, std::vector<int32_t> &colour) {
+    const int64_t E = int64_t(mc.table.size()) / 2;
+    colour.assign(E, 0);
+    int32_t words = 1;
+    std::vector<uint64_t> used(C, 0);
+    int32_t ncol = 0;
+    for (int64_t e = 0; e < E; ++e) {
+        const int32_t L = mc.table[2 * e], R = mc.table[2 * e + 1];
+        int32_t c = 0;
+        for (int32_t w = 0;; ++w) {
+            if (w == words) {  // grow the bit sets by one word per point
+                std::vector<uint64_t> grown(C * (words + 1), 0);
+                for (int64_t p = 0; p < C; ++p)
+                    std::memcpy(&grown[p * (words + 1)], &used[p * words], 8 * words);
+                used.swap(grown);
+                ++words;
+            }
+            uint64_t taken = used[int64_t(L) * words + w] | used[int64_t(R) * words + w];
+            if (~taken) {
+                c = w * 64 + __builtin_ctzll(~taken);
+                break;
+            }
+        }
+        colour[e] = c;
+        used[int64_t(L) * words + c / 64] |= 1ull << (c % 64);
+        used[int64_t(R) * words + c / 64] |= 1ull << (c % 64);
+        ncol = std::max(ncol, c + 1);
+    }
+    return ncol;
+}
+
+}  // namespace
+
+void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
+                     const um_plan_opts &o, HostPlan &hp) {
+    const Map &mc = ctx.maps[ea.map_c];
+    const Map &mn = ctx.maps[ea.map_n];
+    const int64_t E = ctx.sets[iter_set].size;
+    const int64_t C = ctx.sets[mc.to].size;
+    hp.strategy = o.strategy;
+    hp.block_size = o.block_size;
+    hp.n_elem = E;
+    hp.staging = o.staging;
+    hp.tcmode = o.tcmode;
+    auto pack = [&](int64_t e, int32_t *dst) {
+        dst[0] = mc.table[2 * e];
+        dst[1] = mc.table[2 * e + 1];
+        dst[2] = mn.table[2 * e];
+        dst[3] = mn.table[2 * e + 1];
+    };
+
+    if (o.strategy == UM_STRAT_ATOMIC) {
+        hp.emap.resize(4 * E);
+        for (int64_t e = 0; e < E; ++e) pack(e, &hp.emap[4 * e]);
+        return;
+    }
+    if (o.strategy == UM_STRAT_GLOBAL_COLOUR) {
+        int32_t ncol = global_colours(mc, C, hp.elem_colour);
+        std::vector<int32_t> order = counting_order(hp.elem_colour, ncol, hp.colour_off);
+        hp.emap.resize(4 * E);
+        hp.slot_elem = order;
+        for (int64_t s = 0; s < E; ++s) pack(order[s], &hp.emap[4 * s]);
+        return;
+    }
+    if (o.strategy != UM_STRAT_HIER) fail(UM_ERR_ARG, "unknown strategy %d", o.strategy);
+
+    // ---- blocks: the set's partition if built for this size, else chunks
+    const Set &is = ctx.sets[iter_set];
+    if (is.part_block_size == o.block_size && !is.part_off.empty()) {
+        hp.blk_off = is.part_off;
+    } else {
+        hp.blk_off.clear();
+        for (int64_t s = 0; s < E; s += o.block_size) hp.blk_off.push_back(int32_t(s));
+        hp.blk_off.push_back(int32_t(E));
+        if (E == 0) hp.blk_off.assign(1, 0);
+    }
+    const int32_t nb = int32_t(hp.blk_off.size()) - 1;
+
+    // ---- layer 1: block colouring.  For every cell, the blocks that write
+    // it (in block order); a block's forbidden colours are those of the
+    // earlier blocks sharing one of its cells.
+    std::vector<int64_t> cb_off(C + 1, 0);
+    std::vector<int32_t> last(C, -1);
+    for (int32_t b = 0; b < nb; ++b)
+        for (int32_t e = hp.blk_off[b]; e < hp.blk_off[b + 1]; ++e)
+            for (int s = 0; s < 2; ++s) {
+                int32_t c = mc.table[2 * int64_t(e) + s];
+                if (last[c] != b) {
+                    last[c] = b;
+                    cb_off[c + 1]++;
+                }
+            }
+    for (int64_t c = 0; c < C; ++c) cb_off[c + 1] += cb_off[c];
+    std::vector<int32_t> cb(cb_off[C]);
+    {
+        std::vector<int64_t> fill(cb_off.begin(), cb_off.end() - 1);
+        std::fill(last.begin(), last.end(), -1);
+        for (int32_t b = 0; b < nb; ++b)
+            for (int32_t e = hp.blk_off[b]; e < hp.blk_off[b + 1]; ++e)
+                for (int s = 0; s < 2; ++s) {
+                    int32_t c = mc.table[2 * int64_t(e) + s];
+                    if (last[c] != b) {
+                        last[c] = b;
+                        cb[fill[c]++] = b;
+                    }
+                }
+    }
+    const int32_t maxcol = o.max_block_colours > 0 ? o.max_block_colours : 256;
+    hp.blk_colour.assign(nb, -1);
+    std::vector<int32_t> stamp(maxcol + 1, -1);
+    int32_t nbcol = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        for (int32_t e = hp.blk_off[b]; e < hp.blk_off[b + 1]; ++e)
+            for (int s = 0; s < 2; ++s) {
+                int32_t c = mc.table[2 * int64_t(e) + s];
+                for (int64_t i = cb_off[c]; i < cb_off[c + 1] && cb[i] < b; ++i)
+                    stamp[hp.blk_colour[cb[i]]] = b;
+            }
+        int32_t col = 0;
+        while (col < maxcol && stamp[col] == b) ++col;
+        if (col >= maxcol)
+            fail(UM_ERR_COLOURS, "block colouring needs more than %d colours (block %d of %d)",
+                 maxcol, b, nb);
+        hp.blk_colour[b] = col;
+        nbcol = std::max(nbcol, col + 1);
+    }
+    hp.blk_order = counting_order(hp.blk_colour, nbcol, hp.bcol_off);
+
+    // ---- per block in launch order: staged lists, layer 2 colouring, slots
+    std::vector<int32_t> cloc(C, -1), nloc(ctx.sets[mn.to].size, -1);
+    hp.binfo.resize(nb + 1);
+    hp.loc.resize(2 * E);
+    hp.slot_elem.resize(E);
+    hp.tcol.assign(E, 0);
+    hp.stg_c.clear();
+    hp.stg_n.clear();
+    hp.lds_per_colour.assign(nbcol, 0);
+    std::vector<int64_t> lds_all(nb);
+    std::vector<int32_t> mask, ecol, order, goff;
+    int64_t slot = 0, tcol_sum = 0;
+    hp.max_tcol = 0;
+    for (int32_t pos = 0; pos < nb; ++pos) {
+        const int32_t b = hp.blk_order[pos];
+        const int32_t e0 = hp.blk_off[b], e1 = hp.blk_off[b + 1], ne = e1 - e0;
+        BlockInfo &bi = hp.binfo[pos];
+        bi.slot_off = int32_t(slot);
+        bi.cell_off = int32_t(hp.stg_c.size());
+        bi.node_off = int32_t(hp.stg_n.size());
+        const size_t c0 = hp.stg_c.size(), n0 = hp.stg_n.size();
+        for (int32_t e = e0; e < e1; ++e) {
+            hp.stg_c.push_back(mc.table[2 * int64_t(e)]);
+            hp.stg_c.push_back(mc.table[2 * int64_t(e) + 1]);
+            hp.stg_n.push_back(mn.table[2 * int64_t(e)]);
+            hp.stg_n.push_back(mn.table[2 * int64_t(e) + 1]);
+        }
+        std::sort(hp.stg_c.begin() + c0, hp.stg_c.end());
+        hp.stg_c.erase(std::unique(hp.stg_c.begin() + c0, hp.stg_c.end()), hp.stg_c.end());
+        std::sort(hp.stg_n.begin() + n0, hp.stg_n.end());
+        hp.stg_n.erase(std::unique(hp.stg_n.begin() + n0, hp.stg_n.end()), hp.stg_n.end());
+        const int32_t nc = int32_t(hp.stg_c.size() - c0), nn = int32_t(hp.stg_n.size() - n0);
+        for (int32_t i = 0; i < nc; ++i) cloc[hp.stg_c[c0 + i]] = i;
+        for (int32_t i = 0; i < nn; ++i) nloc[hp.stg_n[n0 + i]] = i;
+        if (nc > 2048 || nn > 65535)
+            fail(UM_ERR_UNSUPPORTED, "block %d stages %d cells / %d nodes", b, nc, nn);
+
+        // layer 2: first-fit over the block's edges with per-cell bit masks
+        mask.assign(nc, 0);
+        ecol.assign(ne, 0);
+        int32_t ncol = 0;
+        for (int32_t i = 0; i < ne; ++i) {
+            const int64_t e = e0 + i;
+            const int32_t lL = cloc[mc.table[2 * e]], lR = cloc[mc.table[2 * e + 1]];
+            uint32_t taken = uint32_t(mask[lL]) | uint32_t(mask[lR]);
+            if (taken == 0xFFFFFFFFu)
+                fail(UM_ERR_UNSUPPORTED, "block %d needs more than 32 thread colours", b);
+            int32_t c = __builtin_ctz(~taken);
+            ecol[i] = c;
+            mask[lL] |= 1 << c;
+            mask[lR] |= 1 << c;
+            ncol = std::max(ncol, c + 1);
+        }
+        bi.ncol = ncol;
+        tcol_sum += ncol;
+        hp.max_tcol = std::max(hp.max_tcol, ncol);
+        // slots: the block's edges sorted by colour, stable
+        order = counting_order(ecol, ncol, goff);
+        for (int32_t i = 0; i < ne; ++i) {
+            const int64_t e = e0 + order[i];
+            const uint32_t lL = cloc[mc.table[2 * e]], lR = cloc[mc.table[2 * e + 1]];
+            const uint32_t nA = nloc[mn.table[2 * e]], nB = nloc[mn.table[2 * e + 1]];
+            const uint32_t c = uint32_t(ecol[order[i]]);
+            hp.loc[2 * slot] = lL | (c << 11) | (lR << 16);
+            hp.loc[2 * slot + 1] = nA | (nB << 16);
+            hp.slot_elem[slot] = int32_t(e);
+            hp.tcol[e] = int32_t(c);
+            ++slot;
+        }
+        for (int32_t i = 0; i < nc; ++i) cloc[hp.stg_c[c0 + i]] = -1;
+        for (int32_t i = 0; i < nn; ++i) nloc[hp.stg_n[n0 + i]] = -1;
+        lds_all[pos] = lf2d_lds_bytes(UM_STAGE_ALL, ea.dtype, nc, nn);
+    }
+    hp.binfo[nb] = BlockInfo{int32_t(slot), int32_t(hp.stg_c.size()), int32_t(hp.stg_n.size()), 0};
+
+    // ---- LDS sizing, with the increments-only fallback
+    const int64_t limit = o.lds_limit_bytes > 0 ? o.lds_limit_bytes : ctx.lds_limit;
+    int64_t need_all = 0, need_inc = 0;
+    for (int32_t pos = 0; pos < nb; ++pos) {
+        need_all = std::max(need_all, lds_all[pos]);
+        const int64_t nc = hp.binfo[pos + 1].cell_off - hp.binfo[pos].cell_off;
+        need_inc = std::max(need_inc, lf2d_lds_bytes(UM_STAGE_INC_ONLY, ea.dtype, nc, 0));
+    }
+    if (hp.staging == UM_STAGE_ALL && need_all > limit) {
+        if (!o.allow_fallback)
+            fail(UM_ERR_LDS, "staging all data needs %lld bytes of LDS per block, limit %lld",
+                 (long long)need_all, (long long)limit);
+        hp.staging = UM_STAGE_INC_ONLY;
+    }
+    if (hp.staging == UM_STAGE_INC_ONLY && need_inc > limit)
+        fail(UM_ERR_LDS, "staging increments needs %lld bytes of LDS per block, limit %lld",
+             (long long)need_inc, (long long)limit);
+    hp.lds_max = 0;
+    for (int32_t c = 0; c < nbcol; ++c) {
+        int64_t m = 0;
+        for (int32_t pos = hp.bcol_off[c]; pos < hp.bcol_off[c + 1]; ++pos) {
+            const int64_t nc = hp.binfo[pos + 1].cell_off - hp.binfo[pos].cell_off;
+            const int64_t nn = hp.binfo[pos + 1].node_off - hp.binfo[pos].node_off;
+            m = std::max(m, lf2d_lds_bytes(hp.staging, ea.dtype, nc, nn));
+        }
+        hp.lds_per_colour[c] = m;
+        hp.lds_max = std::max(hp.lds_max, m);
+    }
+    hp.staged_total = int64_t(hp.stg_c.size() + hp.stg_n.size());
+    hp.reuse = hp.stg_c.empty() ? 0.0 : double(2 * E) / double(hp.stg_c.size());
+    hp.avg_tcol = nb ? double(tcol_sum) / nb : 0.0;
+}
+
+}  // namespace um

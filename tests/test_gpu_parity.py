@@ -1,0 +1,193 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Floating-point bar: relative L2 <= 1e-12 over all C*4 residual values
+(accumulated in long double), plus exact checks where the arithmetic makes
+them exact (free stream, contraction-off per-edge fluxes, run-to-run
+determinism of the coloured strategies).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from meshgen import free_stream_state, quad_mesh  # noqa: E402
+from oracle import native  # noqa: E402
+from paper_1802_03749_amd import umesh as U  # noqa: E402
+from paper_1802_03749_amd.edgeloop import EdgeFluxLoop  # noqa: E402
+
+TOL = 1e-12
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.longdouble); b = np.asarray(b, np.longdouble)
+    return float(np.sqrt(((a - b) ** 2).sum()) / np.sqrt((b ** 2).sum()))
+
+
+def max_rel(a, b):
+    return float((np.abs(a - b).max(axis=0) / np.abs(b).max(axis=0)).max())
+
+
+_MESH = {}
+
+
+def mesh(nx, ny, seed=1):
+    key = (nx, ny, seed)
+    if key not in _MESH:
+        m = quad_mesh(nx, ny, seed=seed)
+        _MESH[key] = (m, native.edge_loop(m.e2n, m.e2c, m.x, m.q, m.adt))
+    return _MESH[key]
+
+
+def gpu_res(m, order, strategy, S, layout="aos", staging="all", tcmode="barrier", runs=1, **kw):
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order=order, block_size=S,
+                     layout=layout)
+    p = L.plan(strategy, S, staging=staging, tcmode=tcmode, **kw)
+    out = []
+    for _ in range(runs):
+        L.zero_res()
+        L.run(p)
+        torch.cuda.synchronize()
+        out.append(L.res_user())
+    return L, p, out
+
+
+def test_device_present():
+    assert torch.cuda.is_available()
+    assert "gfx950" in torch.cuda.get_device_properties(0).gcnArchName
+    U.lib()
+
+
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+@pytest.mark.parametrize("order", ["none", "rcm", "rcm+partition"])
+@pytest.mark.parametrize("strategy", ["atomic", "global", "hier"])
+@pytest.mark.parametrize("S", [128, 256, 512])
+def test_parity_small(layout, order, strategy, S):
+    """200x100 cells (~40k edges): every strategy x layout x order x block size."""
+    m, ref = mesh(200, 100)
+    if strategy == "hier" and order == "none":
+        kw = {"max_block_colours": 1 << 20}   # degenerate colouring, run anyway
+    else:
+        kw = {}
+    print(f"parity 200x100 {strategy} {order} {layout} S={S}", flush=True)
+    L, p, (r,) = gpu_res(m, order, strategy, S, layout, **kw)
+    assert rel_l2(r, ref) <= TOL
+    assert max_rel(r, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("staging,tcmode", [("inc", "barrier"), ("all", "lds_atomic"),
+                                            ("inc", "lds_atomic")])
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+def test_parity_hier_variants(staging, tcmode, layout):
+    m, ref = mesh(200, 100)
+    print(f"variant {staging} {tcmode} {layout}", flush=True)
+    L, p, (r,) = gpu_res(m, "rcm+partition", "hier", 512, layout, staging=staging, tcmode=tcmode)
+    assert p.stats["staging"] == (U.UM_STAGE_ALL if staging == "all" else U.UM_STAGE_INC_ONLY)
+    assert rel_l2(r, ref) <= TOL
+
+
+def test_lds_fallback_runs():
+    m, ref = mesh(200, 100)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition", block_size=512)
+    p = L.plan("hier", 512, lds_limit_bytes=12000, allow_fallback=True)
+    assert p.stats["staging"] == U.UM_STAGE_INC_ONLY
+    L.run(p); torch.cuda.synchronize()
+    assert rel_l2(L.res_user(), ref) <= TOL
+
+
+@pytest.mark.parametrize("S", [64, 1024])
+def test_parity_extreme_block_sizes(S):
+    m, ref = mesh(200, 100)
+    L, p, (r,) = gpu_res(m, "rcm+partition", "hier", S)
+    assert rel_l2(r, ref) <= TOL
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 2), (3, 1), (7, 5), (33, 17)])
+def test_parity_tiny_and_ragged(nx, ny):
+    """No interior edge, a single edge, and meshes whose edge count is not a
+    multiple of any block size."""
+    m = quad_mesh(nx, ny, seed=7)
+    ref = native.edge_loop(m.e2n, m.e2c, m.x, m.q, m.adt)
+    for strategy in ("atomic", "global", "hier"):
+        L, p, (r,) = gpu_res(m, "rcm+partition", strategy, 64)
+        if m.e2n.shape[0] == 0:
+            assert np.all(r == 0.0)
+        else:
+            assert rel_l2(r, ref) <= TOL
+
+
+@pytest.mark.parametrize("kind", ["p0", "p1"])
+@pytest.mark.parametrize("strategy", ["atomic", "global", "hier"])
+def test_free_stream_exact_zero_on_gpu(kind, strategy):
+    """Uniform dyadic state: interior residuals are exactly 0.0 on the GPU,
+    whatever the summation order and FMA contraction."""
+    m = quad_mesh(60, 40, seed=3, state=free_stream_state(kind))
+    L, p, (r,) = gpu_res(m, "rcm+partition", strategy, 256)
+    i, j = m.cell_nat % m.nx, m.cell_nat // m.nx
+    inner = (i > 0) & (i < m.nx - 1) & (j > 0) & (j < m.ny - 1)
+    assert np.all(r[inner] == 0.0)
+    ref = native.edge_loop(m.e2n, m.e2c, m.x, m.q, m.adt)
+    assert rel_l2(r, ref) <= TOL
+
+
+def test_contract_off_fluxes_bit_exact():
+    """With contraction disabled every flux is the same sequence of
+    correctly rounded operations as the oracle's: bit-identical."""
+    m, _ = mesh(200, 100)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition", block_size=256)
+    p = L.plan("atomic", 256)
+    f = L.debug_fluxes(p)
+    pe = L.perm(L.s_edges)
+    ref = native.edge_fluxes(m.e2n[pe], m.e2c[pe], m.x, m.q, m.adt)
+    assert np.array_equal(f.view(np.uint64), ref.view(np.uint64))
+
+
+@pytest.mark.parametrize("strategy", ["global", "hier"])
+def test_coloured_strategies_are_deterministic(strategy):
+    m, _ = mesh(200, 100)
+    L, p, (a, b, c) = gpu_res(m, "rcm+partition", strategy, 256, runs=3)
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    assert np.array_equal(a.view(np.uint64), c.view(np.uint64))
+
+
+def test_exec_accumulates_into_res():
+    m, ref = mesh(200, 100)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition", block_size=512)
+    p = L.plan("hier", 512)
+    L.zero_res()
+    for _ in range(3):
+        L.run(p)
+    torch.cuda.synchronize()
+    assert rel_l2(L.res_user(), 3 * ref) <= TOL
+
+
+def test_timing_counts_launches():
+    m, _ = mesh(200, 100)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition", block_size=512)
+    p = L.plan("hier", 512)
+    U.um_plan_set_timing(p.handle, True)
+    L.run(p); L.run(p)
+    ms, n = U.um_plan_timing(p.handle)
+    assert n == 2 * p.stats["n_launches"] and ms > 0
+
+
+@pytest.mark.parametrize("strategy,order", [("hier", "rcm+partition"), ("global", "rcm"),
+                                            ("atomic", "rcm"), ("hier", "rcm")])
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+def test_parity_medium(strategy, order, layout):
+    """1200x600 cells (~1.44M edges)."""
+    m, ref = mesh(1200, 600)
+    print(f"parity 1200x600 {strategy} {order} {layout}", flush=True)
+    L, p, (r,) = gpu_res(m, order, strategy, 512, layout)
+    assert rel_l2(r, ref) <= TOL
+
+
+def test_parity_full_size_headline_config():
+    """2400x1200 cells (~5.76M edges), FP64, RCM + partition + point reorder,
+    hierarchical colouring at the benchmark's block size: every residual
+    compared with the oracle."""
+    m, ref = mesh(2400, 1200)
+    print("parity 2400x1200 hier", flush=True)
+    L, p, (r,) = gpu_res(m, "rcm+partition", "hier", 512)
+    assert rel_l2(r, ref) <= TOL
+    assert max_rel(r, ref) <= 1e-11

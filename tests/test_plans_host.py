@@ -1,0 +1,258 @@
+"""Host-side plans of libumesh checked against the integer oracle (no GPU).
+
+The library runs on a host-only context (device -1): it reorders and plans,
+and every exported integer object is compared bit for bit with the oracle's
+re-derivation, or checked exactly where several results are valid
+(partitions).
+"""
+import ctypes
+import numpy as np
+import pytest
+
+from meshgen import quad_mesh
+from oracle import plans as P
+from paper_1802_03749_amd import umesh as U
+from paper_1802_03749_amd.edgeloop import EdgeFluxLoop
+
+
+def make(nx=40, ny=25, seed=1, **kw):
+    m = quad_mesh(nx, ny, seed=seed)
+    return m, EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=-1, **kw)
+
+
+def user_maps_match(m, L):
+    """Current maps are the user maps renumbered by the exported perms."""
+    pe, pc, pn = L.perm(L.s_edges), L.perm(L.s_cells), L.perm(L.s_nodes)
+    for p, n in [(pe, L.E), (pc, L.C), (pn, L.N)]:
+        assert P.is_permutation(p, n)
+    ic = np.empty_like(pc); ic[pc] = np.arange(pc.size)
+    inn = np.empty_like(pn); inn[pn] = np.arange(pn.size)
+    assert np.array_equal(L.current_map("e2c"), ic[m.e2c[pe]])
+    assert np.array_equal(L.current_map("e2n"), inn[m.e2n[pe]])
+
+
+def test_library_exports_every_declared_symbol():
+    import re
+    with open(U.__file__.replace("paper_1802_03749_amd/umesh.py", "include/umesh.h")) as f:
+        decl = set(re.findall(r"^\S.*?\b(um_[a-z_]+)\(", f.read(), re.M))
+    L = U.lib()
+    assert decl, "no declarations parsed"
+    for name in decl:
+        assert hasattr(L, name), name
+    assert U.um_abi_version() == U.UMESH_ABI_VERSION
+
+
+@pytest.mark.parametrize("order", ["none", "rcm", "gps"])
+def test_rcm_gps_match_oracle(order):
+    m, L = make(order=order)
+    user_maps_match(m, L)
+    if order == "none":
+        assert np.array_equal(L.perm(L.s_cells), np.arange(L.C))
+        return
+    # oracle re-derivation in the user numbering: cells by Cuthill-McKee,
+    # edges lexicographic, nodes first-touch
+    cm = P.cuthill_mckee(m.e2c, m.n_cells, reverse=(order == "rcm"))
+    assert np.array_equal(L.perm(L.s_cells), cm)
+    ic = np.empty_like(cm); ic[cm] = np.arange(cm.size)
+    eord = P.lexicographic_elements(ic[m.e2c])
+    assert np.array_equal(L.perm(L.s_edges), eord)
+    nord = P.first_touch(m.e2n[eord], m.n_nodes)
+    assert np.array_equal(L.perm(L.s_nodes), nord)
+
+
+@pytest.mark.parametrize("S", [64, 100, 512])
+@pytest.mark.parametrize("geometric", [True, False])
+def test_partition_is_valid_and_point_order_matches_oracle(S, geometric):
+    m, L = make(order="rcm+partition", block_size=S, geometric_partition=geometric)
+    user_maps_match(m, L)
+    off = L.part_blocks()
+    assert P.check_block_offsets(off, L.E, S) is None
+    assert len(off) - 1 == -(-L.E // S)   # exactly ceil(E/S) blocks
+    # point reorder: re-derive from the maps as they were after the
+    # partition's element renumbering (current maps with the point
+    # renumbering undone is the same as ordering the old points)
+    e2c, e2n = L.current_map("e2c"), L.current_map("e2n")
+    blk = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    # the library's current cell numbering must be signature-sorted
+    ords = P.signature_order(blk, [e2c], L.C)
+    sig = [tuple(sorted(set(blk[np.nonzero((e2c == c).any(1))[0]]))) for c in ords]
+    keys = [(len(s) if s else 10**9, s) for s in sig]
+    assert keys == sorted(keys)
+    assert np.array_equal(ords, np.arange(L.C)), "current numbering is already in signature order"
+    assert np.array_equal(P.signature_order(blk, [e2n], L.N), np.arange(L.N))
+
+
+def test_partition_signature_order_exact_from_previous_numbering():
+    """Partition without RCM: the point permutation equals the oracle's
+    signature order computed on the pre-reorder numbering."""
+    m, L = make(order="partition", block_size=128)
+    off = L.part_blocks()
+    pe = L.perm(L.s_edges)
+    blk_user = np.empty(L.E, np.int64)
+    blk_user[pe] = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    # in the original numbering the accessing-block signature of each point
+    # only depends on which block each edge went to
+    e_in_block_order = pe  # current edge k is user edge pe[k]
+    order_c = P.signature_order(blk_user[e_in_block_order], [m.e2c[e_in_block_order]], m.n_cells)
+    assert np.array_equal(L.perm(L.s_cells), order_c)
+    order_n = P.signature_order(blk_user[e_in_block_order], [m.e2n[e_in_block_order]], m.n_nodes)
+    assert np.array_equal(L.perm(L.s_nodes), order_n)
+
+
+@pytest.mark.parametrize("order", ["none", "rcm", "rcm+partition"])
+def test_global_colouring_is_first_fit_and_race_free(order):
+    m, L = make(order=order)
+    p = L.plan("global", 256)
+    col = L.export(p, U.UM_EXP_GLOBAL_COLOURS)
+    e2c = L.current_map("e2c")
+    assert P.check_global_colouring(col, e2c)
+    ref, nc = P.first_fit_elements(e2c)
+    assert np.array_equal(col, ref)
+    assert p.stats["n_global_colours"] == nc
+    slots = L.export(p, U.UM_EXP_SLOT_ELEMENTS)
+    assert P.is_permutation(slots, L.E)
+    assert np.all(np.diff(col[slots]) >= 0)        # slots grouped by colour
+    for c in range(nc):                              # stable inside a colour
+        s = slots[col[slots] == c]
+        assert np.all(np.diff(s) > 0)
+
+
+@pytest.mark.parametrize("order,S", [("rcm", 256), ("rcm+partition", 512), ("rcm+partition", 128),
+                                     ("partition", 1024)])
+def test_hier_plan_matches_oracle(order, S):
+    m, L = make(nx=48, ny=30, order=order, block_size=S)
+    p = L.plan("hier", S)
+    e2c, e2n = L.current_map("e2c"), L.current_map("e2n")
+    off = L.export(p, U.UM_EXP_BLOCK_OFFSETS)
+    assert P.check_block_offsets(off, L.E, S) is None
+    if "partition" in order:
+        assert np.array_equal(off, L.part_blocks())
+    # layer 1
+    bcol = L.export(p, U.UM_EXP_BLOCK_COLOURS)
+    assert P.check_block_colouring(off, bcol, e2c)
+    ref, nbc = P.first_fit_blocks(off, e2c)
+    assert np.array_equal(bcol, ref) and p.stats["n_block_colours"] == nbc
+    # layer 2
+    tcol = L.export(p, U.UM_EXP_THREAD_COLOURS)
+    assert P.check_thread_colouring(off, tcol, e2c)
+    tref, ntc = P.first_fit_threads(off, e2c)
+    assert np.array_equal(tcol, tref)
+    assert p.stats["max_thread_colours"] == ntc.max()
+    assert p.stats["avg_thread_colours"] == pytest.approx(ntc.mean())
+    # launch order: blocks grouped by colour, stable
+    border = L.export(p, U.UM_EXP_BLOCK_ORDER)
+    assert P.is_permutation(border, len(off) - 1)
+    assert np.all(np.diff(bcol[border]) >= 0)
+    # slots: each block's elements, sorted by thread colour, stable
+    slots = L.export(p, U.UM_EXP_SLOT_ELEMENTS)
+    assert P.is_permutation(slots, L.E)
+    pos = 0
+    for b in border:
+        els = slots[pos:pos + off[b + 1] - off[b]]
+        assert np.array_equal(np.sort(els), np.arange(off[b], off[b + 1]))
+        key = tcol[els] * (1 << 20) + els
+        assert np.all(np.diff(key) > 0)
+        pos += off[b + 1] - off[b]
+    # staged lists equal the sorted distinct points of each block
+    for fo, fp, t in [(U.UM_EXP_STAGED_OFFSETS_B, U.UM_EXP_STAGED_POINTS_B, e2c),
+                      (U.UM_EXP_STAGED_OFFSETS_A, U.UM_EXP_STAGED_POINTS_A, e2n)]:
+        so, sp = L.export(p, fo), L.export(p, fp)
+        ref_lists = P.staged_points(off, t)
+        assert len(so) == len(ref_lists) + 1
+        for b, r in enumerate(ref_lists):
+            assert np.array_equal(sp[so[b]:so[b + 1]], r)
+    # local indices point at the right staged entries
+    loc = L.export(p, U.UM_EXP_LOCAL_INDEX).reshape(-1, 4)
+    so_c, sp_c = L.export(p, U.UM_EXP_STAGED_OFFSETS_B), L.export(p, U.UM_EXP_STAGED_POINTS_B)
+    so_n, sp_n = L.export(p, U.UM_EXP_STAGED_OFFSETS_A), L.export(p, U.UM_EXP_STAGED_POINTS_A)
+    blk_of_elem = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    for s, e in enumerate(slots):
+        b = blk_of_elem[e]
+        assert sp_c[so_c[b] + loc[s, 0]] == e2c[e, 0] and sp_c[so_c[b] + loc[s, 1]] == e2c[e, 1]
+        assert sp_n[so_n[b] + loc[s, 2]] == e2n[e, 0] and sp_n[so_n[b] + loc[s, 3]] == e2n[e, 1]
+    assert p.stats["reuse_factor"] == pytest.approx(P.reuse_factor(off, e2c))
+    assert p.stats["reuse_factor"] <= 4.0
+
+
+def test_partition_raises_reuse_to_paper_range():
+    """Partition-based reordering lifts reuse from ~2 towards the paper's 3.6
+    at block sizes near 480 (Table 2), bounded by 4 on quads."""
+    _, L = make(nx=120, ny=60, order="rcm+partition", block_size=512)
+    p = L.plan("hier", 512)
+    assert 3.3 <= p.stats["reuse_factor"] <= 4.0
+    assert p.stats["n_block_colours"] <= 8
+    assert p.stats["max_thread_colours"] <= 6
+
+
+def test_random_order_block_colours_degenerate_and_limit():
+    _, L = make(nx=60, ny=30, order="none")
+    p = L.plan("hier", 256)
+    assert p.stats["n_block_colours"] > 0.5 * p.stats["n_blocks"]
+    with pytest.raises(U.UmeshError) as ei:
+        L.plan("hier", 256, max_block_colours=4)
+    assert ei.value.status == U.UM_ERR_COLOURS
+
+
+def test_lds_limit_fallback_and_error():
+    _, L = make(order="rcm+partition", block_size=512)
+    p = L.plan("hier", 512)
+    need = p.stats["lds_bytes_max"]
+    q = L.plan("hier", 512, lds_limit_bytes=need - 8, allow_fallback=True)
+    assert q.stats["staging"] == U.UM_STAGE_INC_ONLY
+    assert q.stats["lds_bytes_max"] < need
+    with pytest.raises(U.UmeshError) as ei:
+        L.plan("hier", 512, lds_limit_bytes=need - 8, allow_fallback=False)
+    assert ei.value.status == U.UM_ERR_LDS
+    with pytest.raises(U.UmeshError) as ei:
+        L.plan("hier", 512, lds_limit_bytes=64, allow_fallback=True)
+    assert ei.value.status == U.UM_ERR_LDS
+
+
+def test_declaration_errors():
+    ctx = U.um_create(-1)
+    try:
+        s_c = U.um_decl_set(ctx, 4, "cells")
+        s_e = U.um_decl_set(ctx, 2, "edges")
+        bad = np.array([[0, 1], [2, 4]], np.int32)         # 4 is out of range
+        with pytest.raises(U.UmeshError) as ei:
+            U.um_decl_map(ctx, s_e, s_c, 2, bad)
+        assert ei.value.status == U.UM_ERR_RANGE
+        assert "outside" in U.um_last_error()
+        with pytest.raises(U.UmeshError) as ei:
+            U.um_decl_map(ctx, s_e, s_c, 0, bad)
+        assert ei.value.status == U.UM_ERR_ARG
+        with pytest.raises(U.UmeshError):
+            U.um_decl_dat(ctx, 7, 4, U.UM_F64, U.UM_AOS, None)
+        m = U.um_decl_map(ctx, s_e, s_c, 2, np.array([[0, 1], [2, 3]], np.int32))
+        d = U.um_decl_dat(ctx, s_c, 4, U.UM_F64, U.UM_AOS, None)
+        # reordering after dats exist is refused
+        o = U.um_reorder_opts(); o.mode = U.UM_REORDER_RCM; o.driving_map = m
+        with pytest.raises(U.UmeshError) as ei:
+            U.um_reorder_mesh(ctx, o)
+        assert ei.value.status == U.UM_ERR_STATE
+        # wrong argument pattern for the edge kernel
+        o = U.um_plan_opts(); o.strategy = U.UM_STRAT_HIER; o.block_size = 64
+        args = [U.um_arg(d, m, 0, U.UM_READ)] * 8
+        with pytest.raises(U.UmeshError) as ei:
+            U.um_plan_build(ctx, U.UM_K_EDGE_FLUX_LF2D, args, s_e, o)
+        assert ei.value.status == U.UM_ERR_ARITY
+        # execution on a host-only context is refused
+    finally:
+        U.um_destroy(ctx)
+
+
+def test_host_only_context_cannot_execute():
+    _, L = make(nx=6, ny=4, order="rcm")
+    p = L.plan("atomic", 64)
+    with pytest.raises(U.UmeshError) as ei:
+        U.um_loop_exec(p.handle, (0.4, 0.25), 0)
+    assert ei.value.status == U.UM_ERR_STATE
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 2), (2, 1), (3, 1)])
+def test_degenerate_meshes_plan(nx, ny):
+    """No interior edge (1x1) or a single one: every strategy plans."""
+    _, L = make(nx=nx, ny=ny, order="rcm+partition", block_size=64)
+    for strat in ("atomic", "global", "hier"):
+        p = L.plan(strat, 64)
+        assert p.stats["n_elements"] == L.E
