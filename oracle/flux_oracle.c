@@ -10,7 +10,7 @@
  * binary64 operation in the order written below.
  *
  * What is computed (paper, Section 1.1.1 "Unstructured meshes" and the
- * Airfoil res_calc description in Section 3.2): a loop over the interior
+ * Airfoil res_calc description in Section 3.1.1): a loop over the interior
  * edges that reads 2 node coordinates through edge->node, 4 conserved
  * variables and 1 time-step scalar on each of 2 cells through edge->cell,
  * evaluates a flux of about 100 flops, and increments 4 residual values on
