@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the race-free indirect-increment edge loop on one MI355X.
+
+One step = one execution of the whole loop (every block-colour launch) over
+the 2D edge-flux workload: a 2400 x 1200 jittered quad mesh (2.88M cells,
+5,756,400 interior edges) in FP64, reordered (reverse Cuthill-McKee, then
+block partitioning with block-signature point grouping) and run with the
+two-layer (hierarchical) colouring.  Inputs are seeded synthetic data
+resident in HBM before timing starts; the plan is built once beforehand and
+its build time is reported separately.
+
+Prints one JSON line (see the keys below) to stdout; progress goes to stderr.
+The global-colouring and atomics baselines run on the same GPU on the same
+mesh (reverse Cuthill-McKee order, their best), and the CPU oracle is timed
+on the host as the CPU baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+METRIC = "edges/s and achieved HBM GB/s (% peak) vs atomics/global-colour, FP64 and FP32"
+KERNEL_SRC = os.path.join(ROOT, "paper_1802_03749_amd", "csrc", "kernels_lf2d.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hier_kernel_2400x1200_traffic.json")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def time_steps(torch, run, steps: int, warmup: int) -> float:
+    """Seconds per step over `steps` timed steps after `warmup` untimed."""
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / steps
+
+
+def copy_probe(torch, nbytes: int = 512 << 20, reps: int = 20):
+    """Device-to-device copy of nbytes (read nbytes + write nbytes): the
+    bandwidth a plain streaming kernel reaches on this GPU, and the
+    reference kernel of known size for scaling HBM byte counters."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2 * nbytes / sec / 1e9, sec
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--nx", type=int, default=2400)
+    ap.add_argument("--ny", type=int, default=1200)
+    ap.add_argument("--block-size", type=int, default=512)
+    ap.add_argument("--layout", default="aos", choices=["aos", "soa"])
+    ap.add_argument("--staging", default="all", choices=["all", "inc"])
+    ap.add_argument("--tcmode", default="barrier", choices=["barrier", "lds_atomic"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="host time spent timing the CPU oracle (0 = skip)")
+    ap.add_argument("--no-baselines", action="store_true",
+                    help="skip the global-colour and atomics baselines")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from meshgen import quad_mesh
+    from paper_1802_03749_amd import measure
+    from paper_1802_03749_amd import umesh as U
+    from paper_1802_03749_amd.edgeloop import PARAMS, EdgeFluxLoop
+
+    U.lib()  # fails loudly if the HIP library is not built
+    dev = torch.cuda.get_device_properties(0)
+    log(f"device {dev.name} {dev.gcnArchName} CUs={dev.multi_processor_count}")
+    copy_gbps, _ = copy_probe(torch)
+    log(f"device copy: {copy_gbps:.0f} GB/s (read + write of 512 MiB)")
+    nx, ny, S = args.nx, args.ny, args.block_size
+    C, N, E = measure.quad_counts(nx, ny)
+    t = time.perf_counter()
+    mesh = quad_mesh(nx, ny, seed=1)
+    log(f"mesh {nx}x{ny}: C={C} N={N} E={E} generated in {time.perf_counter() - t:.1f}s")
+
+    # ---- hierarchical colouring on the reordered + partitioned mesh
+    t = time.perf_counter()
+    hier = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0,
+                        order="rcm+partition", block_size=S, layout=args.layout)
+    reorder_s = time.perf_counter() - t
+    plan = hier.plan("hier", S, staging=args.staging, tcmode=args.tcmode)
+    st = plan.stats
+    log(f"reorder {reorder_s:.1f}s, plan {st['build_seconds']:.2f}s: blocks={st['n_blocks']} "
+        f"block colours={st['n_block_colours']} thread colours<={st['max_thread_colours']} "
+        f"reuse={st['reuse_factor']:.3f} lds={st['lds_bytes_max']}")
+    run = lambda: hier.run(plan)
+    sec = time_steps(torch, run, args.steps, args.warmup)
+    log(f"hier: {sec * 1e6:.1f} us/step")
+
+    # per-launch kernel time over a second timed pass (HIP events around
+    # every launch, recorded by the library on the launch stream)
+    U.um_plan_set_timing(plan.handle, True)
+    for _ in range(args.steps):
+        run()
+    kern_ms, n_launch = U.um_plan_timing(plan.handle)
+    U.um_plan_set_timing(plan.handle, False)
+    torch.cuda.synchronize()
+    useful = measure.useful_bytes(N, C, E)
+    launches_per_step = st["n_launches"]
+    avg_launch_s = kern_ms * 1e-3 / n_launch
+    bytes_per_launch = useful / launches_per_step
+    achieved, frac = measure.roofline(bytes_per_launch, avg_launch_s)
+    log(f"kernel time/step {kern_ms / args.steps * 1e3:.1f} us over {launches_per_step} launches; "
+        f"achieved {achieved:.0f} GB/s ({100 * frac:.1f}% of peak)")
+
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if (tr.get("kernel_source_sha256") == kernel_hash() and tr.get("block_size") == S
+                and tr.get("layout") == args.layout and tr.get("staging") == args.staging):
+            traffic = tr.get("bytes_per_launch")
+
+    # ---- baselines on the same GPU and mesh
+    baselines = {}
+    if not args.no_baselines:
+        base = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0, order="rcm",
+                            layout=args.layout)
+        for name, strat in (("global_colour", "global"), ("atomics", "atomic")):
+            p = base.plan(strat, 256)
+            s = time_steps(torch, lambda: base.run(p), args.steps, args.warmup)
+            baselines[name] = {
+                "order": "rcm", "edges_per_s": E / s, "ms_per_step": s * 1e3,
+                "useful_gbps": useful / s / 1e9, "launches": p.stats["n_launches"],
+                "hier_speedup": s / sec,
+            }
+            log(f"{name}: {s * 1e6:.1f} us/step ({useful / s / 1e9:.0f} GB/s)")
+        base.close()
+
+    # ---- CPU baseline: the oracle's sequential loop on the host
+    cpu = None
+    if args.cpu_seconds > 0:
+        from oracle import native
+        native.lib()
+        t0 = time.perf_counter()
+        sweeps = 0
+        while True:
+            native.edge_loop(mesh.e2n, mesh.e2c, mesh.x, mesh.q, mesh.adt)
+            sweeps += 1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds and sweeps >= 2:
+                break
+        cpu = {"value": E * sweeps / el, "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": f"{sweeps} full sequential sweeps of the same {nx}x{ny} mesh "
+                         f"({E} edges) in user numbering, {el:.1f}s on 1 host core "
+                         f"(host has {os.cpu_count()} logical CPUs)"}
+        log(f"cpu oracle: {cpu['value']:.3g} edges/s")
+
+    out = {
+        "metric": METRIC,
+        "value": E / sec,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"2D quad edge-flux loop (central Euler flux + scalar Lax-Friedrichs "
+                        f"dissipation), {nx}x{ny} cells, jitter 0.2h, seed 1, FP64",
+            "cells": C, "nodes": N, "edges": E,
+            "strategy": "hierarchical two-layer colouring",
+            "order": "rcm+partition+point-reorder",
+            "block_size": S, "layout": args.layout, "staging": args.staging,
+            "tcmode": args.tcmode, "parallelism": "none (one GPU)",
+        },
+        "useful_gbps": useful / sec / 1e9,
+        "useful_bytes_per_step": useful,
+        "pct_hbm_peak_step": 100 * useful / sec / 1e9 / measure.HBM_PEAK_GBPS,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": measure.HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": frac, "traffic": traffic,
+                     "kernel": "hier_kernel", "launches_per_step": launches_per_step,
+                     "avg_launch_us": avg_launch_s * 1e6,
+                     "bytes_per_launch": bytes_per_launch},
+        "cpu_baseline": cpu,
+        "baselines": baselines,
+        "plan": {k: st[k] for k in ("n_blocks", "n_block_colours", "max_thread_colours",
+                                     "avg_thread_colours", "reuse_factor", "lds_bytes_max",
+                                     "staged_points", "plan_device_bytes", "build_seconds")},
+        "reorder_seconds": reorder_s,
+        "device_copy_gbps": copy_gbps,
+    }
+    print(json.dumps(out), flush=True)
+    hier.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

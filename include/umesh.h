@@ -150,7 +150,11 @@ typedef struct {
                                   limit (163840 on gfx950; 65536 host-only)  */
     int32_t allow_fallback;    /* HIER: 1 = STAGE_ALL over the LDS limit falls
                                   back to STAGE_INC_ONLY instead of failing  */
-    int32_t reserved[5];
+    int32_t elems_per_thread;  /* HIER: elements each lane computes, 1, 2 or 4
+                                  (0 means 1); the workgroup has
+                                  ceil(block_size / elems_per_thread) lanes
+                                  rounded up to a multiple of 64             */
+    int32_t reserved[4];
 } um_plan_opts;
 
 typedef struct {

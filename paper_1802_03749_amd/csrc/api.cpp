@@ -142,7 +142,8 @@ LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *str
     la.layout = p.ea.layout;
     la.staging = p.hp.staging;
     la.tcmode = p.hp.tcmode;
-    la.block_size = p.hp.block_size;
+    la.block_size = p.hp.strategy == UM_STRAT_HIER ? p.hp.threads : p.hp.block_size;
+    la.ept = p.hp.ept;
     la.binfo = p.dp.binfo;
     la.stg_c = p.dp.stg_c;
     la.stg_n = p.dp.stg_n;
@@ -393,6 +394,9 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
         if (o.tcmode != UM_TC_BARRIER && o.tcmode != UM_TC_LDS_ATOMIC)
             fail(UM_ERR_ARG, "bad tcmode %d", o.tcmode);
         if (o.max_block_colours < 0 || o.lds_limit_bytes < 0) fail(UM_ERR_ARG, "negative limit");
+        if (o.elems_per_thread != 0 && o.elems_per_thread != 1 && o.elems_per_thread != 2 &&
+            o.elems_per_thread != 4)
+            fail(UM_ERR_ARG, "elems_per_thread %d not in {1, 2, 4}", o.elems_per_thread);
         const auto t0 = std::chrono::steady_clock::now();
         EdgeArgs ea = check_lf2d_args(c, args, nargs, iter_set);
         auto *p = new um_plan_s();

@@ -91,6 +91,7 @@ struct BlockInfo {
 
 struct HostPlan {
     int32_t strategy = 0, staging = 0, tcmode = 0, block_size = 0;
+    int32_t ept = 1, threads = 0;              // HIER: elements per lane, lanes per block
     int64_t n_elem = 0;
     // GLOBAL_COLOUR / ATOMIC: packed (L, R, a, b) per slot, slot order
     std::vector<int32_t> emap;                 // [n_slots][4]

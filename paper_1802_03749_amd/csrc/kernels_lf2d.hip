@@ -107,6 +107,14 @@ __device__ __forceinline__ void load2(const double *__restrict__ a, int64_t n, i
     }
 }
 
+// LDS floating-point add without return (ds_add_f64).  Inside one colour
+// round no two lanes touch the same address, so the result equals a plain
+// read-modify-write and stays deterministic; it is one LDS instruction
+// instead of a read and a write.
+__device__ __forceinline__ void lds_add(double *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 struct Dats {
     const double *__restrict__ x;
     const double *__restrict__ q;
@@ -127,7 +135,36 @@ __device__ __forceinline__ void edge_flux_global(const Dats &d, int L, int R, in
     lf2d_flux(xa0, xa1, xb0, xb1, qL, qR, adtL, adtR, gm1, eps, f);
 }
 
-template <int LAYOUT, int STAGING, int TCMODE>
+// Stage the residual (as accumulator) and, when staging all, q and adt of
+// staged cell t into LDS, from registers loaded by fetch_cell.
+struct CellRegs {
+    double r[4], q[4], a;
+};
+
+template <int LAYOUT, int STAGING>
+__device__ __forceinline__ void fetch_cell(const Dats &d, int64_t g, CellRegs &c) {
+    load4<LAYOUT>(d.res, d.C, g, c.r);
+    if constexpr (STAGING == UM_STAGE_ALL) {
+        load4<LAYOUT>(d.q, d.C, g, c.q);
+        c.a = d.adt[g];
+    }
+}
+
+template <int STAGING>
+__device__ __forceinline__ void put_cell(double *s_inc, double *s_q, double *s_adt, int nc, int t,
+                                         const CellRegs &c) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s_inc[k * nc + t] = c.r[k];
+    if constexpr (STAGING == UM_STAGE_ALL) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_q[k * nc + t] = c.q[k];
+        s_adt[t] = c.a;
+    }
+}
+
+// EPT = elements (edges) per lane: the workgroup has T lanes and handles a
+// block of up to EPT*T edges; lane l computes slots l, l+T, ...
+template <int LAYOUT, int STAGING, int TCMODE, int EPT>
 __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict__ binfo,
                                                     const int32_t *__restrict__ stg_c,
                                                     const int32_t *__restrict__ stg_n,
@@ -145,74 +182,103 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
     double *s_q = s_inc + 4 * nc;   // [4][nc]
     double *s_adt = s_q + 4 * nc;   // [nc]
     double *s_x = s_adt + nc;       // [2][nn]
-    const int tid = int(threadIdx.x), S = int(blockDim.x);
+    const int tid = int(threadIdx.x), T = int(blockDim.x);
 
-    // gather: residuals (as accumulators) and, when staging all, q, adt, x
-    for (int t = tid; t < nc; t += S) {
-        const int64_t g = sc[t];
-        double r[4];
-        load4<LAYOUT>(d.res, d.C, g, r);
-        if constexpr (STAGING == UM_STAGE_ALL) {
-            double qv[4];
-            load4<LAYOUT>(d.q, d.C, g, qv);
-            const double a = d.adt[g];
+    // local index words of this lane's slots: issued first, used after the
+    // barrier
+    uint2 w[EPT];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) s_q[k * nc + t] = qv[k];
-            s_adt[t] = a;
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s_inc[k * nc + t] = r[k];
+    for (int j = 0; j < EPT; ++j) {
+        const int s = tid + j * T;
+        w[j] = s < ne ? loc[bi.slot_off + s] : make_uint2(0, 0);
+    }
+
+    // gather: two staged cells and two staged nodes per lane per pass, all
+    // loads of a pass issued before its LDS stores
+    for (int t0 = tid; t0 < nc; t0 += 2 * T) {
+        const int t1 = t0 + T;
+        const bool has1 = t1 < nc;
+        const int64_t g0 = sc[t0];
+        const int64_t g1 = has1 ? sc[t1] : g0;
+        CellRegs c0, c1;
+        fetch_cell<LAYOUT, STAGING>(d, g0, c0);
+        fetch_cell<LAYOUT, STAGING>(d, g1, c1);
+        put_cell<STAGING>(s_inc, s_q, s_adt, nc, t0, c0);
+        if (has1) put_cell<STAGING>(s_inc, s_q, s_adt, nc, t1, c1);
     }
     if constexpr (STAGING == UM_STAGE_ALL) {
-        for (int t = tid; t < nn; t += S) {
-            double x0, x1;
-            load2<LAYOUT>(d.x, d.N, sn[t], x0, x1);
-            s_x[t] = x0;
-            s_x[nn + t] = x1;
+        for (int t0 = tid; t0 < nn; t0 += 2 * T) {
+            const int t1 = t0 + T;
+            const bool has1 = t1 < nn;
+            const int64_t g0 = sn[t0];
+            const int64_t g1 = has1 ? sn[t1] : g0;
+            double a0, a1, b0, b1;
+            load2<LAYOUT>(d.x, d.N, g0, a0, a1);
+            load2<LAYOUT>(d.x, d.N, g1, b0, b1);
+            s_x[t0] = a0;
+            s_x[nn + t0] = a1;
+            if (has1) {
+                s_x[t1] = b0;
+                s_x[nn + t1] = b1;
+            }
         }
     }
-    uint2 w = make_uint2(0, 0);
-    if (tid < ne) w = loc[bi.slot_off + tid];
     __syncthreads();
 
-    const int lL = int(w.x & 0x7FFu), col = int((w.x >> 11) & 31u), lR = int((w.x >> 16) & 0x7FFu);
-    const int nA = int(w.y & 0xFFFFu), nB = int(w.y >> 16);
-    double f[4] = {0.0, 0.0, 0.0, 0.0};
-    if (tid < ne) {
-        if constexpr (STAGING == UM_STAGE_ALL) {
-            double qL[4], qR[4];
+    // fluxes of this lane's edges into registers
+    int lL[EPT], lR[EPT], col[EPT];
+    double f[EPT][4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                qL[k] = s_q[k * nc + lL];
-                qR[k] = s_q[k * nc + lR];
+    for (int j = 0; j < EPT; ++j) {
+        lL[j] = int(w[j].x & 0x7FFu);
+        col[j] = (tid + j * T) < ne ? int((w[j].x >> 11) & 31u) : -1;
+        lR[j] = int((w[j].x >> 16) & 0x7FFu);
+        const int nA = int(w[j].y & 0xFFFFu), nB = int(w[j].y >> 16);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[j][k] = 0.0;
+        if (col[j] >= 0) {
+            if constexpr (STAGING == UM_STAGE_ALL) {
+                double qL[4], qR[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    qL[k] = s_q[k * nc + lL[j]];
+                    qR[k] = s_q[k * nc + lR[j]];
+                }
+                lf2d_flux(s_x[nA], s_x[nn + nA], s_x[nB], s_x[nn + nB], qL, qR, s_adt[lL[j]],
+                          s_adt[lR[j]], gm1, eps, f[j]);
+            } else {
+                edge_flux_global<LAYOUT>(d, sc[lL[j]], sc[lR[j]], sn[nA], sn[nB], gm1, eps, f[j]);
             }
-            lf2d_flux(s_x[nA], s_x[nn + nA], s_x[nB], s_x[nn + nB], qL, qR, s_adt[lL],
-                      s_adt[lR], gm1, eps, f);
-        } else {
-            edge_flux_global<LAYOUT>(d, sc[lL], sc[lR], sn[nA], sn[nB], gm1, eps, f);
         }
     }
 
     if constexpr (TCMODE == UM_TC_BARRIER) {
-        // layer 2: one thread colour at a time; same-colour lanes never
-        // share a cell, so their LDS read-modify-writes do not race
+        // layer 2: one thread colour at a time; same-colour edges never share
+        // a cell, so their LDS read-modify-writes do not race.  Slots are
+        // sorted by colour, so most wavefronts hold a single colour.
         const int ncol = bi.ncol;
         for (int c = 0; c < ncol; ++c) {
-            if (tid < ne && col == c) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    s_inc[k * nc + lL] += f[k];
-                    s_inc[k * nc + lR] -= f[k];
+            for (int j = 0; j < EPT; ++j) {
+                if (col[j] == c) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        lds_add(&s_inc[k * nc + lL[j]], f[j][k]);
+                        lds_add(&s_inc[k * nc + lR[j]], -f[j][k]);
+                    }
                 }
             }
             __syncthreads();
         }
     } else {
-        if (tid < ne) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                atomicAdd(&s_inc[k * nc + lL], f[k]);
-                atomicAdd(&s_inc[k * nc + lR], -f[k]);
+        for (int j = 0; j < EPT; ++j) {
+            if (col[j] >= 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    lds_add(&s_inc[k * nc + lL[j]], f[j][k]);
+                    lds_add(&s_inc[k * nc + lR[j]], -f[j][k]);
+                }
             }
         }
         __syncthreads();
@@ -220,7 +286,7 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
 
     // write back once per staged cell; no other block of this colour
     // touches these cells
-    for (int t = tid; t < nc; t += S) {
+    for (int t = tid; t < nc; t += T) {
         double r[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) r[k] = s_inc[k * nc + t];
@@ -282,38 +348,54 @@ __global__ __launch_bounds__(1024) void debug_kernel(const int4 *__restrict__ em
     for (int k = 0; k < 4; ++k) out[4 * int64_t(s) + k] = f[k];
 }
 
-template <int LAYOUT>
-hipError_t launch_hier(const LaunchArgs &la, int staging, int tcmode, int32_t nblocks,
-                       int32_t base, int64_t lds, Dats d) {
-    dim3 grid(nblocks), block(la.block_size);
-    const BlockInfo *bi = la.binfo;
-    const uint2 *loc = reinterpret_cast<const uint2 *>(la.loc);
-#define UM_HIER_CASE(ST, TC)                                                         \
-    if (staging == ST && tcmode == TC) {                                            \
-        hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC>), grid, block, size_t(lds), \
-                           la.stream, bi, la.stg_c, la.stg_n, loc, d, la.gm1, la.eps,  \
-                           base);                                                   \
-        return hipGetLastError();                                                   \
+template <int LAYOUT, int ST, int TC, int EPT>
+void set_attr_one() {
+    hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, ST, TC, EPT>),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+template <int LAYOUT, int ST, int TC>
+hipError_t launch_hier_ept(const LaunchArgs &la, int32_t nblocks, int32_t base, int64_t lds,
+                           Dats d) {
+    static bool attrs = false;
+    if (!attrs) {
+        set_attr_one<LAYOUT, ST, TC, 1>();
+        set_attr_one<LAYOUT, ST, TC, 2>();
+        set_attr_one<LAYOUT, ST, TC, 4>();
+        attrs = true;
     }
-    UM_HIER_CASE(UM_STAGE_ALL, UM_TC_BARRIER)
-    UM_HIER_CASE(UM_STAGE_ALL, UM_TC_LDS_ATOMIC)
-    UM_HIER_CASE(UM_STAGE_INC_ONLY, UM_TC_BARRIER)
-    UM_HIER_CASE(UM_STAGE_INC_ONLY, UM_TC_LDS_ATOMIC)
-#undef UM_HIER_CASE
-    return hipErrorInvalidValue;
+    dim3 grid(nblocks), block(la.block_size);
+    const uint2 *loc = reinterpret_cast<const uint2 *>(la.loc);
+    switch (la.ept) {
+    case 1:
+        hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, 1>), grid, block, size_t(lds), la.stream,
+                           la.binfo, la.stg_c, la.stg_n, loc, d, la.gm1, la.eps, base);
+        break;
+    case 2:
+        hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, 2>), grid, block, size_t(lds), la.stream,
+                           la.binfo, la.stg_c, la.stg_n, loc, d, la.gm1, la.eps, base);
+        break;
+    case 4:
+        hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, 4>), grid, block, size_t(lds), la.stream,
+                           la.binfo, la.stg_c, la.stg_n, loc, d, la.gm1, la.eps, base);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <int LAYOUT>
-void set_lds_attrs() {
-    const int max_lds = 160 * 1024;
-    hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, UM_STAGE_ALL, UM_TC_BARRIER>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, UM_STAGE_ALL, UM_TC_LDS_ATOMIC>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, UM_STAGE_INC_ONLY, UM_TC_BARRIER>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
-    hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, UM_STAGE_INC_ONLY, UM_TC_LDS_ATOMIC>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+hipError_t launch_hier(const LaunchArgs &la, int32_t nblocks, int32_t base, int64_t lds, Dats d) {
+    if (la.staging == UM_STAGE_ALL && la.tcmode == UM_TC_BARRIER)
+        return launch_hier_ept<LAYOUT, UM_STAGE_ALL, UM_TC_BARRIER>(la, nblocks, base, lds, d);
+    if (la.staging == UM_STAGE_ALL && la.tcmode == UM_TC_LDS_ATOMIC)
+        return launch_hier_ept<LAYOUT, UM_STAGE_ALL, UM_TC_LDS_ATOMIC>(la, nblocks, base, lds, d);
+    if (la.staging == UM_STAGE_INC_ONLY && la.tcmode == UM_TC_BARRIER)
+        return launch_hier_ept<LAYOUT, UM_STAGE_INC_ONLY, UM_TC_BARRIER>(la, nblocks, base, lds, d);
+    if (la.staging == UM_STAGE_INC_ONLY && la.tcmode == UM_TC_LDS_ATOMIC)
+        return launch_hier_ept<LAYOUT, UM_STAGE_INC_ONLY, UM_TC_LDS_ATOMIC>(la, nblocks, base, lds, d);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -322,17 +404,9 @@ hipError_t lf2d_launch_one(const LaunchArgs &la, int which, int32_t begin, int32
                            int64_t lds) {
     Dats d{la.x, la.q, la.adt, la.res, la.N, la.C};
     const int layout = la.layout;
-    if (which == LAUNCH_HIER) {
-        static bool attrs = false;
-        if (!attrs) {
-            set_lds_attrs<UM_AOS>();
-            set_lds_attrs<UM_SOA>();
-            attrs = true;
-        }
-        return layout == UM_AOS
-                   ? launch_hier<UM_AOS>(la, la.staging, la.tcmode, end - begin, begin, lds, d)
-                   : launch_hier<UM_SOA>(la, la.staging, la.tcmode, end - begin, begin, lds, d);
-    }
+    if (which == LAUNCH_HIER)
+        return layout == UM_AOS ? launch_hier<UM_AOS>(la, end - begin, begin, lds, d)
+                                : launch_hier<UM_SOA>(la, end - begin, begin, lds, d);
     const int32_t n = end - begin;
     if (n <= 0) return hipSuccess;
     const int tb = la.block_size;

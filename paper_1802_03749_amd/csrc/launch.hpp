@@ -11,7 +11,7 @@ enum { LAUNCH_HIER = 0, LAUNCH_GCOL = 1, LAUNCH_ATOMIC = 2, LAUNCH_DEBUG = 3 };
 
 struct LaunchArgs {
     hipStream_t stream;
-    int32_t layout, staging, tcmode, block_size;
+    int32_t layout, staging, tcmode, block_size, ept;
     const BlockInfo *binfo;
     const int32_t *stg_c, *stg_n;
     const uint32_t *loc;

@@ -76,6 +76,8 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     hp.n_elem = E;
     hp.staging = o.staging;
     hp.tcmode = o.tcmode;
+    hp.ept = o.elems_per_thread > 0 ? o.elems_per_thread : 1;
+    hp.threads = ((o.block_size + hp.ept - 1) / hp.ept + 63) / 64 * 64;
     auto pack = [&](int64_t e, int32_t *dst) {
         dst[0] = mc.table[2 * e];
         dst[1] = mc.table[2 * e + 1];

@@ -166,7 +166,7 @@ class EdgeFluxLoop:
 
     def plan(self, strategy: str = "hier", block_size: int = 512, staging: str = "all",
              tcmode: str = "barrier", max_block_colours: int = 256, lds_limit_bytes: int = 0,
-             allow_fallback: bool = True) -> Plan:
+             allow_fallback: bool = True, elems_per_thread: int = 1) -> Plan:
         o = U.um_plan_opts()
         o.strategy = STRATEGIES[strategy]
         o.block_size = block_size
@@ -175,6 +175,7 @@ class EdgeFluxLoop:
         o.max_block_colours = max_block_colours
         o.lds_limit_bytes = lds_limit_bytes
         o.allow_fallback = 1 if allow_fallback else 0
+        o.elems_per_thread = elems_per_thread
         h = U.um_plan_build(self.ctx, U.UM_K_EDGE_FLUX_LF2D, self.args(), self.s_edges, o)
         p = Plan(h, strategy, block_size, U.um_plan_stats_get(h).as_dict())
         self._plans.append(p)

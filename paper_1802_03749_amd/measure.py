@@ -1,0 +1,37 @@
+"""Bandwidth accounting for the edge-flux loop.
+
+Useful bandwidth (paper Section 3.1, "Experimental setup"): the sum over the
+datasets of w_d * S_d, with w_d = 2 for data that is read and written and 1
+otherwise, divided by the kernel time.  For the 2D edge-flux loop the
+datasets are x (2 values per node), q (4 per cell), adt (1 per cell), res
+(4 per cell, read and written) and the two int32 edge maps (2 entries per
+edge each).  Counting the maps reproduces the paper's own figures: bandwidth
+times runtime is 437-440 MB in every column of the Airfoil res_calc table
+(Table 2), which is what this formula gives for 2.88M cells.
+"""
+from __future__ import annotations
+
+HBM_PEAK_GBPS = 8000.0        # MI355X HBM3E, published peak
+FP64_VECTOR_TFLOPS = 78.6     # MI355X, published
+FLOPS_PER_EDGE = 100          # the paper's figure for this loop (Section 3.1.1)
+
+
+def useful_bytes(n_nodes: int, n_cells: int, n_edges: int, real_bytes: int = 8,
+                 res_bytes: int = 8, map_bytes: int = 4) -> int:
+    """Algorithmic bytes of one sweep: every dataset once, res twice, both maps."""
+    x = 2 * real_bytes * n_nodes
+    q = 4 * real_bytes * n_cells
+    adt = 1 * real_bytes * n_cells
+    res = 2 * 4 * res_bytes * n_cells
+    maps = 2 * 2 * map_bytes * n_edges
+    return x + q + adt + res + maps
+
+
+def quad_counts(nx: int, ny: int):
+    """(cells, nodes, interior edges) of an nx x ny quad mesh."""
+    return nx * ny, (nx + 1) * (ny + 1), 2 * nx * ny - nx - ny
+
+
+def roofline(bytes_per_launch: float, avg_launch_s: float, peak_gbps: float = HBM_PEAK_GBPS):
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    return achieved, achieved / peak_gbps

@@ -61,7 +61,7 @@ class um_plan_opts(ct.Structure):
     _fields_ = [("strategy", ct.c_int32), ("block_size", ct.c_int32), ("staging", ct.c_int32),
                 ("tcmode", ct.c_int32), ("max_block_colours", ct.c_int32),
                 ("lds_limit_bytes", ct.c_int32), ("allow_fallback", ct.c_int32),
-                ("reserved", ct.c_int32 * 5)]
+                ("elems_per_thread", ct.c_int32), ("reserved", ct.c_int32 * 4)]
 
 
 class um_plan_stats(ct.Structure):

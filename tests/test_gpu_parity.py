@@ -86,6 +86,18 @@ def test_parity_hier_variants(staging, tcmode, layout):
     assert rel_l2(r, ref) <= TOL
 
 
+@pytest.mark.parametrize("ept", [2, 4])
+@pytest.mark.parametrize("S", [256, 512, 1024])
+@pytest.mark.parametrize("tcmode", ["barrier", "lds_atomic"])
+def test_parity_elems_per_thread(ept, S, tcmode):
+    """Several edges per lane: every slot of the block is still computed
+    once, with the same colour rounds."""
+    m, ref = mesh(200, 100)
+    print(f"ept={ept} S={S} {tcmode}", flush=True)
+    L, p, (r,) = gpu_res(m, "rcm+partition", "hier", S, tcmode=tcmode, elems_per_thread=ept)
+    assert rel_l2(r, ref) <= TOL
+
+
 def test_lds_fallback_runs():
     m, ref = mesh(200, 100)
     L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition", block_size=512)
