@@ -87,6 +87,13 @@ typedef enum { UM_STAGE_ALL = 0, UM_STAGE_INC_ONLY = 1 } um_staging;
  * workgroup barriers (Algorithm 1), or LDS floating-point atomics without
  * thread colours (an extension; order inside a block is not fixed). */
 typedef enum { UM_TC_BARRIER = 0, UM_TC_LDS_ATOMIC = 1 } um_tcmode;
+/* Block colouring (layer 1).  FIRST_FIT: first-fit greedy in block order.
+ * RECOLOUR: after first-fit, one iterated-greedy pass (blocks revisited by
+ * decreasing colour, first-fit again; never more colours) and one balancing
+ * pass (in block order a block moves to the least used colour none of its
+ * neighbours holds when that class is smaller by two or more); fewer and
+ * more even launches. */
+typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1 } um_bcolouring;
 
 /* Elemental kernels compiled into the library (no run-time code generation).
  *
@@ -154,7 +161,12 @@ typedef struct {
                                   (0 means 1); the workgroup has
                                   ceil(block_size / elems_per_thread) lanes
                                   rounded up to a multiple of 64             */
-    int32_t reserved[4];
+    int32_t explicit_lists;    /* HIER: 0 = a block whose staged points form
+                                  at most 32 runs of consecutive ids finds
+                                  them from the runs (no index loads); 1 =
+                                  every block reads its explicit id list     */
+    int32_t block_colouring;   /* HIER: um_bcolouring                        */
+    int32_t reserved[2];
 } um_plan_opts;
 
 typedef struct {
@@ -192,7 +204,13 @@ typedef enum {
     UM_EXP_STAGED_POINTS_B = 8,
     UM_EXP_LOCAL_INDEX = 9,     /* int32[n_elements][4]: per slot, local staged index
                                    of (B slot 0, B slot 1, A slot 0, A slot 1)        */
-    UM_EXP_BLOCK_ORDER = 10     /* int32[n_blocks]: block id at each launch position  */
+    UM_EXP_BLOCK_ORDER = 10,    /* int32[n_blocks]: block id at each launch position  */
+    UM_EXP_RUN_OFFSETS_A = 11,  /* int32[n_blocks+1]: run descriptors per block of the
+                                   first indirect map's staged list, block id order;
+                                   a block with none reads its explicit list        */
+    UM_EXP_RUNS_A = 12,         /* int32[...][2]: (first point id, staged position)  */
+    UM_EXP_RUN_OFFSETS_B = 13,  /* as above for the INC map                          */
+    UM_EXP_RUNS_B = 14
 } um_export_field;
 
 /* ---------------------------------------------------------------- context */

@@ -141,6 +141,66 @@ def first_fit_blocks(block_off, writes, max_colours: int = 1 << 20):
                             int(w.max()) + 1 if w.size else 0, max_colours)
 
 
+def first_fit_blocks_in_order(block_off, writes, order):
+    """First-fit colours of blocks visited in `order` (block ids)."""
+    off = np.asarray(block_off, np.int64); w = np.asarray(writes, np.int64)
+    k = w.shape[1]
+    sizes = np.diff(off)[order]
+    off2 = np.zeros(len(order) + 1, np.int64)
+    off2[1:] = np.cumsum(sizes)
+    pts = np.concatenate([w[off[b]:off[b + 1]].ravel() for b in order]) if len(order) else np.zeros(0)
+    c, nc = native.first_fit(off2 * k, pts.astype(np.int32), int(w.max()) + 1 if w.size else 0)
+    col = np.empty(len(order), np.int32)
+    col[np.asarray(order)] = c
+    return col, nc
+
+
+def block_neighbours(block_off, writes):
+    """Per block, the set of other blocks writing one of its points."""
+    off = np.asarray(block_off, np.int64); w = np.asarray(writes, np.int64)
+    nb = off.shape[0] - 1
+    writers = {}
+    for b in range(nb):
+        for p in np.unique(w[off[b]:off[b + 1]]):
+            writers.setdefault(int(p), []).append(b)
+    nbrs = [set() for _ in range(nb)]
+    for bl in writers.values():
+        for b in bl:
+            nbrs[b].update(bl)
+    for b in range(nb):
+        nbrs[b].discard(b)
+    return nbrs
+
+
+def recolour_blocks(block_off, writes):
+    """Block colours after first-fit, one iterated-greedy pass and one
+    balancing pass (the library's RECOLOUR option):
+      1. first-fit in block order;
+      2. first-fit again visiting blocks by decreasing colour of step 1,
+         ties by block id (Culberson's iterated greedy: never more colours);
+      3. in block order, a block moves to the least used colour (lowest on
+         ties) that none of its neighbours holds, if that colour's class is
+         at least two smaller than the block's current class."""
+    nb = len(block_off) - 1
+    c1, _ = first_fit_blocks(block_off, writes)
+    order = sorted(range(nb), key=lambda b: (-int(c1[b]), b))
+    col, nc = first_fit_blocks_in_order(block_off, writes, order)
+    nbrs = block_neighbours(block_off, writes)
+    count = np.bincount(col, minlength=nc).astype(np.int64)
+    for b in range(nb):
+        taken = {int(col[x]) for x in nbrs[b]}
+        cur = int(col[b])
+        best = cur
+        for k in range(nc):
+            if k not in taken and count[k] < count[best]:
+                best = k
+        if best != cur and count[best] + 1 < count[cur]:
+            count[cur] -= 1
+            count[best] += 1
+            col[b] = best
+    return col, nc
+
+
 def first_fit_threads(block_off, writes):
     """Per block, first-fit colours of its elements in element order."""
     off = np.asarray(block_off, np.int64); w = np.asarray(writes, np.int64)

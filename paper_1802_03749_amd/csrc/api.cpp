@@ -76,7 +76,7 @@ T *upload(const std::vector<T> &v, int64_t &bytes) {
 }
 
 void free_device_plan(Plan &p) {
-    void *bufs[5] = {p.dp.emap, p.dp.binfo, p.dp.stg_c, p.dp.stg_n, p.dp.loc};
+    void *bufs[7] = {p.dp.emap, p.dp.binfo, p.dp.stg_c, p.dp.stg_n, p.dp.loc, p.dp.crun, p.dp.nrun};
     for (void *b : bufs)
         if (b) hipFree(b);
     p.dp = DevicePlan{};
@@ -147,6 +147,8 @@ LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *str
     la.binfo = p.dp.binfo;
     la.stg_c = p.dp.stg_c;
     la.stg_n = p.dp.stg_n;
+    la.crun = p.dp.crun;
+    la.nrun = p.dp.nrun;
     la.loc = p.dp.loc;
     la.emap = p.dp.emap;
     const Dat &x = ctx.dats[p.ea.dat_x], &q = ctx.dats[p.ea.dat_q];
@@ -397,6 +399,8 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
         if (o.elems_per_thread != 0 && o.elems_per_thread != 1 && o.elems_per_thread != 2 &&
             o.elems_per_thread != 4)
             fail(UM_ERR_ARG, "elems_per_thread %d not in {1, 2, 4}", o.elems_per_thread);
+        if (o.block_colouring != UM_BCOL_FIRST_FIT && o.block_colouring != UM_BCOL_RECOLOUR)
+            fail(UM_ERR_ARG, "bad block_colouring %d", o.block_colouring);
         const auto t0 = std::chrono::steady_clock::now();
         EdgeArgs ea = check_lf2d_args(c, args, nargs, iter_set);
         auto *p = new um_plan_s();
@@ -413,6 +417,8 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
                 p->dp.binfo = upload(p->hp.binfo, bytes);
                 p->dp.stg_c = upload(p->hp.stg_c, bytes);
                 p->dp.stg_n = upload(p->hp.stg_n, bytes);
+                p->dp.crun = upload(p->hp.crun, bytes);
+                p->dp.nrun = upload(p->hp.nrun, bytes);
                 p->dp.loc = upload(p->hp.loc, bytes);
                 p->dp.bytes = bytes;
                 UM_HIP(hipDeviceSynchronize());
@@ -490,7 +496,31 @@ um_status um_plan_export(um_plan plan, int32_t field, int32_t *host_out, int64_t
                         tmp.push_back(cells ? hp.stg_c[i] : hp.stg_n[i]);
             }
         };
+        auto runs = [&](bool cells, bool offsets) {
+            const int32_t nb = int32_t(hp.blk_order.size());
+            std::vector<int32_t> pos_of(nb);
+            for (int32_t pos = 0; pos < nb; ++pos) pos_of[hp.blk_order[pos]] = pos;
+            const std::vector<Run> &rv = cells ? hp.crun : hp.nrun;
+            tmp.clear();
+            if (offsets) tmp.push_back(0);
+            for (int32_t b = 0; b < nb; ++b) {
+                const BlockInfo &a = hp.binfo[pos_of[b]], &z = hp.binfo[pos_of[b] + 1];
+                const int32_t r0 = cells ? a.crun_off : a.nrun_off;
+                const int32_t r1 = cells ? z.crun_off : z.nrun_off;
+                if (offsets)
+                    tmp.push_back(tmp.back() + (r1 - r0));
+                else
+                    for (int32_t r = r0; r < r1; ++r) {
+                        tmp.push_back(rv[r].start);
+                        tmp.push_back(rv[r].local);
+                    }
+            }
+        };
         switch (field) {
+        case UM_EXP_RUN_OFFSETS_A: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); runs(false, true); break;
+        case UM_EXP_RUNS_A: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); runs(false, false); break;
+        case UM_EXP_RUN_OFFSETS_B: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); runs(true, true); break;
+        case UM_EXP_RUNS_B: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); runs(true, false); break;
         case UM_EXP_BLOCK_OFFSETS: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); v = &hp.blk_off; break;
         case UM_EXP_BLOCK_COLOURS: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); v = &hp.blk_colour; break;
         case UM_EXP_THREAD_COLOURS: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); v = &hp.tcol; break;

@@ -87,7 +87,21 @@ struct BlockInfo {
     int32_t cell_off;   // first staged cell (into stg_c)
     int32_t node_off;   // first staged node (into stg_n)
     int32_t ncol;       // thread colours used by the block
+    int32_t crun_off;   // first run of the staged cells (into crun); a block
+    int32_t nrun_off;   // with no runs reads its explicit list instead
+    int32_t pad0, pad1;
 };
+
+// A run of consecutive staged points: staged positions local, local+1, ...
+// (up to the next run's `local`) hold point ids start, start+1, ...
+struct Run {
+    int32_t start;
+    int32_t local;
+};
+
+// Blocks whose staged list splits into more runs than this read the
+// explicit list.
+constexpr int32_t MAX_RUNS = 32;
 
 struct HostPlan {
     int32_t strategy = 0, staging = 0, tcmode = 0, block_size = 0;
@@ -104,6 +118,8 @@ struct HostPlan {
     std::vector<int32_t> bcol_off;             // [nbcol + 1] launch position ranges
     std::vector<BlockInfo> binfo;              // [nb + 1] launch order (+ sentinel)
     std::vector<int32_t> stg_c, stg_n;         // launch order
+    std::vector<Run> crun, nrun;               // run encoding of stg_c, stg_n
+    int32_t use_runs = 1;
     std::vector<uint32_t> loc;                 // [n_slots][2]: (lL|lR<<16 | col<<11), (nA|nB<<16)
     std::vector<int32_t> slot_elem;            // slot -> element
     std::vector<int32_t> tcol;                 // element -> thread colour
@@ -124,6 +140,7 @@ struct DevicePlan {
     int32_t *emap = nullptr;                   // int4 per slot
     BlockInfo *binfo = nullptr;
     int32_t *stg_c = nullptr, *stg_n = nullptr;
+    Run *crun = nullptr, *nrun = nullptr;
     uint32_t *loc = nullptr;
     int64_t bytes = 0;
 };

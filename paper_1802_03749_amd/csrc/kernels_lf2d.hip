@@ -162,12 +162,28 @@ __device__ __forceinline__ void put_cell(double *s_inc, double *s_q, double *s_a
     }
 }
 
+// Point id at staged position t of a block: from the block's run
+// descriptors (uniform, scalar loads) when it has any, else from its explicit
+// list.  Runs are ordered by `local`, the first one starts at 0.
+__device__ __forceinline__ int32_t staged_id(const Run *__restrict__ runs, int r0, int nr,
+                                             const int32_t *__restrict__ list, int t) {
+    if (nr == 0) return list[t];
+    int32_t g = runs[r0].start + t;
+    for (int r = 1; r < nr; ++r) {
+        const Run R = runs[r0 + r];
+        if (t >= R.local) g = R.start + (t - R.local);
+    }
+    return g;
+}
+
 // EPT = elements (edges) per lane: the workgroup has T lanes and handles a
 // block of up to EPT*T edges; lane l computes slots l, l+T, ...
 template <int LAYOUT, int STAGING, int TCMODE, int EPT>
 __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict__ binfo,
                                                     const int32_t *__restrict__ stg_c,
                                                     const int32_t *__restrict__ stg_n,
+                                                    const Run *__restrict__ crun,
+                                                    const Run *__restrict__ nrun,
                                                     const uint2 *__restrict__ loc, Dats d,
                                                     double gm1, double eps, int32_t base) {
     extern __shared__ double lds[];
@@ -176,8 +192,11 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
     const int ne = bn.slot_off - bi.slot_off;
     const int nc = bn.cell_off - bi.cell_off;
     const int nn = bn.node_off - bi.node_off;
+    const int ncr = bn.crun_off - bi.crun_off, nnr = bn.nrun_off - bi.nrun_off;
     const int32_t *__restrict__ sc = stg_c + bi.cell_off;
     const int32_t *__restrict__ sn = stg_n + bi.node_off;
+    auto cell_id = [&](int t) { return staged_id(crun, bi.crun_off, ncr, sc, t); };
+    auto node_id = [&](int t) { return staged_id(nrun, bi.nrun_off, nnr, sn, t); };
     double *s_inc = lds;            // [4][nc] increment accumulators
     double *s_q = s_inc + 4 * nc;   // [4][nc]
     double *s_adt = s_q + 4 * nc;   // [nc]
@@ -198,8 +217,8 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
     for (int t0 = tid; t0 < nc; t0 += 2 * T) {
         const int t1 = t0 + T;
         const bool has1 = t1 < nc;
-        const int64_t g0 = sc[t0];
-        const int64_t g1 = has1 ? sc[t1] : g0;
+        const int64_t g0 = cell_id(t0);
+        const int64_t g1 = has1 ? cell_id(t1) : g0;
         CellRegs c0, c1;
         fetch_cell<LAYOUT, STAGING>(d, g0, c0);
         fetch_cell<LAYOUT, STAGING>(d, g1, c1);
@@ -210,8 +229,8 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
         for (int t0 = tid; t0 < nn; t0 += 2 * T) {
             const int t1 = t0 + T;
             const bool has1 = t1 < nn;
-            const int64_t g0 = sn[t0];
-            const int64_t g1 = has1 ? sn[t1] : g0;
+            const int64_t g0 = node_id(t0);
+            const int64_t g1 = has1 ? node_id(t1) : g0;
             double a0, a1, b0, b1;
             load2<LAYOUT>(d.x, d.N, g0, a0, a1);
             load2<LAYOUT>(d.x, d.N, g1, b0, b1);
@@ -247,7 +266,8 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
                 lf2d_flux(s_x[nA], s_x[nn + nA], s_x[nB], s_x[nn + nB], qL, qR, s_adt[lL[j]],
                           s_adt[lR[j]], gm1, eps, f[j]);
             } else {
-                edge_flux_global<LAYOUT>(d, sc[lL[j]], sc[lR[j]], sn[nA], sn[nB], gm1, eps, f[j]);
+                edge_flux_global<LAYOUT>(d, cell_id(lL[j]), cell_id(lR[j]), node_id(nA),
+                                         node_id(nB), gm1, eps, f[j]);
             }
         }
     }
@@ -290,7 +310,7 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
         double r[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) r[k] = s_inc[k * nc + t];
-        store4<LAYOUT>(d.res, d.C, sc[t], r);
+        store4<LAYOUT>(d.res, d.C, cell_id(t), r);
     }
 }
 
@@ -369,15 +389,18 @@ hipError_t launch_hier_ept(const LaunchArgs &la, int32_t nblocks, int32_t base, 
     switch (la.ept) {
     case 1:
         hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, 1>), grid, block, size_t(lds), la.stream,
-                           la.binfo, la.stg_c, la.stg_n, loc, d, la.gm1, la.eps, base);
+                           la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun, loc, d, la.gm1,
+                           la.eps, base);
         break;
     case 2:
         hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, 2>), grid, block, size_t(lds), la.stream,
-                           la.binfo, la.stg_c, la.stg_n, loc, d, la.gm1, la.eps, base);
+                           la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun, loc, d, la.gm1,
+                           la.eps, base);
         break;
     case 4:
         hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, 4>), grid, block, size_t(lds), la.stream,
-                           la.binfo, la.stg_c, la.stg_n, loc, d, la.gm1, la.eps, base);
+                           la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun, loc, d, la.gm1,
+                           la.eps, base);
         break;
     default:
         return hipErrorInvalidValue;

@@ -14,6 +14,7 @@ struct LaunchArgs {
     int32_t layout, staging, tcmode, block_size, ept;
     const BlockInfo *binfo;
     const int32_t *stg_c, *stg_n;
+    const Run *crun, *nrun;
     const uint32_t *loc;
     const int32_t *emap;
     const double *x, *q, *adt;

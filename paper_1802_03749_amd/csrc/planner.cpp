@@ -141,24 +141,72 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
                     }
                 }
     }
+    // block adjacency: blocks sharing a written cell
+    std::vector<int64_t> adj_off(nb + 1, 0);
+    std::vector<int32_t> adj;
+    {
+        std::vector<int32_t> nbrs;
+        for (int32_t b = 0; b < nb; ++b) {
+            nbrs.clear();
+            for (int32_t e = hp.blk_off[b]; e < hp.blk_off[b + 1]; ++e)
+                for (int s = 0; s < 2; ++s) {
+                    const int32_t c = mc.table[2 * int64_t(e) + s];
+                    for (int64_t i = cb_off[c]; i < cb_off[c + 1]; ++i)
+                        if (cb[i] != b) nbrs.push_back(cb[i]);
+                }
+            std::sort(nbrs.begin(), nbrs.end());
+            nbrs.erase(std::unique(nbrs.begin(), nbrs.end()), nbrs.end());
+            adj.insert(adj.end(), nbrs.begin(), nbrs.end());
+            adj_off[b + 1] = int64_t(adj.size());
+        }
+    }
     const int32_t maxcol = o.max_block_colours > 0 ? o.max_block_colours : 256;
-    hp.blk_colour.assign(nb, -1);
     std::vector<int32_t> stamp(maxcol + 1, -1);
-    int32_t nbcol = 0;
-    for (int32_t b = 0; b < nb; ++b) {
-        for (int32_t e = hp.blk_off[b]; e < hp.blk_off[b + 1]; ++e)
-            for (int s = 0; s < 2; ++s) {
-                int32_t c = mc.table[2 * int64_t(e) + s];
-                for (int64_t i = cb_off[c]; i < cb_off[c + 1] && cb[i] < b; ++i)
-                    stamp[hp.blk_colour[cb[i]]] = b;
+    // first-fit over blocks visited in `order`
+    auto first_fit = [&](const std::vector<int32_t> &order, std::vector<int32_t> &col) {
+        col.assign(nb, -1);
+        std::fill(stamp.begin(), stamp.end(), -1);
+        int32_t ncol = 0;
+        for (int32_t b : order) {
+            for (int64_t i = adj_off[b]; i < adj_off[b + 1]; ++i)
+                if (col[adj[i]] >= 0) stamp[col[adj[i]]] = b;
+            int32_t c = 0;
+            while (c < maxcol && stamp[c] == b) ++c;
+            if (c >= maxcol)
+                fail(UM_ERR_COLOURS, "block colouring needs more than %d colours (block %d of %d)",
+                     maxcol, b, nb);
+            col[b] = c;
+            ncol = std::max(ncol, c + 1);
+        }
+        return ncol;
+    };
+    std::vector<int32_t> order(nb);
+    std::iota(order.begin(), order.end(), 0);
+    int32_t nbcol = first_fit(order, hp.blk_colour);
+    if (o.block_colouring == UM_BCOL_RECOLOUR && nb > 0) {
+        // one iterated-greedy pass: colour classes revisited from the last to
+        // the first (ties by block id) never need more colours
+        std::vector<int32_t> prev = hp.blk_colour;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t x, int32_t y) { return prev[x] > prev[y]; });
+        nbcol = first_fit(order, hp.blk_colour);
+        // balancing: in block order, move a block to the least used colour
+        // none of its neighbours holds, if that class is smaller by two or more
+        std::vector<int64_t> count(nbcol, 0);
+        for (int32_t c : hp.blk_colour) count[c]++;
+        for (int32_t b = 0; b < nb; ++b) {
+            for (int64_t i = adj_off[b]; i < adj_off[b + 1]; ++i) stamp[hp.blk_colour[adj[i]]] = nb + b;
+            const int32_t c = hp.blk_colour[b];
+            int32_t best = c;
+            for (int32_t k = 0; k < nbcol; ++k)
+                if (stamp[k] != nb + b && count[k] < count[best]) best = k;
+            if (best != c && count[best] + 1 < count[c]) {
+                count[c]--;
+                count[best]++;
+                hp.blk_colour[b] = best;
             }
-        int32_t col = 0;
-        while (col < maxcol && stamp[col] == b) ++col;
-        if (col >= maxcol)
-            fail(UM_ERR_COLOURS, "block colouring needs more than %d colours (block %d of %d)",
-                 maxcol, b, nb);
-        hp.blk_colour[b] = col;
-        nbcol = std::max(nbcol, col + 1);
+        }
+        std::fill(stamp.begin(), stamp.end(), -1);
     }
     hp.blk_order = counting_order(hp.blk_colour, nbcol, hp.bcol_off);
 
@@ -170,9 +218,12 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     hp.tcol.assign(E, 0);
     hp.stg_c.clear();
     hp.stg_n.clear();
+    hp.crun.clear();
+    hp.nrun.clear();
+    hp.use_runs = o.explicit_lists == 0;
     hp.lds_per_colour.assign(nbcol, 0);
     std::vector<int64_t> lds_all(nb);
-    std::vector<int32_t> mask, ecol, order, goff;
+    std::vector<int32_t> mask, ecol, goff;
     int64_t slot = 0, tcol_sum = 0;
     hp.max_tcol = 0;
     for (int32_t pos = 0; pos < nb; ++pos) {
@@ -216,6 +267,21 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
             ncol = std::max(ncol, c + 1);
         }
         bi.ncol = ncol;
+        // run encoding of the staged lists (sorted, so runs are maximal)
+        auto encode = [&](const std::vector<int32_t> &lst, size_t first, size_t n,
+                          std::vector<Run> &runs, int32_t &off) {
+            off = int32_t(runs.size());
+            if (!hp.use_runs) return;
+            int32_t nr = 0;
+            for (size_t i = 0; i < n; ++i)
+                if (i == 0 || lst[first + i] != lst[first + i - 1] + 1) ++nr;
+            if (nr > MAX_RUNS) return;
+            for (size_t i = 0; i < n; ++i)
+                if (i == 0 || lst[first + i] != lst[first + i - 1] + 1)
+                    runs.push_back(Run{lst[first + i], int32_t(i)});
+        };
+        encode(hp.stg_c, c0, nc, hp.crun, bi.crun_off);
+        encode(hp.stg_n, n0, nn, hp.nrun, bi.nrun_off);
         tcol_sum += ncol;
         hp.max_tcol = std::max(hp.max_tcol, ncol);
         // slots: the block's edges sorted by colour, stable
@@ -235,7 +301,8 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
         for (int32_t i = 0; i < nn; ++i) nloc[hp.stg_n[n0 + i]] = -1;
         lds_all[pos] = lf2d_lds_bytes(UM_STAGE_ALL, ea.dtype, nc, nn);
     }
-    hp.binfo[nb] = BlockInfo{int32_t(slot), int32_t(hp.stg_c.size()), int32_t(hp.stg_n.size()), 0};
+    hp.binfo[nb] = BlockInfo{int32_t(slot), int32_t(hp.stg_c.size()), int32_t(hp.stg_n.size()), 0,
+                             int32_t(hp.crun.size()), int32_t(hp.nrun.size()), 0, 0};
 
     // ---- LDS sizing, with the increments-only fallback
     const int64_t limit = o.lds_limit_bytes > 0 ? o.lds_limit_bytes : ctx.lds_limit;

@@ -29,11 +29,13 @@ UM_STRAT_ATOMIC, UM_STRAT_GLOBAL_COLOUR, UM_STRAT_HIER = 0, 1, 2
 UM_REORDER_NONE, UM_REORDER_RCM, UM_REORDER_GPS, UM_REORDER_PARTITION = 0, 1, 2, 3
 UM_STAGE_ALL, UM_STAGE_INC_ONLY = 0, 1
 UM_TC_BARRIER, UM_TC_LDS_ATOMIC = 0, 1
+UM_BCOL_FIRST_FIT, UM_BCOL_RECOLOUR = 0, 1
 UM_K_EDGE_FLUX_LF2D = 0
 (UM_EXP_BLOCK_OFFSETS, UM_EXP_BLOCK_COLOURS, UM_EXP_THREAD_COLOURS, UM_EXP_SLOT_ELEMENTS,
  UM_EXP_GLOBAL_COLOURS, UM_EXP_STAGED_OFFSETS_A, UM_EXP_STAGED_POINTS_A,
  UM_EXP_STAGED_OFFSETS_B, UM_EXP_STAGED_POINTS_B, UM_EXP_LOCAL_INDEX,
- UM_EXP_BLOCK_ORDER) = range(11)
+ UM_EXP_BLOCK_ORDER, UM_EXP_RUN_OFFSETS_A, UM_EXP_RUNS_A, UM_EXP_RUN_OFFSETS_B,
+ UM_EXP_RUNS_B) = range(15)
 
 STATUS_NAMES = {0: "UM_OK", -1: "UM_ERR_ARG", -2: "UM_ERR_RANGE", -3: "UM_ERR_ARITY",
                 -4: "UM_ERR_COLOURS", -5: "UM_ERR_LDS", -6: "UM_ERR_HIP", -7: "UM_ERR_STATE",
@@ -61,7 +63,8 @@ class um_plan_opts(ct.Structure):
     _fields_ = [("strategy", ct.c_int32), ("block_size", ct.c_int32), ("staging", ct.c_int32),
                 ("tcmode", ct.c_int32), ("max_block_colours", ct.c_int32),
                 ("lds_limit_bytes", ct.c_int32), ("allow_fallback", ct.c_int32),
-                ("elems_per_thread", ct.c_int32), ("reserved", ct.c_int32 * 4)]
+                ("elems_per_thread", ct.c_int32), ("explicit_lists", ct.c_int32),
+                ("block_colouring", ct.c_int32), ("reserved", ct.c_int32 * 2)]
 
 
 class um_plan_stats(ct.Structure):

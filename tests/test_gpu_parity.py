@@ -98,6 +98,23 @@ def test_parity_elems_per_thread(ept, S, tcmode):
     assert rel_l2(r, ref) <= TOL
 
 
+@pytest.mark.parametrize("order", ["rcm", "rcm+partition", "none"])
+@pytest.mark.parametrize("explicit", [False, True])
+def test_parity_staged_lists(order, explicit):
+    """Run-encoded and explicit staged lists give the same residual."""
+    m, ref = mesh(200, 100)
+    L, p, (r,) = gpu_res(m, order, "hier", 512, explicit_lists=explicit,
+                         max_block_colours=1 << 20)
+    assert rel_l2(r, ref) <= TOL
+
+
+@pytest.mark.parametrize("S", [256, 512])
+def test_parity_recolour(S):
+    m, ref = mesh(200, 100)
+    L, p, (r,) = gpu_res(m, "rcm+partition", "hier", S, block_colouring="recolour")
+    assert rel_l2(r, ref) <= TOL
+
+
 def test_lds_fallback_runs():
     m, ref = mesh(200, 100)
     L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition", block_size=512)

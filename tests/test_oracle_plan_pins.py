@@ -152,3 +152,29 @@ def test_signature_order_hand_example():
     # accessing blocks: 0:{0,1} 1:{0} 2:{0,1} 3:{1} 4:{1} 5:{}
     order = plans.signature_order(blk, [t], 6)
     assert order.tolist() == [1, 3, 4, 0, 2, 5]
+
+
+def test_recolour_hand_example():
+    """Path of 6 blocks b0-b1-...-b5 (neighbours share one point).  First-fit
+    in block order gives 0,1,0,1,0,1.  Revisiting colour 1 first (b1, b3, b5)
+    then colour 0 reproduces the same 2-colouring with colours swapped:
+    b1,b3,b5 -> 0 and b0,b2,b4 -> 1; counts are equal so nothing moves."""
+    w = np.array([[i, i + 1] for i in range(6)])
+    off = np.arange(7)
+    col, nc = plans.recolour_blocks(off, w)
+    assert nc == 2 and col.tolist() == [1, 0, 1, 0, 1, 0]
+
+
+def test_recolour_balances_a_star():
+    """Star: centre block 0 touches blocks 1..4, which are mutually
+    independent.  First-fit: 0,1,1,1,1.  Iterated pass (colour 1 first):
+    blocks 1..4 -> 0, block 0 -> 1.  Balance: counts are (4, 1) and no leaf
+    can move (its only neighbour holds colour 1), so the result stays."""
+    w = np.array([[0, 1], [1, 10], [2, 11], [3, 12], [4, 13]])
+    # block 0 = element 0..0 writes points {0,1,2,3,4} via a wide element
+    w = np.array([[0, 1, 2, 3, 4], [0, 20, 21, 22, 23], [1, 24, 25, 26, 27],
+                  [2, 28, 29, 30, 31], [3, 32, 33, 34, 35]])
+    off = np.arange(6)
+    col, nc = plans.recolour_blocks(off, w)
+    assert nc == 2 and col.tolist() == [1, 0, 0, 0, 0]
+    assert plans.check_block_colouring(off, col, w)

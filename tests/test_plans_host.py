@@ -256,3 +256,53 @@ def test_degenerate_meshes_plan(nx, ny):
     for strat in ("atomic", "global", "hier"):
         p = L.plan(strat, 64)
         assert p.stats["n_elements"] == L.E
+
+
+@pytest.mark.parametrize("order", ["rcm", "rcm+partition", "none"])
+def test_run_encoding_decodes_to_staged_lists(order):
+    """Run descriptors, decoded the way the kernel does (last run whose
+    staged position is <= t), reproduce every block's sorted staged list;
+    blocks with more than 32 runs carry none (explicit list)."""
+    m, L = make(nx=48, ny=30, order=order, block_size=256)
+    p = L.plan("hier", 256, max_block_colours=1 << 20)
+    for fo, fp, ro, rp in [(U.UM_EXP_STAGED_OFFSETS_B, U.UM_EXP_STAGED_POINTS_B,
+                            U.UM_EXP_RUN_OFFSETS_B, U.UM_EXP_RUNS_B),
+                           (U.UM_EXP_STAGED_OFFSETS_A, U.UM_EXP_STAGED_POINTS_A,
+                            U.UM_EXP_RUN_OFFSETS_A, U.UM_EXP_RUNS_A)]:
+        so, sp = L.export(p, fo), L.export(p, fp)
+        roff, runs = L.export(p, ro), L.export(p, rp).reshape(-1, 2)
+        n_with_runs = 0
+        for b in range(len(so) - 1):
+            lst = sp[so[b]:so[b + 1]]
+            nruns_true = 1 + int(np.sum(np.diff(lst) != 1))
+            r = runs[roff[b]:roff[b + 1]]
+            if len(r) == 0:
+                assert nruns_true > 32
+                continue
+            n_with_runs += 1
+            assert len(r) == nruns_true and r[0, 1] == 0
+            dec = np.empty_like(lst)
+            for t in range(len(lst)):
+                k = np.nonzero(r[:, 1] <= t)[0][-1]
+                dec[t] = r[k, 0] + (t - r[k, 1])
+            assert np.array_equal(dec, lst)
+        if order != "none":
+            assert n_with_runs == len(so) - 1
+    q = L.plan("hier", 256, max_block_colours=1 << 20, explicit_lists=True)
+    assert len(L.export(q, U.UM_EXP_RUNS_B)) == 0
+
+
+@pytest.mark.parametrize("S", [128, 512])
+def test_recolour_matches_oracle(S):
+    m, L = make(nx=60, ny=40, order="rcm+partition", block_size=S)
+    p = L.plan("hier", S, block_colouring="recolour")
+    q = L.plan("hier", S)
+    off = L.export(p, U.UM_EXP_BLOCK_OFFSETS)
+    e2c = L.current_map("e2c")
+    bcol = L.export(p, U.UM_EXP_BLOCK_COLOURS)
+    assert P.check_block_colouring(off, bcol, e2c)
+    ref, nc = P.recolour_blocks(off, e2c)
+    assert np.array_equal(bcol, ref)
+    assert p.stats["n_block_colours"] == nc <= q.stats["n_block_colours"]
+    counts = np.bincount(bcol)
+    assert counts.max() - counts.min() <= np.bincount(L.export(q, U.UM_EXP_BLOCK_COLOURS)).max()
