@@ -109,8 +109,10 @@ typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1 } um_bcolouring;
  *   5: adt dim 1 via edge->cell map slot 1, UM_READ
  *   6: res dim 4 via edge->cell map slot 0, UM_INC
  *   7: res dim 4 via edge->cell map slot 1, UM_INC
- * Both maps have arity 2 and the iteration set as from-set; x, q, adt and
- * res are UM_F64 (or x, q, adt UM_F32 with res UM_F64 once provided).
+ * Both maps have arity 2 and the iteration set as from-set; res is UM_F64;
+ * x, q and adt are all UM_F64, or all UM_F32 (the flux is then evaluated in
+ * FP32 and each increment is accumulated into the FP64 residual without
+ * further rounding of the FP32 value).  One layout for all four dats.
  * params = {gm1, eps}.  Per edge, with n = (y_b - y_a, x_a - x_b):
  *   per side s: ri = 1/q0, u = q1 ri, v = q2 ri,
  *               p = gm1 (q3 - 0.5 (q1 u + q2 v)), U = u n_x + v n_y,
@@ -157,7 +159,7 @@ typedef struct {
                                   limit (163840 on gfx950; 65536 host-only)  */
     int32_t allow_fallback;    /* HIER: 1 = STAGE_ALL over the LDS limit falls
                                   back to STAGE_INC_ONLY instead of failing  */
-    int32_t elems_per_thread;  /* HIER: elements each lane computes, 1, 2 or 4
+    int32_t elems_per_thread;  /* HIER: elements each lane computes, 1 or 2
                                   (0 means 1); the workgroup has
                                   ceil(block_size / elems_per_thread) lanes
                                   rounded up to a multiple of 64             */

@@ -145,3 +145,57 @@ int32_t oracle_first_fit(int64_t n, const int64_t *off, const int32_t *pts,
     }
     return ncol;
 }
+
+/*
+ * Binary32 evaluation of the same flux (test infrastructure for the FP32
+ * storage variant): inputs are binary32, every operation is one correctly
+ * rounded binary32 operation in the order of oracle_lf2d_flux, gm1 is the
+ * binary32 value nearest the binary64 gm1.  The loop accumulates each
+ * binary32 flux, converted exactly to binary64, into a binary64 residual.
+ */
+static void oracle_side_flux_f32(const float *q, float nx, float ny, float gm1, float F[4])
+{
+    float ri = 1.0f / q[0];
+    float u = q[1] * ri;
+    float v = q[2] * ri;
+    float p = gm1 * (q[3] - 0.5f * (q[1] * u + q[2] * v));
+    float U = u * nx + v * ny;
+    F[0] = q[0] * U;
+    F[1] = q[1] * U + p * nx;
+    F[2] = q[2] * U + p * ny;
+    F[3] = (q[3] + p) * U;
+}
+
+void oracle_lf2d_flux_f32(const float *xa, const float *xb, const float *qL, const float *qR,
+                          float adtL, float adtR, float gm1, float eps, float *f)
+{
+    float nx = xb[1] - xa[1];
+    float ny = xa[0] - xb[0];
+    float FL[4], FR[4];
+    oracle_side_flux_f32(qL, nx, ny, gm1, FL);
+    oracle_side_flux_f32(qR, nx, ny, gm1, FR);
+    float mu = eps * 0.5f * (adtL + adtR);
+    for (int k = 0; k < 4; ++k)
+        f[k] = 0.5f * (FL[k] + FR[k]) + 0.5f * mu * (qL[k] - qR[k]);
+}
+
+void oracle_edge_loop_f32(int64_t E, const int32_t *e2n, const int32_t *e2c, const float *x,
+                          const float *q, const float *adt, double gm1, double eps, double *res,
+                          double *f_out)
+{
+    const float g = (float)gm1, ep = (float)eps;
+    for (int64_t e = 0; e < E; ++e) {
+        int32_t a = e2n[2 * e], b = e2n[2 * e + 1];
+        int32_t L = e2c[2 * e], R = e2c[2 * e + 1];
+        float f[4];
+        oracle_lf2d_flux_f32(x + 2 * (int64_t)a, x + 2 * (int64_t)b, q + 4 * (int64_t)L,
+                             q + 4 * (int64_t)R, adt[L], adt[R], g, ep, f);
+        for (int k = 0; k < 4; ++k) {
+            if (res) {
+                res[4 * (int64_t)L + k] += (double)f[k];
+                res[4 * (int64_t)R + k] -= (double)f[k];
+            }
+            if (f_out) f_out[4 * e + k] = (double)f[k];
+        }
+    }
+}

@@ -29,6 +29,9 @@ def lib():
         L.oracle_edge_loop.restype = None
         L.oracle_edge_fluxes.argtypes = L.oracle_edge_loop.argtypes
         L.oracle_edge_fluxes.restype = None
+        L.oracle_edge_loop_f32.argtypes = [ct.c_int64, P, P, P, P, P, ct.c_double,
+                                           ct.c_double, P, P]
+        L.oracle_edge_loop_f32.restype = None
         L.oracle_first_fit.argtypes = [ct.c_int64, P, P, ct.c_int64, ct.c_int32,
                                        P, P, P, P, P]
         L.oracle_first_fit.restype = ct.c_int32
@@ -93,3 +96,16 @@ def first_fit(off, pts, npts: int, max_colours: int = 1 << 20):
     if nc < 0:
         return None, -1
     return colour, int(nc)
+
+
+def edge_loop_f32(e2n, e2c, x, q, adt, gm1=GM1, eps=EPS_D):
+    """Binary32 flux evaluation, binary64 accumulation: (res[C][4], f[E][4]).
+
+    x, q, adt are rounded to binary32 (round to nearest even) first."""
+    e2n = _c(e2n, np.int32); e2c = _c(e2c, np.int32)
+    x = _c(x, np.float32); q = _c(q, np.float32); adt = _c(adt, np.float32)
+    res = np.zeros((q.shape[0], 4))
+    f = np.zeros((e2n.shape[0], 4))
+    lib().oracle_edge_loop_f32(e2n.shape[0], _p(e2n), _p(e2c), _p(x), _p(q), _p(adt),
+                               float(gm1), float(eps), _p(res), _p(f))
+    return res, f

@@ -122,14 +122,14 @@ EdgeArgs check_lf2d_args(const Ctx &ctx, const um_arg *args, int32_t nargs, int3
     if (ea.map_n == ea.map_c) fail(UM_ERR_ARITY, "x must use the edge->node map");
     const int ids[4] = {ea.dat_x, ea.dat_q, ea.dat_adt, ea.dat_res};
     ea.layout = ctx.dats[ea.dat_q].layout;
-    for (int id : ids) {
-        const Dat &d = ctx.dats[id];
-        if (d.dtype != UM_F64)
-            fail(UM_ERR_UNSUPPORTED, "edge flux kernel: only UM_F64 dats are provided");
-        if (d.layout != ea.layout)
+    ea.dtype = ctx.dats[ea.dat_q].dtype;
+    for (int id : ids)
+        if (ctx.dats[id].layout != ea.layout)
             fail(UM_ERR_UNSUPPORTED, "edge flux kernel: x, q, adt and res must share one layout");
-    }
-    ea.dtype = UM_F64;
+    if (ctx.dats[ea.dat_x].dtype != ea.dtype || ctx.dats[ea.dat_adt].dtype != ea.dtype)
+        fail(UM_ERR_UNSUPPORTED, "edge flux kernel: x, q and adt must share one dtype");
+    if (ctx.dats[ea.dat_res].dtype != UM_F64)
+        fail(UM_ERR_UNSUPPORTED, "edge flux kernel: res must be UM_F64");
     return ea;
 }
 
@@ -156,9 +156,10 @@ LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *str
     const int64_t E = ctx.sets[p.iter_set].size;
     if (E > 0 && (!x.ptr || !q.ptr || !adt.ptr || !res.ptr))
         fail(UM_ERR_STATE, "a dat of the loop has no device memory");
-    la.x = static_cast<const double *>(x.ptr);
-    la.q = static_cast<const double *>(q.ptr);
-    la.adt = static_cast<const double *>(adt.ptr);
+    la.dtype = p.ea.dtype;
+    la.x = x.ptr;
+    la.q = q.ptr;
+    la.adt = adt.ptr;
     la.res = static_cast<double *>(res.ptr);
     la.N = ctx.sets[x.set].size;
     la.C = ctx.sets[q.set].size;
@@ -396,9 +397,8 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
         if (o.tcmode != UM_TC_BARRIER && o.tcmode != UM_TC_LDS_ATOMIC)
             fail(UM_ERR_ARG, "bad tcmode %d", o.tcmode);
         if (o.max_block_colours < 0 || o.lds_limit_bytes < 0) fail(UM_ERR_ARG, "negative limit");
-        if (o.elems_per_thread != 0 && o.elems_per_thread != 1 && o.elems_per_thread != 2 &&
-            o.elems_per_thread != 4)
-            fail(UM_ERR_ARG, "elems_per_thread %d not in {1, 2, 4}", o.elems_per_thread);
+        if (o.elems_per_thread != 0 && o.elems_per_thread != 1 && o.elems_per_thread != 2)
+            fail(UM_ERR_ARG, "elems_per_thread %d not in {1, 2}", o.elems_per_thread);
         if (o.block_colouring != UM_BCOL_FIRST_FIT && o.block_colouring != UM_BCOL_RECOLOUR)
             fail(UM_ERR_ARG, "bad block_colouring %d", o.block_colouring);
         const auto t0 = std::chrono::steady_clock::now();

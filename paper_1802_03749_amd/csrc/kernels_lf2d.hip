@@ -1,21 +1,25 @@
 // gfx950 kernels of the 2D edge-flux indirect-increment loop.
 //
 //  hier_kernel   two-layer colouring (paper Section 2.2, Algorithm 1): one
-//                workgroup per block, one lane per edge.  The block's staged
-//                cells and nodes are gathered into LDS (structure-of-arrays
-//                inside LDS), the residuals of the staged cells are preloaded
-//                as the increment accumulators, every lane computes its
-//                edge's flux into registers, increments are applied to LDS
-//                one thread colour at a time with a workgroup barrier after
-//                each colour, and the accumulators are stored back once.
-//                Blocks of one block colour write disjoint cells, so a launch
-//                per block colour needs no atomics.
+//                workgroup per block.  The block's staged cells and nodes are
+//                gathered into LDS (structure-of-arrays inside LDS), the
+//                residuals of the staged cells are preloaded as the FP64
+//                increment accumulators, every lane computes its edges'
+//                fluxes into registers, increments are applied to LDS one
+//                thread colour at a time with a workgroup barrier after each
+//                colour, and the accumulators are stored back once.  Blocks
+//                of one block colour write disjoint cells, so a launch per
+//                block colour needs no atomics.
 //  gcol_kernel   global colouring baseline (Section 2.1): one launch per
 //                colour, gather through the int32 maps, plain read-modify-
 //                write of res.
 //  atomic_kernel atomics baseline (Section 2.1): one launch, hardware FP64
 //                atomic adds on res.
 //  debug_kernel  per-edge fluxes with floating-point contraction disabled.
+//
+// Every kernel is a template on the real type of x, q and adt (double, or
+// float for the FP32-storage variant); the flux is evaluated in that type and
+// the residual and its accumulators are always double.
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
@@ -24,61 +28,69 @@
 namespace um {
 namespace {
 
-// Flux through an edge from cell L into cell R (formula in umesh.h).
+// Flux through an edge from cell L into cell R (formula in umesh.h),
+// evaluated in type Real.
 #define UM_LF2D_FLUX_BODY                                                      \
-    const double nx = xb1 - xa1;                                               \
-    const double ny = xa0 - xb0;                                               \
-    double FL[4], FR[4];                                                       \
+    const Real half = Real(0.5), one = Real(1);                                \
+    const Real nx = xb1 - xa1;                                                 \
+    const Real ny = xa0 - xb0;                                                 \
+    Real FL[4], FR[4];                                                         \
     {                                                                          \
-        const double ri = 1.0 / qL[0];                                         \
-        const double u = qL[1] * ri;                                           \
-        const double v = qL[2] * ri;                                           \
-        const double p = gm1 * (qL[3] - 0.5 * (qL[1] * u + qL[2] * v));       \
-        const double U = u * nx + v * ny;                                      \
+        const Real ri = one / qL[0];                                           \
+        const Real u = qL[1] * ri;                                             \
+        const Real v = qL[2] * ri;                                             \
+        const Real p = gm1 * (qL[3] - half * (qL[1] * u + qL[2] * v));         \
+        const Real U = u * nx + v * ny;                                        \
         FL[0] = qL[0] * U;                                                     \
         FL[1] = qL[1] * U + p * nx;                                            \
         FL[2] = qL[2] * U + p * ny;                                            \
         FL[3] = (qL[3] + p) * U;                                               \
     }                                                                          \
     {                                                                          \
-        const double ri = 1.0 / qR[0];                                         \
-        const double u = qR[1] * ri;                                           \
-        const double v = qR[2] * ri;                                           \
-        const double p = gm1 * (qR[3] - 0.5 * (qR[1] * u + qR[2] * v));       \
-        const double U = u * nx + v * ny;                                      \
+        const Real ri = one / qR[0];                                           \
+        const Real u = qR[1] * ri;                                             \
+        const Real v = qR[2] * ri;                                             \
+        const Real p = gm1 * (qR[3] - half * (qR[1] * u + qR[2] * v));         \
+        const Real U = u * nx + v * ny;                                        \
         FR[0] = qR[0] * U;                                                     \
         FR[1] = qR[1] * U + p * nx;                                            \
         FR[2] = qR[2] * U + p * ny;                                            \
         FR[3] = (qR[3] + p) * U;                                               \
     }                                                                          \
-    const double mu = eps * 0.5 * (adtL + adtR);                               \
+    const Real mu = eps * half * (adtL + adtR);                                \
     _Pragma("unroll") for (int k = 0; k < 4; ++k)                              \
-        f[k] = 0.5 * (FL[k] + FR[k]) + 0.5 * mu * (qL[k] - qR[k]);
+        f[k] = half * (FL[k] + FR[k]) + half * mu * (qL[k] - qR[k]);
 
-__device__ __forceinline__ void lf2d_flux(double xa0, double xa1, double xb0, double xb1,
-                                          const double qL[4], const double qR[4], double adtL,
-                                          double adtR, double gm1, double eps, double f[4]) {
+template <typename Real>
+__device__ __forceinline__ void lf2d_flux(Real xa0, Real xa1, Real xb0, Real xb1,
+                                          const Real qL[4], const Real qR[4], Real adtL,
+                                          Real adtR, Real gm1, Real eps, Real f[4]) {
     UM_LF2D_FLUX_BODY
 }
 
-__device__ __forceinline__ void lf2d_flux_nocontract(double xa0, double xa1, double xb0,
-                                                     double xb1, const double qL[4],
-                                                     const double qR[4], double adtL,
-                                                     double adtR, double gm1, double eps,
-                                                     double f[4]) {
+template <typename Real>
+__device__ __forceinline__ void lf2d_flux_nocontract(Real xa0, Real xa1, Real xb0, Real xb1,
+                                                     const Real qL[4], const Real qR[4],
+                                                     Real adtL, Real adtR, Real gm1, Real eps,
+                                                     Real f[4]) {
 #pragma clang fp contract(off)
     UM_LF2D_FLUX_BODY
 }
 
-// Element g of a dim-4 / dim-2 / dim-1 FP64 dat in AoS ([n][dim]) or SoA
-// ([dim][n]) layout.
-template <int LAYOUT>
-__device__ __forceinline__ void load4(const double *__restrict__ a, int64_t n, int64_t g,
-                                      double v[4]) {
+// Element g of a dim-4 / dim-2 dat in AoS ([n][dim]) or SoA ([dim][n])
+// layout; AoS uses 16-byte vector loads.
+template <int LAYOUT, typename Real>
+__device__ __forceinline__ void load4(const Real *__restrict__ a, int64_t n, int64_t g,
+                                      Real v[4]) {
     if constexpr (LAYOUT == UM_AOS) {
-        const double2 *p = reinterpret_cast<const double2 *>(a + 4 * g);
-        const double2 lo = p[0], hi = p[1];
-        v[0] = lo.x; v[1] = lo.y; v[2] = hi.x; v[3] = hi.y;
+        if constexpr (sizeof(Real) == 8) {
+            const double2 *p = reinterpret_cast<const double2 *>(a + 4 * g);
+            const double2 lo = p[0], hi = p[1];
+            v[0] = lo.x; v[1] = lo.y; v[2] = hi.x; v[3] = hi.y;
+        } else {
+            const float4 t = reinterpret_cast<const float4 *>(a)[g];
+            v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+        }
     } else {
         v[0] = a[g]; v[1] = a[n + g]; v[2] = a[2 * n + g]; v[3] = a[3 * n + g];
     }
@@ -96,12 +108,17 @@ __device__ __forceinline__ void store4(double *__restrict__ a, int64_t n, int64_
     }
 }
 
-template <int LAYOUT>
-__device__ __forceinline__ void load2(const double *__restrict__ a, int64_t n, int64_t g,
-                                      double &v0, double &v1) {
+template <int LAYOUT, typename Real>
+__device__ __forceinline__ void load2(const Real *__restrict__ a, int64_t n, int64_t g, Real &v0,
+                                      Real &v1) {
     if constexpr (LAYOUT == UM_AOS) {
-        const double2 t = reinterpret_cast<const double2 *>(a)[g];
-        v0 = t.x; v1 = t.y;
+        if constexpr (sizeof(Real) == 8) {
+            const double2 t = reinterpret_cast<const double2 *>(a)[g];
+            v0 = t.x; v1 = t.y;
+        } else {
+            const float2 t = reinterpret_cast<const float2 *>(a)[g];
+            v0 = t.x; v1 = t.y;
+        }
     } else {
         v0 = a[g]; v1 = a[n + g];
     }
@@ -115,34 +132,36 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+template <typename Real>
 struct Dats {
-    const double *__restrict__ x;
-    const double *__restrict__ q;
-    const double *__restrict__ adt;
+    const Real *__restrict__ x;
+    const Real *__restrict__ q;
+    const Real *__restrict__ adt;
     double *__restrict__ res;
     int64_t N, C;
 };
 
-template <int LAYOUT>
-__device__ __forceinline__ void edge_flux_global(const Dats &d, int L, int R, int a, int b,
-                                                 double gm1, double eps, double f[4]) {
-    double qL[4], qR[4], xa0, xa1, xb0, xb1;
+template <int LAYOUT, typename Real>
+__device__ __forceinline__ void edge_flux_global(const Dats<Real> &d, int L, int R, int a, int b,
+                                                 Real gm1, Real eps, Real f[4]) {
+    Real qL[4], qR[4], xa0, xa1, xb0, xb1;
     load4<LAYOUT>(d.q, d.C, L, qL);
     load4<LAYOUT>(d.q, d.C, R, qR);
     load2<LAYOUT>(d.x, d.N, a, xa0, xa1);
     load2<LAYOUT>(d.x, d.N, b, xb0, xb1);
-    const double adtL = d.adt[L], adtR = d.adt[R];
+    const Real adtL = d.adt[L], adtR = d.adt[R];
     lf2d_flux(xa0, xa1, xb0, xb1, qL, qR, adtL, adtR, gm1, eps, f);
 }
 
-// Stage the residual (as accumulator) and, when staging all, q and adt of
-// staged cell t into LDS, from registers loaded by fetch_cell.
+// One staged cell in registers between its global loads and LDS stores.
+template <typename Real>
 struct CellRegs {
-    double r[4], q[4], a;
+    double r[4];
+    Real q[4], a;
 };
 
-template <int LAYOUT, int STAGING>
-__device__ __forceinline__ void fetch_cell(const Dats &d, int64_t g, CellRegs &c) {
+template <int LAYOUT, int STAGING, typename Real>
+__device__ __forceinline__ void fetch_cell(const Dats<Real> &d, int64_t g, CellRegs<Real> &c) {
     load4<LAYOUT>(d.res, d.C, g, c.r);
     if constexpr (STAGING == UM_STAGE_ALL) {
         load4<LAYOUT>(d.q, d.C, g, c.q);
@@ -150,9 +169,9 @@ __device__ __forceinline__ void fetch_cell(const Dats &d, int64_t g, CellRegs &c
     }
 }
 
-template <int STAGING>
-__device__ __forceinline__ void put_cell(double *s_inc, double *s_q, double *s_adt, int nc, int t,
-                                         const CellRegs &c) {
+template <int STAGING, typename Real>
+__device__ __forceinline__ void put_cell(double *s_inc, Real *s_q, Real *s_adt, int nc, int t,
+                                         const CellRegs<Real> &c) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) s_inc[k * nc + t] = c.r[k];
     if constexpr (STAGING == UM_STAGE_ALL) {
@@ -178,15 +197,16 @@ __device__ __forceinline__ int32_t staged_id(const Run *__restrict__ runs, int r
 
 // EPT = elements (edges) per lane: the workgroup has T lanes and handles a
 // block of up to EPT*T edges; lane l computes slots l, l+T, ...
-template <int LAYOUT, int STAGING, int TCMODE, int EPT>
+template <int LAYOUT, int STAGING, int TCMODE, int EPT, typename Real>
 __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict__ binfo,
                                                     const int32_t *__restrict__ stg_c,
                                                     const int32_t *__restrict__ stg_n,
                                                     const Run *__restrict__ crun,
                                                     const Run *__restrict__ nrun,
-                                                    const uint2 *__restrict__ loc, Dats d,
-                                                    double gm1, double eps, int32_t base) {
+                                                    const uint2 *__restrict__ loc, Dats<Real> d,
+                                                    double gm1d, double epsd, int32_t base) {
     extern __shared__ double lds[];
+    const Real gm1 = Real(gm1d), eps = Real(epsd);
     const int32_t pos = base + int32_t(blockIdx.x);
     const BlockInfo bi = binfo[pos], bn = binfo[pos + 1];
     const int ne = bn.slot_off - bi.slot_off;
@@ -197,10 +217,10 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
     const int32_t *__restrict__ sn = stg_n + bi.node_off;
     auto cell_id = [&](int t) { return staged_id(crun, bi.crun_off, ncr, sc, t); };
     auto node_id = [&](int t) { return staged_id(nrun, bi.nrun_off, nnr, sn, t); };
-    double *s_inc = lds;            // [4][nc] increment accumulators
-    double *s_q = s_inc + 4 * nc;   // [4][nc]
-    double *s_adt = s_q + 4 * nc;   // [nc]
-    double *s_x = s_adt + nc;       // [2][nn]
+    double *s_inc = lds;                                      // [4][nc] accumulators
+    Real *s_q = reinterpret_cast<Real *>(s_inc + 4 * nc);     // [4][nc]
+    Real *s_adt = s_q + 4 * nc;                               // [nc]
+    Real *s_x = s_adt + nc;                                   // [2][nn]
     const int tid = int(threadIdx.x), T = int(blockDim.x);
 
     // local index words of this lane's slots: issued first, used after the
@@ -219,7 +239,7 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
         const bool has1 = t1 < nc;
         const int64_t g0 = cell_id(t0);
         const int64_t g1 = has1 ? cell_id(t1) : g0;
-        CellRegs c0, c1;
+        CellRegs<Real> c0, c1;
         fetch_cell<LAYOUT, STAGING>(d, g0, c0);
         fetch_cell<LAYOUT, STAGING>(d, g1, c1);
         put_cell<STAGING>(s_inc, s_q, s_adt, nc, t0, c0);
@@ -231,7 +251,7 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
             const bool has1 = t1 < nn;
             const int64_t g0 = node_id(t0);
             const int64_t g1 = has1 ? node_id(t1) : g0;
-            double a0, a1, b0, b1;
+            Real a0, a1, b0, b1;
             load2<LAYOUT>(d.x, d.N, g0, a0, a1);
             load2<LAYOUT>(d.x, d.N, g1, b0, b1);
             s_x[t0] = a0;
@@ -246,7 +266,7 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
 
     // fluxes of this lane's edges into registers
     int lL[EPT], lR[EPT], col[EPT];
-    double f[EPT][4];
+    Real f[EPT][4];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         lL[j] = int(w[j].x & 0x7FFu);
@@ -254,10 +274,10 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
         lR[j] = int((w[j].x >> 16) & 0x7FFu);
         const int nA = int(w[j].y & 0xFFFFu), nB = int(w[j].y >> 16);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) f[j][k] = 0.0;
+        for (int k = 0; k < 4; ++k) f[j][k] = Real(0);
         if (col[j] >= 0) {
             if constexpr (STAGING == UM_STAGE_ALL) {
-                double qL[4], qR[4];
+                Real qL[4], qR[4];
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     qL[k] = s_q[k * nc + lL[j]];
@@ -274,8 +294,8 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
 
     if constexpr (TCMODE == UM_TC_BARRIER) {
         // layer 2: one thread colour at a time; same-colour edges never share
-        // a cell, so their LDS read-modify-writes do not race.  Slots are
-        // sorted by colour, so most wavefronts hold a single colour.
+        // a cell, so their LDS updates do not race.  Slots are sorted by
+        // colour, so most wavefronts hold a single colour.
         const int ncol = bi.ncol;
         for (int c = 0; c < ncol; ++c) {
 #pragma unroll
@@ -283,8 +303,8 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
                 if (col[j] == c) {
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        lds_add(&s_inc[k * nc + lL[j]], f[j][k]);
-                        lds_add(&s_inc[k * nc + lR[j]], -f[j][k]);
+                        lds_add(&s_inc[k * nc + lL[j]], double(f[j][k]));
+                        lds_add(&s_inc[k * nc + lR[j]], -double(f[j][k]));
                     }
                 }
             }
@@ -296,8 +316,8 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
             if (col[j] >= 0) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    lds_add(&s_inc[k * nc + lL[j]], f[j][k]);
-                    lds_add(&s_inc[k * nc + lR[j]], -f[j][k]);
+                    lds_add(&s_inc[k * nc + lL[j]], double(f[j][k]));
+                    lds_add(&s_inc[k * nc + lR[j]], -double(f[j][k]));
                 }
             }
         }
@@ -314,102 +334,89 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
     }
 }
 
-template <int LAYOUT>
+template <int LAYOUT, typename Real>
 __global__ __launch_bounds__(1024) void gcol_kernel(const int4 *__restrict__ emap, int32_t begin,
-                                                   int32_t end, Dats d, double gm1, double eps) {
+                                                   int32_t end, Dats<Real> d, double gm1,
+                                                   double eps) {
     const int32_t s = begin + int32_t(blockIdx.x * blockDim.x + threadIdx.x);
     if (s >= end) return;
     const int4 m = emap[s];  // L, R, a, b
-    double f[4];
-    edge_flux_global<LAYOUT>(d, m.x, m.y, m.z, m.w, gm1, eps, f);
+    Real f[4];
+    edge_flux_global<LAYOUT>(d, m.x, m.y, m.z, m.w, Real(gm1), Real(eps), f);
     double rL[4], rR[4];
     load4<LAYOUT>(d.res, d.C, m.x, rL);
     load4<LAYOUT>(d.res, d.C, m.y, rR);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        rL[k] += f[k];
-        rR[k] -= f[k];
+        rL[k] += double(f[k]);
+        rR[k] -= double(f[k]);
     }
     store4<LAYOUT>(d.res, d.C, m.x, rL);
     store4<LAYOUT>(d.res, d.C, m.y, rR);
 }
 
-template <int LAYOUT>
+template <int LAYOUT, typename Real>
 __global__ __launch_bounds__(1024) void atomic_kernel(const int4 *__restrict__ emap, int32_t n,
-                                                     Dats d, double gm1, double eps) {
+                                                     Dats<Real> d, double gm1, double eps) {
     const int32_t s = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
     if (s >= n) return;
     const int4 m = emap[s];
-    double f[4];
-    edge_flux_global<LAYOUT>(d, m.x, m.y, m.z, m.w, gm1, eps, f);
+    Real f[4];
+    edge_flux_global<LAYOUT>(d, m.x, m.y, m.z, m.w, Real(gm1), Real(eps), f);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int64_t iL = LAYOUT == UM_AOS ? 4 * int64_t(m.x) + k : k * d.C + m.x;
         const int64_t iR = LAYOUT == UM_AOS ? 4 * int64_t(m.y) + k : k * d.C + m.y;
-        unsafeAtomicAdd(&d.res[iL], f[k]);
-        unsafeAtomicAdd(&d.res[iR], -f[k]);
+        unsafeAtomicAdd(&d.res[iL], double(f[k]));
+        unsafeAtomicAdd(&d.res[iR], -double(f[k]));
     }
 }
 
-template <int LAYOUT>
+template <int LAYOUT, typename Real>
 __global__ __launch_bounds__(1024) void debug_kernel(const int4 *__restrict__ emap, int32_t n,
-                                                    Dats d, double gm1, double eps,
+                                                    Dats<Real> d, double gm1, double eps,
                                                     double *__restrict__ out) {
     const int32_t s = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
     if (s >= n) return;
     const int4 m = emap[s];
-    double qL[4], qR[4], xa0, xa1, xb0, xb1, f[4];
+    Real qL[4], qR[4], xa0, xa1, xb0, xb1, f[4];
     load4<LAYOUT>(d.q, d.C, m.x, qL);
     load4<LAYOUT>(d.q, d.C, m.y, qR);
     load2<LAYOUT>(d.x, d.N, m.z, xa0, xa1);
     load2<LAYOUT>(d.x, d.N, m.w, xb0, xb1);
-    lf2d_flux_nocontract(xa0, xa1, xb0, xb1, qL, qR, d.adt[m.x], d.adt[m.y], gm1, eps, f);
+    lf2d_flux_nocontract(xa0, xa1, xb0, xb1, qL, qR, d.adt[m.x], d.adt[m.y], Real(gm1), Real(eps),
+                         f);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) out[4 * int64_t(s) + k] = f[k];
+    for (int k = 0; k < 4; ++k) out[4 * int64_t(s) + k] = double(f[k]);
 }
 
-template <int LAYOUT, int ST, int TC, int EPT>
-void set_attr_one() {
-    hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, ST, TC, EPT>),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-}
-
-template <int LAYOUT, int ST, int TC>
-hipError_t launch_hier_ept(const LaunchArgs &la, int32_t nblocks, int32_t base, int64_t lds,
-                           Dats d) {
-    static bool attrs = false;
-    if (!attrs) {
-        set_attr_one<LAYOUT, ST, TC, 1>();
-        set_attr_one<LAYOUT, ST, TC, 2>();
-        set_attr_one<LAYOUT, ST, TC, 4>();
-        attrs = true;
+template <int LAYOUT, int ST, int TC, int EPT, typename Real>
+hipError_t launch_hier_one(const LaunchArgs &la, int32_t nblocks, int32_t base, int64_t lds,
+                           const Dats<Real> &d) {
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, ST, TC, EPT, Real>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
     }
-    dim3 grid(nblocks), block(la.block_size);
-    const uint2 *loc = reinterpret_cast<const uint2 *>(la.loc);
-    switch (la.ept) {
-    case 1:
-        hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, 1>), grid, block, size_t(lds), la.stream,
-                           la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun, loc, d, la.gm1,
-                           la.eps, base);
-        break;
-    case 2:
-        hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, 2>), grid, block, size_t(lds), la.stream,
-                           la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun, loc, d, la.gm1,
-                           la.eps, base);
-        break;
-    case 4:
-        hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, 4>), grid, block, size_t(lds), la.stream,
-                           la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun, loc, d, la.gm1,
-                           la.eps, base);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
+    hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, EPT, Real>), dim3(nblocks),
+                       dim3(la.block_size), size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n,
+                       la.crun, la.nrun, reinterpret_cast<const uint2 *>(la.loc), d, la.gm1,
+                       la.eps, base);
     return hipGetLastError();
 }
 
-template <int LAYOUT>
-hipError_t launch_hier(const LaunchArgs &la, int32_t nblocks, int32_t base, int64_t lds, Dats d) {
+template <int LAYOUT, int ST, int TC, typename Real>
+hipError_t launch_hier_ept(const LaunchArgs &la, int32_t nblocks, int32_t base, int64_t lds,
+                           const Dats<Real> &d) {
+    if (la.ept == 1) return launch_hier_one<LAYOUT, ST, TC, 1>(la, nblocks, base, lds, d);
+    if (la.ept == 2) return launch_hier_one<LAYOUT, ST, TC, 2>(la, nblocks, base, lds, d);
+    return hipErrorInvalidValue;
+}
+
+template <int LAYOUT, typename Real>
+hipError_t launch_hier(const LaunchArgs &la, int32_t nblocks, int32_t base, int64_t lds,
+                       const Dats<Real> &d) {
     if (la.staging == UM_STAGE_ALL && la.tcmode == UM_TC_BARRIER)
         return launch_hier_ept<LAYOUT, UM_STAGE_ALL, UM_TC_BARRIER>(la, nblocks, base, lds, d);
     if (la.staging == UM_STAGE_ALL && la.tcmode == UM_TC_LDS_ATOMIC)
@@ -417,49 +424,45 @@ hipError_t launch_hier(const LaunchArgs &la, int32_t nblocks, int32_t base, int6
     if (la.staging == UM_STAGE_INC_ONLY && la.tcmode == UM_TC_BARRIER)
         return launch_hier_ept<LAYOUT, UM_STAGE_INC_ONLY, UM_TC_BARRIER>(la, nblocks, base, lds, d);
     if (la.staging == UM_STAGE_INC_ONLY && la.tcmode == UM_TC_LDS_ATOMIC)
-        return launch_hier_ept<LAYOUT, UM_STAGE_INC_ONLY, UM_TC_LDS_ATOMIC>(la, nblocks, base, lds, d);
+        return launch_hier_ept<LAYOUT, UM_STAGE_INC_ONLY, UM_TC_LDS_ATOMIC>(la, nblocks, base, lds,
+                                                                            d);
     return hipErrorInvalidValue;
+}
+
+template <int LAYOUT, typename Real>
+hipError_t launch_typed(const LaunchArgs &la, int which, int32_t begin, int32_t end, int64_t lds) {
+    const Dats<Real> d{static_cast<const Real *>(la.x), static_cast<const Real *>(la.q),
+                       static_cast<const Real *>(la.adt), la.res, la.N, la.C};
+    if (which == LAUNCH_HIER) return launch_hier<LAYOUT>(la, end - begin, begin, lds, d);
+    const int32_t n = end - begin;
+    if (n <= 0) return hipSuccess;
+    const int tb = la.block_size;
+    dim3 grid((n + tb - 1) / tb), block(tb);
+    const int4 *em = reinterpret_cast<const int4 *>(la.emap);
+    if (which == LAUNCH_GCOL)
+        hipLaunchKernelGGL((gcol_kernel<LAYOUT, Real>), grid, block, 0, la.stream, em, begin, end,
+                           d, la.gm1, la.eps);
+    else if (which == LAUNCH_ATOMIC)
+        hipLaunchKernelGGL((atomic_kernel<LAYOUT, Real>), grid, block, 0, la.stream, em, n, d,
+                           la.gm1, la.eps);
+    else if (which == LAUNCH_DEBUG)
+        hipLaunchKernelGGL((debug_kernel<LAYOUT, Real>), grid, block, 0, la.stream, em, n, d,
+                           la.gm1, la.eps, la.out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t lf2d_launch_one(const LaunchArgs &la, int which, int32_t begin, int32_t end,
                            int64_t lds) {
-    Dats d{la.x, la.q, la.adt, la.res, la.N, la.C};
-    const int layout = la.layout;
-    if (which == LAUNCH_HIER)
-        return layout == UM_AOS ? launch_hier<UM_AOS>(la, end - begin, begin, lds, d)
-                                : launch_hier<UM_SOA>(la, end - begin, begin, lds, d);
-    const int32_t n = end - begin;
-    if (n <= 0) return hipSuccess;
-    const int tb = la.block_size;
-    dim3 grid((n + tb - 1) / tb), block(tb);
-    const int4 *em = reinterpret_cast<const int4 *>(la.emap);
-    if (which == LAUNCH_GCOL) {
-        if (layout == UM_AOS)
-            hipLaunchKernelGGL(gcol_kernel<UM_AOS>, grid, block, 0, la.stream, em, begin, end, d,
-                               la.gm1, la.eps);
-        else
-            hipLaunchKernelGGL(gcol_kernel<UM_SOA>, grid, block, 0, la.stream, em, begin, end, d,
-                               la.gm1, la.eps);
-    } else if (which == LAUNCH_ATOMIC) {
-        if (layout == UM_AOS)
-            hipLaunchKernelGGL(atomic_kernel<UM_AOS>, grid, block, 0, la.stream, em, n, d, la.gm1,
-                               la.eps);
-        else
-            hipLaunchKernelGGL(atomic_kernel<UM_SOA>, grid, block, 0, la.stream, em, n, d, la.gm1,
-                               la.eps);
-    } else if (which == LAUNCH_DEBUG) {
-        if (layout == UM_AOS)
-            hipLaunchKernelGGL(debug_kernel<UM_AOS>, grid, block, 0, la.stream, em, n, d, la.gm1,
-                               la.eps, la.out);
-        else
-            hipLaunchKernelGGL(debug_kernel<UM_SOA>, grid, block, 0, la.stream, em, n, d, la.gm1,
-                               la.eps, la.out);
-    } else {
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const bool f64 = la.dtype == UM_F64;
+    if (la.layout == UM_AOS)
+        return f64 ? launch_typed<UM_AOS, double>(la, which, begin, end, lds)
+                   : launch_typed<UM_AOS, float>(la, which, begin, end, lds);
+    return f64 ? launch_typed<UM_SOA, double>(la, which, begin, end, lds)
+               : launch_typed<UM_SOA, float>(la, which, begin, end, lds);
 }
 
 }  // namespace um

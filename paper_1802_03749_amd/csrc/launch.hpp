@@ -11,13 +11,13 @@ enum { LAUNCH_HIER = 0, LAUNCH_GCOL = 1, LAUNCH_ATOMIC = 2, LAUNCH_DEBUG = 3 };
 
 struct LaunchArgs {
     hipStream_t stream;
-    int32_t layout, staging, tcmode, block_size, ept;
+    int32_t layout, staging, tcmode, block_size, ept, dtype;
     const BlockInfo *binfo;
     const int32_t *stg_c, *stg_n;
     const Run *crun, *nrun;
     const uint32_t *loc;
     const int32_t *emap;
-    const double *x, *q, *adt;
+    const void *x, *q, *adt;  // UM_F64 or UM_F32 per dtype
     double *res;
     int64_t N, C;
     double gm1, eps;

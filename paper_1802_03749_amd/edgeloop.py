@@ -54,9 +54,15 @@ class EdgeFluxLoop:
 
     def __init__(self, x, q, adt, e2n, e2c, *, device: int = 0, order: str = "rcm+partition",
                  block_size: int = 512, point_reorder: bool = True, layout: str = "aos",
-                 geometric_partition: bool = True):
+                 geometric_partition: bool = True, dtype: str = "f64"):
+        """dtype: "f64", or "f32" to store x, q and adt in binary32 (rounded to
+        nearest from the given binary64 values); res is always binary64."""
         self.device = device
         self.layout = LAYOUTS[layout]
+        if dtype not in ("f64", "f32"):
+            raise ValueError(dtype)
+        self.um_dtype = U.UM_F64 if dtype == "f64" else U.UM_F32
+        self.tdtype = torch.float64 if dtype == "f64" else torch.float32
         x = np.ascontiguousarray(x, np.float64); q = np.ascontiguousarray(q, np.float64)
         adt = np.ascontiguousarray(adt, np.float64)
         e2n = np.ascontiguousarray(e2n, np.int32); e2c = np.ascontiguousarray(e2c, np.int32)
@@ -89,19 +95,19 @@ class EdgeFluxLoop:
         if device >= 0:
             self.dev = torch.device("cuda", device)
             self.stream = torch.cuda.current_stream(self.dev).cuda_stream
-            self.x = self._upload(x, self.s_nodes)
-            self.q = self._upload(q, self.s_cells)
-            self.adt = self._upload(adt[:, None], self.s_cells)
+            self.x = self._upload(x, self.s_nodes, self.um_dtype)
+            self.q = self._upload(q, self.s_cells, self.um_dtype)
+            self.adt = self._upload(adt[:, None], self.s_cells, self.um_dtype)
             self.res = self._alloc(self.C, 4)
             ptr = lambda t: t.data_ptr()
         else:
             self.x = self.q = self.adt = self.res = None
             ptr = lambda t: None
-        d = lambda s, dim, t: U.um_decl_dat(self.ctx, s, dim, U.UM_F64, self.layout, ptr(t))
-        self.d_x = d(self.s_nodes, 2, self.x)
-        self.d_q = d(self.s_cells, 4, self.q)
-        self.d_adt = d(self.s_cells, 1, self.adt)
-        self.d_res = d(self.s_cells, 4, self.res)
+        d = lambda s, dim, t, dt: U.um_decl_dat(self.ctx, s, dim, dt, self.layout, ptr(t))
+        self.d_x = d(self.s_nodes, 2, self.x, self.um_dtype)
+        self.d_q = d(self.s_cells, 4, self.q, self.um_dtype)
+        self.d_adt = d(self.s_cells, 1, self.adt, self.um_dtype)
+        self.d_res = d(self.s_cells, 4, self.res, U.UM_F64)
 
     # ------------------------------------------------------------ numbering
     def perm(self, set_id: int) -> np.ndarray:
@@ -129,16 +135,16 @@ class EdgeFluxLoop:
         shape = (n, dim) if self.layout == U.UM_AOS else (dim, n)
         return torch.zeros(shape, dtype=torch.float64, device=self.dev)
 
-    def _to_dev_layout(self, a: np.ndarray) -> torch.Tensor:
+    def _to_dev_layout(self, a: np.ndarray, np_dtype=np.float64) -> torch.Tensor:
         a = a if self.layout == U.UM_AOS else np.ascontiguousarray(a.T)
-        return torch.from_numpy(np.ascontiguousarray(a)).to(self.dev)
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np_dtype)).to(self.dev)
 
-    def _upload(self, a: np.ndarray, set_id: int) -> torch.Tensor:
+    def _upload(self, a: np.ndarray, set_id: int, um_dtype: int = U.UM_F64) -> torch.Tensor:
         """User-numbered host array -> device tensor in the current numbering."""
-        src = self._to_dev_layout(a)
+        src = self._to_dev_layout(a, np.float64 if um_dtype == U.UM_F64 else np.float32)
         dst = torch.empty_like(src)
         U.um_permute_dat(self.ctx, set_id, 0, src.data_ptr(), dst.data_ptr(), a.shape[1],
-                         U.UM_F64, self.layout, self.stream)
+                         um_dtype, self.layout, self.stream)
         torch.cuda.synchronize(self.dev)
         return dst
 
