@@ -94,6 +94,18 @@ typedef enum { UM_TC_BARRIER = 0, UM_TC_LDS_ATOMIC = 1 } um_tcmode;
  * neighbours holds when that class is smaller by two or more); fewer and
  * more even launches. */
 typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1 } um_bcolouring;
+/* How block colours are ordered in time (HIER).  COLOUR_LAUNCHES: one kernel
+ * launch per block colour (the kernel boundary orders colours, Section 2.2).
+ * DATAFLOW: one launch over all blocks in colour order; each block computes
+ * its fluxes, then waits until every neighbouring block of an earlier colour
+ * has published its write-back (a per-block completion flag written with
+ * device-scope release and read with device-scope acquire), then loads and
+ * updates its residuals.  The per-cell order of additions is the same as
+ * with colour launches, so both schedules give bitwise identical results.
+ * A wait that exceeds a time limit sets the plan's error count instead of
+ * hanging (um_plan_errors).  Supported for STAGE_ALL with one element per
+ * lane; a plan must not execute concurrently with itself. */
+typedef enum { UM_SCHED_COLOUR_LAUNCHES = 0, UM_SCHED_DATAFLOW = 1 } um_schedule;
 
 /* Elemental kernels compiled into the library (no run-time code generation).
  *
@@ -168,7 +180,8 @@ typedef struct {
                                   them from the runs (no index loads); 1 =
                                   every block reads its explicit id list     */
     int32_t block_colouring;   /* HIER: um_bcolouring                        */
-    int32_t reserved[2];
+    int32_t schedule;          /* HIER: um_schedule                          */
+    int32_t reserved[1];
 } um_plan_opts;
 
 typedef struct {
@@ -342,6 +355,11 @@ um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void
  * returns the summed kernel time in ms and the number of launches timed
  * since the last reset, then resets. */
 um_status um_plan_set_timing(um_plan plan, int32_t enable);
+
+/* Synchronise the device and return in *n_errors the number of executions
+ * of a DATAFLOW plan in which a block gave up waiting for a neighbour
+ * (results of those executions are invalid); 0 for other plans. */
+um_status um_plan_errors(um_plan plan, int32_t *n_errors);
 um_status um_plan_timing(um_plan plan, double *ms_total, int64_t *n_launches);
 
 /* Verification entry point: evaluate the elemental flux of every element of

@@ -76,7 +76,8 @@ T *upload(const std::vector<T> &v, int64_t &bytes) {
 }
 
 void free_device_plan(Plan &p) {
-    void *bufs[7] = {p.dp.emap, p.dp.binfo, p.dp.stg_c, p.dp.stg_n, p.dp.loc, p.dp.crun, p.dp.nrun};
+    void *bufs[11] = {p.dp.emap, p.dp.binfo,    p.dp.stg_c, p.dp.stg_n, p.dp.loc, p.dp.crun,
+                      p.dp.nrun, p.dp.pred_off, p.dp.preds, p.dp.flags, p.dp.err};
     for (void *b : bufs)
         if (b) hipFree(b);
     p.dp = DevicePlan{};
@@ -165,6 +166,11 @@ LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *str
     la.C = ctx.sets[q.set].size;
     la.gm1 = params[0];
     la.eps = params[1];
+    la.schedule = p.hp.schedule;
+    la.pred_off = p.dp.pred_off;
+    la.preds = p.dp.preds;
+    la.flags = p.dp.flags;
+    la.err = p.dp.err;
     return la;
 }
 
@@ -401,6 +407,8 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
             fail(UM_ERR_ARG, "elems_per_thread %d not in {1, 2}", o.elems_per_thread);
         if (o.block_colouring != UM_BCOL_FIRST_FIT && o.block_colouring != UM_BCOL_RECOLOUR)
             fail(UM_ERR_ARG, "bad block_colouring %d", o.block_colouring);
+        if (o.schedule != UM_SCHED_COLOUR_LAUNCHES && o.schedule != UM_SCHED_DATAFLOW)
+            fail(UM_ERR_ARG, "bad schedule %d", o.schedule);
         const auto t0 = std::chrono::steady_clock::now();
         EdgeArgs ea = check_lf2d_args(c, args, nargs, iter_set);
         auto *p = new um_plan_s();
@@ -420,6 +428,14 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
                 p->dp.crun = upload(p->hp.crun, bytes);
                 p->dp.nrun = upload(p->hp.nrun, bytes);
                 p->dp.loc = upload(p->hp.loc, bytes);
+                if (p->hp.schedule == UM_SCHED_DATAFLOW && !p->hp.binfo.empty()) {
+                    p->dp.pred_off = upload(p->hp.pred_off, bytes);
+                    p->dp.preds = upload(p->hp.preds, bytes);
+                    std::vector<int32_t> zeros(p->hp.binfo.size(), 0);
+                    p->dp.flags = upload(zeros, bytes);
+                    std::vector<int32_t> zero1(1, 0);
+                    p->dp.err = upload(zero1, bytes);
+                }
                 p->dp.bytes = bytes;
                 UM_HIP(hipDeviceSynchronize());
             }
@@ -459,6 +475,7 @@ um_status um_plan_stats_get(um_plan plan, um_plan_stats *out) {
             out->n_launches = 0;
             for (int32_t c = 0; c + 1 < int32_t(hp.bcol_off.size()); ++c)
                 out->n_launches += hp.bcol_off[c + 1] > hp.bcol_off[c];
+            if (hp.schedule == UM_SCHED_DATAFLOW) out->n_launches = out->n_launches > 0;
         } else if (hp.strategy == UM_STRAT_GLOBAL_COLOUR) {
             out->n_global_colours = int32_t(hp.colour_off.size()) - 1;
             out->n_launches = out->n_global_colours;
@@ -598,7 +615,17 @@ um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void
                 ++p.pending_pairs;
             }
         };
-        if (hp.strategy == UM_STRAT_HIER) {
+        if (hp.strategy == UM_STRAT_HIER && hp.schedule == UM_SCHED_DATAFLOW) {
+            // epochs mark completion flags of this execution; on wrap-around
+            // the flags are cleared with a plain upload first
+            if (p.epoch == INT32_MAX) {
+                std::vector<int32_t> zeros(hp.binfo.size(), 0);
+                UM_HIP(hipMemcpy(p.dp.flags, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice));
+                p.epoch = 0;
+            }
+            la.epoch = ++p.epoch;
+            one(LAUNCH_HIER_FLOW, 0, int32_t(hp.blk_order.size()), hp.lds_max);
+        } else if (hp.strategy == UM_STRAT_HIER) {
             for (int32_t c = 0; c + 1 < int32_t(hp.bcol_off.size()); ++c)
                 if (hp.bcol_off[c + 1] > hp.bcol_off[c])
                     one(LAUNCH_HIER, hp.bcol_off[c], hp.bcol_off[c + 1], hp.lds_per_colour[c]);
@@ -633,6 +660,18 @@ um_status um_plan_timing(um_plan plan, double *ms_total, int64_t *n_launches) {
         *ms_total = ms;
         *n_launches = p.pending_pairs;
         p.pending_pairs = 0;
+    });
+}
+
+um_status um_plan_errors(um_plan plan, int32_t *n_errors) {
+    return guarded([&] {
+        Plan &p = need(plan);
+        if (!n_errors) fail(UM_ERR_ARG, "null output");
+        *n_errors = 0;
+        if (!p.dp.err) return;
+        DeviceGuard g(p.ctx->device);
+        UM_HIP(hipDeviceSynchronize());
+        UM_HIP(hipMemcpy(n_errors, p.dp.err, sizeof(int32_t), hipMemcpyDeviceToHost));
     });
 }
 

@@ -106,6 +106,7 @@ constexpr int32_t MAX_RUNS = 32;
 struct HostPlan {
     int32_t strategy = 0, staging = 0, tcmode = 0, block_size = 0;
     int32_t ept = 1, threads = 0;              // HIER: elements per lane, lanes per block
+    int32_t schedule = 0;                      // HIER: um_schedule
     int64_t n_elem = 0;
     // GLOBAL_COLOUR / ATOMIC: packed (L, R, a, b) per slot, slot order
     std::vector<int32_t> emap;                 // [n_slots][4]
@@ -124,6 +125,7 @@ struct HostPlan {
     std::vector<int32_t> slot_elem;            // slot -> element
     std::vector<int32_t> tcol;                 // element -> thread colour
     std::vector<int64_t> lds_per_colour;       // max LDS bytes per block colour
+    std::vector<int32_t> pred_off, preds;      // DATAFLOW: earlier neighbours per position
     int32_t max_tcol = 0;
     double avg_tcol = 0.0, reuse = 0.0;
     int64_t lds_max = 0, staged_total = 0;
@@ -142,6 +144,8 @@ struct DevicePlan {
     int32_t *stg_c = nullptr, *stg_n = nullptr;
     Run *crun = nullptr, *nrun = nullptr;
     uint32_t *loc = nullptr;
+    int32_t *pred_off = nullptr, *preds = nullptr;  // DATAFLOW
+    int32_t *flags = nullptr, *err = nullptr;       // DATAFLOW: completion epochs, error count
     int64_t bytes = 0;
 };
 
@@ -158,6 +162,7 @@ struct Plan {
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
     int64_t pending_pairs = 0;
+    int32_t epoch = 0;                         // DATAFLOW: executions so far
 };
 
 }  // namespace um

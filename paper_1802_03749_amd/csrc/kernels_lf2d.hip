@@ -334,6 +334,173 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
     }
 }
 
+// Longest a block waits for one predecessor before giving up (s_memrealtime
+// ticks at 100 MHz: 0.2 s).
+constexpr uint64_t FLOW_WAIT_TICKS = 20000000ull;
+
+// DATAFLOW schedule: one launch over all blocks in colour order (position =
+// blockIdx.x).  Same per-block work as hier_kernel with STAGE_ALL and one
+// edge per lane, except that the residuals are loaded only after every
+// neighbouring block of an earlier colour has published its write-back.
+// Publication: all lanes finish their stores (s_waitcnt), the workgroup
+// meets at a barrier, then one lane issues a device-scope release fence and
+// stores the execution's epoch into the block's flag.  Consumption: lanes
+// of the first wavefront poll one predecessor flag each until it holds the
+// epoch, then issue a device-scope acquire fence before the barrier that
+// precedes the residual loads.  Blocks are dispatched in increasing
+// blockIdx order and a block only waits for smaller positions, so every
+// awaited block is already running or finished; the wait is bounded in time
+// anyway and a timeout is counted in *err instead of hanging.
+template <int LAYOUT, int TCMODE, typename Real>
+__global__ __launch_bounds__(1024) void hier_flow_kernel(
+    const BlockInfo *__restrict__ binfo, const int32_t *__restrict__ stg_c,
+    const int32_t *__restrict__ stg_n, const Run *__restrict__ crun, const Run *__restrict__ nrun,
+    const uint2 *__restrict__ loc, Dats<Real> d, double gm1d, double epsd,
+    const int32_t *__restrict__ pred_off, const int32_t *__restrict__ preds, int32_t *flags,
+    int32_t *err, int32_t epoch) {
+    extern __shared__ double lds[];
+    const Real gm1 = Real(gm1d), eps = Real(epsd);
+    const int32_t pos = int32_t(blockIdx.x);
+    const BlockInfo bi = binfo[pos], bn = binfo[pos + 1];
+    const int ne = bn.slot_off - bi.slot_off;
+    const int nc = bn.cell_off - bi.cell_off;
+    const int nn = bn.node_off - bi.node_off;
+    const int ncr = bn.crun_off - bi.crun_off, nnr = bn.nrun_off - bi.nrun_off;
+    const int32_t *__restrict__ sc = stg_c + bi.cell_off;
+    const int32_t *__restrict__ sn = stg_n + bi.node_off;
+    auto cell_id = [&](int t) { return staged_id(crun, bi.crun_off, ncr, sc, t); };
+    auto node_id = [&](int t) { return staged_id(nrun, bi.nrun_off, nnr, sn, t); };
+    double *s_inc = lds;
+    Real *s_q = reinterpret_cast<Real *>(s_inc + 4 * nc);
+    Real *s_adt = s_q + 4 * nc;
+    Real *s_x = s_adt + nc;
+    const int tid = int(threadIdx.x), T = int(blockDim.x);
+    const int p0 = pred_off[pos], np = pred_off[pos + 1] - p0;
+
+    const uint2 w = tid < ne ? loc[bi.slot_off + tid] : make_uint2(0, 0);
+    // gather the read-only data (q, adt, x); residuals come after the wait
+    for (int t0 = tid; t0 < nc; t0 += 2 * T) {
+        const int t1 = t0 + T;
+        const bool has1 = t1 < nc;
+        const int64_t g0 = cell_id(t0);
+        const int64_t g1 = has1 ? cell_id(t1) : g0;
+        Real q0[4], q1[4];
+        load4<LAYOUT>(d.q, d.C, g0, q0);
+        load4<LAYOUT>(d.q, d.C, g1, q1);
+        const Real a0 = d.adt[g0], a1 = d.adt[g1];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_q[k * nc + t0] = q0[k];
+        s_adt[t0] = a0;
+        if (has1) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_q[k * nc + t1] = q1[k];
+            s_adt[t1] = a1;
+        }
+    }
+    for (int t0 = tid; t0 < nn; t0 += 2 * T) {
+        const int t1 = t0 + T;
+        const bool has1 = t1 < nn;
+        const int64_t g0 = node_id(t0);
+        const int64_t g1 = has1 ? node_id(t1) : g0;
+        Real a0, a1, b0, b1;
+        load2<LAYOUT>(d.x, d.N, g0, a0, a1);
+        load2<LAYOUT>(d.x, d.N, g1, b0, b1);
+        s_x[t0] = a0;
+        s_x[nn + t0] = a1;
+        if (has1) {
+            s_x[t1] = b0;
+            s_x[nn + t1] = b1;
+        }
+    }
+    __syncthreads();
+
+    const int lL = int(w.x & 0x7FFu), lR = int((w.x >> 16) & 0x7FFu);
+    const int col = tid < ne ? int((w.x >> 11) & 31u) : -1;
+    Real f[4] = {Real(0), Real(0), Real(0), Real(0)};
+    if (col >= 0) {
+        const int nA = int(w.y & 0xFFFFu), nB = int(w.y >> 16);
+        Real qL[4], qR[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            qL[k] = s_q[k * nc + lL];
+            qR[k] = s_q[k * nc + lR];
+        }
+        lf2d_flux(s_x[nA], s_x[nn + nA], s_x[nB], s_x[nn + nB], qL, qR, s_adt[lL], s_adt[lR], gm1,
+                  eps, f);
+    }
+
+    // wait for the earlier-coloured neighbours (np <= 64: first wavefront)
+    if (tid < np) {
+        const int32_t *fl = flags + preds[p0 + tid];
+        const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+            if (__builtin_amdgcn_s_memrealtime() - t_begin > FLOW_WAIT_TICKS) {
+                __hip_atomic_fetch_add(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    __syncthreads();
+
+    // residuals as accumulators
+    for (int t0 = tid; t0 < nc; t0 += 2 * T) {
+        const int t1 = t0 + T;
+        const bool has1 = t1 < nc;
+        const int64_t g0 = cell_id(t0);
+        const int64_t g1 = has1 ? cell_id(t1) : g0;
+        double r0[4], r1[4];
+        load4<LAYOUT>(d.res, d.C, g0, r0);
+        load4<LAYOUT>(d.res, d.C, g1, r1);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s_inc[k * nc + t0] = r0[k];
+        if (has1) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_inc[k * nc + t1] = r1[k];
+        }
+    }
+    __syncthreads();
+
+    if constexpr (TCMODE == UM_TC_BARRIER) {
+        const int ncol = bi.ncol;
+        for (int c = 0; c < ncol; ++c) {
+            if (col == c) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    lds_add(&s_inc[k * nc + lL], double(f[k]));
+                    lds_add(&s_inc[k * nc + lR], -double(f[k]));
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        if (col >= 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                lds_add(&s_inc[k * nc + lL], double(f[k]));
+                lds_add(&s_inc[k * nc + lR], -double(f[k]));
+            }
+        }
+        __syncthreads();
+    }
+
+    for (int t = tid; t < nc; t += T) {
+        double r[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = s_inc[k * nc + t];
+        store4<LAYOUT>(d.res, d.C, cell_id(t), r);
+    }
+    // publish: every lane's stores complete, then one release + flag store
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(flags + pos, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 template <int LAYOUT, typename Real>
 __global__ __launch_bounds__(1024) void gcol_kernel(const int4 *__restrict__ emap, int32_t begin,
                                                    int32_t end, Dats<Real> d, double gm1,
@@ -429,11 +596,33 @@ hipError_t launch_hier(const LaunchArgs &la, int32_t nblocks, int32_t base, int6
     return hipErrorInvalidValue;
 }
 
+template <int LAYOUT, int TC, typename Real>
+hipError_t launch_flow(const LaunchArgs &la, int32_t nblocks, int64_t lds, const Dats<Real> &d) {
+    static bool attr = false;
+    if (!attr) {
+        hipFuncSetAttribute(reinterpret_cast<const void *>(hier_flow_kernel<LAYOUT, TC, Real>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr = true;
+    }
+    hipLaunchKernelGGL((hier_flow_kernel<LAYOUT, TC, Real>), dim3(nblocks), dim3(la.block_size),
+                       size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun,
+                       reinterpret_cast<const uint2 *>(la.loc), d, la.gm1, la.eps, la.pred_off,
+                       la.preds, la.flags, la.err, la.epoch);
+    return hipGetLastError();
+}
+
 template <int LAYOUT, typename Real>
 hipError_t launch_typed(const LaunchArgs &la, int which, int32_t begin, int32_t end, int64_t lds) {
     const Dats<Real> d{static_cast<const Real *>(la.x), static_cast<const Real *>(la.q),
                        static_cast<const Real *>(la.adt), la.res, la.N, la.C};
     if (which == LAUNCH_HIER) return launch_hier<LAYOUT>(la, end - begin, begin, lds, d);
+    if (which == LAUNCH_HIER_FLOW) {
+        if (la.staging != UM_STAGE_ALL || la.ept != 1 || end - begin <= 0)
+            return hipErrorInvalidValue;
+        return la.tcmode == UM_TC_BARRIER
+                   ? launch_flow<LAYOUT, UM_TC_BARRIER>(la, end - begin, lds, d)
+                   : launch_flow<LAYOUT, UM_TC_LDS_ATOMIC>(la, end - begin, lds, d);
+    }
     const int32_t n = end - begin;
     if (n <= 0) return hipSuccess;
     const int tb = la.block_size;

@@ -7,7 +7,8 @@
 
 namespace um {
 
-enum { LAUNCH_HIER = 0, LAUNCH_GCOL = 1, LAUNCH_ATOMIC = 2, LAUNCH_DEBUG = 3 };
+enum { LAUNCH_HIER = 0, LAUNCH_GCOL = 1, LAUNCH_ATOMIC = 2, LAUNCH_DEBUG = 3,
+       LAUNCH_HIER_FLOW = 4 };
 
 struct LaunchArgs {
     hipStream_t stream;
@@ -22,6 +23,9 @@ struct LaunchArgs {
     int64_t N, C;
     double gm1, eps;
     double *out;  // debug fluxes
+    int32_t schedule, epoch;
+    const int32_t *pred_off, *preds;
+    int32_t *flags, *err;
 };
 
 // One kernel launch of the LF2D loop: HIER covers launch positions

@@ -209,6 +209,23 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
         std::fill(stamp.begin(), stamp.end(), -1);
     }
     hp.blk_order = counting_order(hp.blk_colour, nbcol, hp.bcol_off);
+    hp.schedule = o.schedule;
+    if (o.schedule == UM_SCHED_DATAFLOW) {
+        // predecessors of a launch position: its neighbours launched earlier,
+        // which are exactly its neighbours of smaller colour
+        std::vector<int32_t> pos_of(nb);
+        for (int32_t pos = 0; pos < nb; ++pos) pos_of[hp.blk_order[pos]] = pos;
+        hp.pred_off.assign(nb + 1, 0);
+        hp.preds.clear();
+        for (int32_t pos = 0; pos < nb; ++pos) {
+            const int32_t b = hp.blk_order[pos];
+            for (int64_t i = adj_off[b]; i < adj_off[b + 1]; ++i)
+                if (pos_of[adj[i]] < pos) hp.preds.push_back(pos_of[adj[i]]);
+            hp.pred_off[pos + 1] = int32_t(hp.preds.size());
+            if (hp.pred_off[pos + 1] - hp.pred_off[pos] > 64)
+                fail(UM_ERR_UNSUPPORTED, "dataflow schedule: block %d waits on more than 64 blocks", b);
+        }
+    }
 
     // ---- per block in launch order: staged lists, layer 2 colouring, slots
     std::vector<int32_t> cloc(C, -1), nloc(ctx.sets[mn.to].size, -1);
@@ -318,6 +335,8 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
                  (long long)need_all, (long long)limit);
         hp.staging = UM_STAGE_INC_ONLY;
     }
+    if (hp.schedule == UM_SCHED_DATAFLOW && (hp.staging != UM_STAGE_ALL || hp.ept != 1))
+        fail(UM_ERR_UNSUPPORTED, "dataflow schedule needs STAGE_ALL staging and one element per lane");
     if (hp.staging == UM_STAGE_INC_ONLY && need_inc > limit)
         fail(UM_ERR_LDS, "staging increments needs %lld bytes of LDS per block, limit %lld",
              (long long)need_inc, (long long)limit);

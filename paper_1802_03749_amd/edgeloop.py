@@ -25,6 +25,7 @@ LAYOUTS = {"aos": U.UM_AOS, "soa": U.UM_SOA}
 STAGING = {"all": U.UM_STAGE_ALL, "inc": U.UM_STAGE_INC_ONLY}
 TCMODES = {"barrier": U.UM_TC_BARRIER, "lds_atomic": U.UM_TC_LDS_ATOMIC}
 BCOLOURING = {"first_fit": U.UM_BCOL_FIRST_FIT, "recolour": U.UM_BCOL_RECOLOUR}
+SCHEDULES = {"colour_launches": U.UM_SCHED_COLOUR_LAUNCHES, "dataflow": U.UM_SCHED_DATAFLOW}
 
 
 def parse_order(order: str):
@@ -174,7 +175,8 @@ class EdgeFluxLoop:
     def plan(self, strategy: str = "hier", block_size: int = 512, staging: str = "all",
              tcmode: str = "barrier", max_block_colours: int = 256, lds_limit_bytes: int = 0,
              allow_fallback: bool = True, elems_per_thread: int = 1,
-             explicit_lists: bool = False, block_colouring: str = "first_fit") -> Plan:
+             explicit_lists: bool = False, block_colouring: str = "first_fit",
+             schedule: str = "colour_launches") -> Plan:
         o = U.um_plan_opts()
         o.strategy = STRATEGIES[strategy]
         o.block_size = block_size
@@ -186,6 +188,7 @@ class EdgeFluxLoop:
         o.elems_per_thread = elems_per_thread
         o.explicit_lists = 1 if explicit_lists else 0
         o.block_colouring = BCOLOURING[block_colouring]
+        o.schedule = SCHEDULES[schedule]
         h = U.um_plan_build(self.ctx, U.UM_K_EDGE_FLUX_LF2D, self.args(), self.s_edges, o)
         p = Plan(h, strategy, block_size, U.um_plan_stats_get(h).as_dict())
         self._plans.append(p)

@@ -30,6 +30,7 @@ UM_REORDER_NONE, UM_REORDER_RCM, UM_REORDER_GPS, UM_REORDER_PARTITION = 0, 1, 2,
 UM_STAGE_ALL, UM_STAGE_INC_ONLY = 0, 1
 UM_TC_BARRIER, UM_TC_LDS_ATOMIC = 0, 1
 UM_BCOL_FIRST_FIT, UM_BCOL_RECOLOUR = 0, 1
+UM_SCHED_COLOUR_LAUNCHES, UM_SCHED_DATAFLOW = 0, 1
 UM_K_EDGE_FLUX_LF2D = 0
 (UM_EXP_BLOCK_OFFSETS, UM_EXP_BLOCK_COLOURS, UM_EXP_THREAD_COLOURS, UM_EXP_SLOT_ELEMENTS,
  UM_EXP_GLOBAL_COLOURS, UM_EXP_STAGED_OFFSETS_A, UM_EXP_STAGED_POINTS_A,
@@ -64,7 +65,8 @@ class um_plan_opts(ct.Structure):
                 ("tcmode", ct.c_int32), ("max_block_colours", ct.c_int32),
                 ("lds_limit_bytes", ct.c_int32), ("allow_fallback", ct.c_int32),
                 ("elems_per_thread", ct.c_int32), ("explicit_lists", ct.c_int32),
-                ("block_colouring", ct.c_int32), ("reserved", ct.c_int32 * 2)]
+                ("block_colouring", ct.c_int32), ("schedule", ct.c_int32),
+                ("reserved", ct.c_int32 * 1)]
 
 
 class um_plan_stats(ct.Structure):
@@ -109,6 +111,7 @@ _SIGNATURES = {
     "um_loop_exec": [_P, _P, _I32, _P],
     "um_plan_set_timing": [_P, _I32],
     "um_plan_timing": [_P, ct.POINTER(ct.c_double), _PI64],
+    "um_plan_errors": [_P, _PI32],
     "um_debug_fluxes": [_P, _P, _I32, _P, _P],
 }
 _RESTYPES = {"um_abi_version": ct.c_int32, "um_last_error": ct.c_char_p}
@@ -273,3 +276,9 @@ def um_plan_timing(plan: int):
 def um_debug_fluxes(plan: int, params, f_out: int, stream: int) -> None:
     p = (ct.c_double * len(params))(*params)
     _check(lib().um_debug_fluxes(plan, p, len(params), f_out, stream), "um_debug_fluxes")
+
+
+def um_plan_errors(plan: int) -> int:
+    n = _I32()
+    _check(lib().um_plan_errors(plan, ct.byref(n)), "um_plan_errors")
+    return n.value

@@ -306,3 +306,16 @@ def test_recolour_matches_oracle(S):
     assert p.stats["n_block_colours"] == nc <= q.stats["n_block_colours"]
     counts = np.bincount(bcol)
     assert counts.max() - counts.min() <= np.bincount(L.export(q, U.UM_EXP_BLOCK_COLOURS)).max()
+
+
+def test_dataflow_plan_options():
+    _, L = make(nx=40, ny=30, order="rcm+partition", block_size=128)
+    p = L.plan("hier", 128, schedule="dataflow")
+    assert p.stats["n_launches"] == 1
+    with pytest.raises(U.UmeshError) as ei:
+        L.plan("hier", 128, schedule="dataflow", staging="inc")
+    assert ei.value.status == U.UM_ERR_UNSUPPORTED
+    with pytest.raises(U.UmeshError):
+        L.plan("hier", 128, schedule="dataflow", elems_per_thread=2)
+    # a host-only plan reports no errors without touching a device
+    assert U.um_plan_errors(p.handle) == 0
