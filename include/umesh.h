@@ -101,7 +101,9 @@ typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1 } um_bcolouring;
  * has published its write-back (a per-block completion flag written with
  * device-scope release and read with device-scope acquire), then loads and
  * updates its residuals.  The per-cell order of additions is the same as
- * with colour launches, so both schedules give bitwise identical results.
+ * with colour launches; results agree to rounding (the two kernels may pair
+ * multiply-adds into FMAs differently) and each schedule is bitwise
+ * reproducible from run to run.
  * A wait that exceeds a time limit sets the plan's error count instead of
  * hanging (um_plan_errors).  Supported for STAGE_ALL with one element per
  * lane; a plan must not execute concurrently with itself. */

@@ -118,9 +118,10 @@ def test_parity_recolour(S):
 @pytest.mark.parametrize("layout", ["aos", "soa"])
 @pytest.mark.parametrize("tcmode", ["barrier", "lds_atomic"])
 def test_dataflow_schedule_parity(layout, tcmode):
-    """One launch with per-block completion flags gives the oracle's result
-    and, for barrier colour rounds, bitwise the same residual as one launch
-    per block colour (same per-cell order of additions)."""
+    """One launch with per-block completion flags gives the oracle's result,
+    is bitwise reproducible, and agrees with one launch per block colour to
+    rounding (same per-cell order of additions; the two kernels may pair
+    multiply-adds into FMAs differently)."""
     m, ref = mesh(200, 100)
     L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
                      block_size=256, layout=layout)
@@ -136,9 +137,9 @@ def test_dataflow_schedule_parity(layout, tcmode):
         outs.append(L.res_user())
     assert U.um_plan_errors(pf.handle) == 0
     assert rel_l2(outs[0], 3 * ref) <= TOL
+    assert rel_l2(outs[0], outs[1]) <= 1e-14
     if tcmode == "barrier":
-        assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
-        assert np.array_equal(outs[2].view(np.uint64), outs[1].view(np.uint64))
+        assert np.array_equal(outs[0].view(np.uint64), outs[2].view(np.uint64))
 
 
 def test_dataflow_schedule_full_size():
@@ -155,7 +156,7 @@ def test_dataflow_schedule_full_size():
         torch.cuda.synchronize()
         res.append(L.res_user())
     assert U.um_plan_errors(pf.handle) == 0
-    assert np.array_equal(res[0].view(np.uint64), res[1].view(np.uint64))
+    assert rel_l2(res[0], res[1]) <= 1e-14
     assert rel_l2(res[1], 5 * ref) <= TOL
 
 
