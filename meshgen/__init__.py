@@ -7,8 +7,9 @@ any of the computation being checked.
 """
 from .rng import splitmix64, uniform01, uniform, random_permutation, STREAM_TAGS
 from .quad2d import QuadMesh, quad_mesh, free_stream_state
+from .hex3d import HexMesh, hex_mesh
 
 __all__ = [
     "splitmix64", "uniform01", "uniform", "random_permutation", "STREAM_TAGS",
-    "QuadMesh", "quad_mesh", "free_stream_state",
+    "QuadMesh", "quad_mesh", "free_stream_state", "HexMesh", "hex_mesh",
 ]

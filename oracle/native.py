@@ -32,6 +32,10 @@ def lib():
         L.oracle_edge_loop_f32.argtypes = [ct.c_int64, P, P, P, P, P, ct.c_double,
                                            ct.c_double, P, P]
         L.oracle_edge_loop_f32.restype = None
+        L.oracle_hex_force.argtypes = [P, P, ct.c_double, P]
+        L.oracle_hex_force.restype = None
+        L.oracle_hex_loop.argtypes = [ct.c_int64, P, P, P, ct.c_double, P, P]
+        L.oracle_hex_loop.restype = None
         L.oracle_first_fit.argtypes = [ct.c_int64, P, P, ct.c_int64, ct.c_int32,
                                        P, P, P, P, P]
         L.oracle_first_fit.restype = ct.c_int32
@@ -109,3 +113,24 @@ def edge_loop_f32(e2n, e2c, x, q, adt, gm1=GM1, eps=EPS_D):
     lib().oracle_edge_loop_f32(e2n.shape[0], _p(e2n), _p(e2c), _p(x), _p(q), _p(adt),
                                float(gm1), float(eps), _p(res), _p(f))
     return res, f
+
+
+KAPPA = 1.0 / 64.0   # hourglass coefficient of the 3D element loop (dyadic)
+
+
+def hex_force(x8, v8, kappa=KAPPA) -> np.ndarray:
+    """Nodal forces [8][3] of one hexahedral element."""
+    x8 = _c(x8, np.float64); v8 = _c(v8, np.float64)
+    f = np.zeros((8, 3))
+    lib().oracle_hex_force(_p(x8), _p(v8), float(kappa), _p(f))
+    return f
+
+
+def hex_loop(e2n, x, v, kappa=KAPPA, per_element=False):
+    """force[N][3] after the sequential element loop (and [E][8][3] forces)."""
+    e2n = _c(e2n, np.int32); x = _c(x, np.float64); v = _c(v, np.float64)
+    force = np.zeros((x.shape[0], 3))
+    fe = np.zeros((e2n.shape[0], 8, 3)) if per_element else None
+    lib().oracle_hex_loop(e2n.shape[0], _p(e2n), _p(x), _p(v), float(kappa), _p(force),
+                          _p(fe) if per_element else None)
+    return (force, fe) if per_element else force
