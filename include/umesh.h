@@ -134,11 +134,31 @@ typedef enum { UM_SCHED_COLOUR_LAUNCHES = 0, UM_SCHED_DATAFLOW = 1 } um_schedule
  *   mu = eps 0.5 (adt_L + adt_R)
  *   f  = 0.5 (F_L + F_R) + 0.5 mu (q_L - q_R)
  *   res[L] += f, res[R] -= f.
+ *
+ * UM_K_HEX_HOURGLASS_3D -- 3D element loop over hexahedra (the access
+ * pattern of the LULESH stress/hourglass loop, Section 3.1.4: per element,
+ * read 3 coordinates and 3 velocities on each of its 8 nodes, increment 3
+ * force values on each of the 8 nodes).  Required args, in order, each
+ * through all 8 slots of one element->node map (idx = UM_ALL_SLOTS):
+ *   0: x     dim 3, UM_READ
+ *   1: v     dim 3, UM_READ
+ *   2: force dim 3, UM_INC
+ * All UM_F64, one layout.  params = {kappa}.  Per element, with node order
+ * 0-3 counter-clockwise on the bottom face and 4-7 above them, and the
+ * hourglass base vectors
+ *   G_1 = ( 1,  1, -1, -1, -1, -1,  1,  1)    G_2 = ( 1, -1, -1,  1, -1,  1,  1, -1)
+ *   G_3 = ( 1, -1,  1, -1,  1, -1,  1, -1)    G_4 = (-1,  1, -1,  1,  1, -1,  1, -1)
+ *   h = |x_6 - x_0|;  m_i,d = sum_b G_i,b v_b,d;  f_a,d = (-kappa h) sum_i G_i,a m_i,d
+ *   force[node a] += f_a.
  */
-typedef enum { UM_K_EDGE_FLUX_LF2D = 0 } um_kernel;
+typedef enum { UM_K_EDGE_FLUX_LF2D = 0, UM_K_HEX_HOURGLASS_3D = 1 } um_kernel;
+
+/* Map slot value meaning "every slot of the map" (a vector argument). */
+#define UM_ALL_SLOTS (-1)
 
 /* One loop argument: dat `dat` accessed through slot `idx` of map `map`
- * (map = -1: direct access on the iteration set) with access mode `acc`. */
+ * (map = -1: direct access on the iteration set; idx = UM_ALL_SLOTS: every
+ * slot) with access mode `acc`. */
 typedef struct {
     int32_t dat;
     int32_t map;
@@ -214,13 +234,16 @@ typedef enum {
     UM_EXP_SLOT_ELEMENTS = 3,   /* int32[n_elements]: element executed at each slot;
                                    slots are grouped by block in launch order        */
     UM_EXP_GLOBAL_COLOURS = 4,  /* int32[n_elements]: global colour per element      */
-    UM_EXP_STAGED_OFFSETS_A = 5,/* int32[n_blocks+1]: staged points of the first
-                                   indirect map (edge->node for LF2D), block id order */
+    UM_EXP_STAGED_OFFSETS_A = 5,/* int32[n_blocks+1]: staged points of the read-only
+                                   indirect map (edge->node for LF2D; none for the
+                                   hex loop), block id order                         */
     UM_EXP_STAGED_POINTS_A = 6, /* int32[...]: those points                          */
-    UM_EXP_STAGED_OFFSETS_B = 7,/* as above for the INC map (edge->cell for LF2D)    */
+    UM_EXP_STAGED_OFFSETS_B = 7,/* as above for the INC map (edge->cell for LF2D,
+                                   element->node for the hex loop)                   */
     UM_EXP_STAGED_POINTS_B = 8,
-    UM_EXP_LOCAL_INDEX = 9,     /* int32[n_elements][4]: per slot, local staged index
-                                   of (B slot 0, B slot 1, A slot 0, A slot 1)        */
+    UM_EXP_LOCAL_INDEX = 9,     /* int32[n_elements][k]: per slot, local staged index;
+                                   LF2D k = 4: (B slot 0, B slot 1, A slot 0, A slot 1);
+                                   hex k = 8: B slots 0..7                           */
     UM_EXP_BLOCK_ORDER = 10,    /* int32[n_blocks]: block id at each launch position  */
     UM_EXP_RUN_OFFSETS_A = 11,  /* int32[n_blocks+1]: run descriptors per block of the
                                    first indirect map's staged list, block id order;

@@ -134,7 +134,69 @@ EdgeArgs check_lf2d_args(const Ctx &ctx, const um_arg *args, int32_t nargs, int3
     return ea;
 }
 
+// Hex loop argument pattern (umesh.h, UM_K_HEX_HOURGLASS_3D).
+HexArgs check_hex_args(const Ctx &ctx, const um_arg *args, int32_t nargs, int32_t iter) {
+    if (nargs != 3 || !args) fail(UM_ERR_ARITY, "hex kernel takes 3 args, got %d", nargs);
+    const int acc[3] = {UM_READ, UM_READ, UM_INC};
+    const char *name[3] = {"x", "v", "force"};
+    for (int i = 0; i < 3; ++i) {
+        const um_arg &a = args[i];
+        if (a.dat < 0 || a.dat >= int32_t(ctx.dats.size()))
+            fail(UM_ERR_RANGE, "arg %d: dat %d does not exist", i, a.dat);
+        if (a.map < 0 || a.map >= int32_t(ctx.maps.size()))
+            fail(UM_ERR_ARITY, "arg %d: must be accessed through a map", i);
+        const Dat &d = ctx.dats[a.dat];
+        const Map &m = ctx.maps[a.map];
+        if (m.from != iter || m.arity != 8)
+            fail(UM_ERR_ARITY, "arg %d: needs an arity-8 map from the iteration set", i);
+        if (m.to != d.set) fail(UM_ERR_ARITY, "arg %d: %s is not on the map's to-set", i, name[i]);
+        if (d.dim != 3) fail(UM_ERR_ARITY, "arg %d: %s needs dim 3", i, name[i]);
+        if (a.idx != UM_ALL_SLOTS) fail(UM_ERR_ARITY, "arg %d: needs idx UM_ALL_SLOTS", i);
+        if (a.acc != acc[i]) fail(UM_ERR_ARITY, "arg %d: wrong access mode for %s", i, name[i]);
+        if (d.dtype != UM_F64) fail(UM_ERR_UNSUPPORTED, "hex kernel: only UM_F64 dats");
+        if (a.map != args[0].map) fail(UM_ERR_ARITY, "hex kernel: one map for all args");
+        if (d.layout != ctx.dats[args[0].dat].layout)
+            fail(UM_ERR_UNSUPPORTED, "hex kernel: x, v and force must share one layout");
+    }
+    HexArgs ha;
+    ha.map = args[0].map;
+    ha.dat_x = args[0].dat;
+    ha.dat_v = args[1].dat;
+    ha.dat_f = args[2].dat;
+    ha.layout = ctx.dats[ha.dat_x].layout;
+    return ha;
+}
+
+LaunchArgs launch_args_hex(Plan &p, const double *params, int32_t nparams, void *stream) {
+    const Ctx &ctx = *p.ctx;
+    if (ctx.device < 0) fail(UM_ERR_STATE, "host-only context cannot execute");
+    if (nparams != 1 || !params) fail(UM_ERR_ARG, "hex kernel takes params {kappa}");
+    LaunchArgs la{};
+    la.stream = static_cast<hipStream_t>(stream);
+    la.layout = p.ha.layout;
+    la.dtype = UM_F64;
+    la.staging = p.hp.staging;
+    la.tcmode = p.hp.tcmode;
+    la.block_size = p.hp.strategy == UM_STRAT_HIER ? p.hp.threads : p.hp.block_size;
+    la.ept = 1;
+    la.binfo = p.dp.binfo;
+    la.stg_c = p.dp.stg_c;
+    la.crun = p.dp.crun;
+    la.loc = p.dp.loc;
+    la.emap = p.dp.emap;
+    const Dat &x = ctx.dats[p.ha.dat_x], &v = ctx.dats[p.ha.dat_v], &f = ctx.dats[p.ha.dat_f];
+    if (ctx.sets[p.iter_set].size > 0 && (!x.ptr || !v.ptr || !f.ptr))
+        fail(UM_ERR_STATE, "a dat of the loop has no device memory");
+    la.x = x.ptr;
+    la.q = v.ptr;
+    la.res = static_cast<double *>(f.ptr);
+    la.N = ctx.sets[x.set].size;
+    la.gm1 = params[0];
+    return la;
+}
+
 LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *stream) {
+    if (p.kernel == UM_K_HEX_HOURGLASS_3D) return launch_args_hex(p, params, nparams, stream);
     const Ctx &ctx = *p.ctx;
     if (ctx.device < 0) fail(UM_ERR_STATE, "host-only context cannot execute");
     if (nparams != 2 || !params) fail(UM_ERR_ARG, "edge flux kernel takes params {gm1, eps}");
@@ -391,7 +453,8 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
         Ctx &c = need(ctx);
         if (!out || !opts) fail(UM_ERR_ARG, "null options or output");
         *out = nullptr;
-        if (kernel != UM_K_EDGE_FLUX_LF2D) fail(UM_ERR_UNSUPPORTED, "unknown kernel %d", kernel);
+        if (kernel != UM_K_EDGE_FLUX_LF2D && kernel != UM_K_HEX_HOURGLASS_3D)
+            fail(UM_ERR_UNSUPPORTED, "unknown kernel %d", kernel);
         if (iter_set < 0 || iter_set >= int32_t(c.sets.size())) fail(UM_ERR_ARG, "bad iteration set");
         const um_plan_opts &o = *opts;
         if (o.strategy < UM_STRAT_ATOMIC || o.strategy > UM_STRAT_HIER)
@@ -410,14 +473,18 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
         if (o.schedule != UM_SCHED_COLOUR_LAUNCHES && o.schedule != UM_SCHED_DATAFLOW)
             fail(UM_ERR_ARG, "bad schedule %d", o.schedule);
         const auto t0 = std::chrono::steady_clock::now();
-        EdgeArgs ea = check_lf2d_args(c, args, nargs, iter_set);
         auto *p = new um_plan_s();
         p->ctx = &c;
         p->kernel = kernel;
         p->iter_set = iter_set;
-        p->ea = ea;
         try {
-            build_host_plan(c, ea, iter_set, o, p->hp);
+            if (kernel == UM_K_EDGE_FLUX_LF2D) {
+                p->ea = check_lf2d_args(c, args, nargs, iter_set);
+                build_host_plan(c, p->ea, iter_set, o, p->hp);
+            } else {
+                p->ha = check_hex_args(c, args, nargs, iter_set);
+                build_host_plan_hex(c, p->ha, iter_set, o, p->hp);
+            }
             if (c.device >= 0) {
                 DeviceGuard g(c.device);
                 int64_t bytes = 0;
@@ -556,6 +623,16 @@ um_status um_plan_export(um_plan plan, int32_t field, int32_t *host_out, int64_t
         case UM_EXP_STAGED_POINTS_B: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); staged(true, false); break;
         case UM_EXP_LOCAL_INDEX:
             if (!hier) fail(UM_ERR_STATE, "not a HIER plan");
+            if (p.kernel == UM_K_HEX_HOURGLASS_3D) {
+                tmp.resize(8 * hp.n_elem);
+                for (int64_t s = 0; s < hp.n_elem; ++s)
+                    for (int w = 0; w < 4; ++w) {
+                        const uint32_t v = hp.loc[4 * s + w];
+                        tmp[8 * s + 2 * w] = int32_t(w == 0 ? (v & 0x7FFu) : (v & 0xFFFFu));
+                        tmp[8 * s + 2 * w + 1] = int32_t(v >> 16);
+                    }
+                break;
+            }
             tmp.resize(4 * hp.n_elem);
             for (int64_t s = 0; s < hp.n_elem; ++s) {
                 const uint32_t w0 = hp.loc[2 * s], w1 = hp.loc[2 * s + 1];
@@ -609,7 +686,8 @@ um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void
                 e1 = static_cast<hipEvent_t>(p.events[2 * p.pending_pairs + 1]);
                 UM_HIP(hipEventRecord(e0, la.stream));
             }
-            UM_HIP(lf2d_launch_one(la, which, b, e, lds));
+            UM_HIP(p.kernel == UM_K_HEX_HOURGLASS_3D ? hex_launch_one(la, which, b, e, lds)
+                                                    : lf2d_launch_one(la, which, b, e, lds));
             if (p.timing) {
                 UM_HIP(hipEventRecord(e1, la.stream));
                 ++p.pending_pairs;
@@ -685,20 +763,27 @@ um_status um_debug_fluxes(um_plan plan, const double *params, int32_t nparams, v
         if (E == 0) return;
         if (!f_out) fail(UM_ERR_ARG, "null output buffer");
         DeviceGuard g(c.device);
-        std::vector<int32_t> em(4 * E);
-        const Map &mc = c.maps[p.ea.map_c], &mn = c.maps[p.ea.map_n];
-        for (int64_t e = 0; e < E; ++e) {
-            em[4 * e] = mc.table[2 * e];
-            em[4 * e + 1] = mc.table[2 * e + 1];
-            em[4 * e + 2] = mn.table[2 * e];
-            em[4 * e + 3] = mn.table[2 * e + 1];
+        std::vector<int32_t> em;
+        if (p.kernel == UM_K_HEX_HOURGLASS_3D) {
+            em = c.maps[p.ha.map].table;
+        } else {
+            em.resize(4 * E);
+            const Map &mc = c.maps[p.ea.map_c], &mn = c.maps[p.ea.map_n];
+            for (int64_t e = 0; e < E; ++e) {
+                em[4 * e] = mc.table[2 * e];
+                em[4 * e + 1] = mc.table[2 * e + 1];
+                em[4 * e + 2] = mn.table[2 * e];
+                em[4 * e + 3] = mn.table[2 * e + 1];
+            }
         }
         int64_t bytes = 0;
         int32_t *d_em = upload(em, bytes);
         la.emap = d_em;
         la.out = static_cast<double *>(f_out);
         la.block_size = 256;
-        hipError_t err = lf2d_launch_one(la, LAUNCH_DEBUG, 0, int32_t(E), 0);
+        hipError_t err = p.kernel == UM_K_HEX_HOURGLASS_3D
+                             ? hex_launch_one(la, LAUNCH_DEBUG, 0, int32_t(E), 0)
+                             : lf2d_launch_one(la, LAUNCH_DEBUG, 0, int32_t(E), 0);
         hipError_t err2 = hipStreamSynchronize(la.stream);
         hipFree(d_em);
         if (err != hipSuccess || err2 != hipSuccess)

@@ -81,6 +81,14 @@ struct EdgeArgs {
     int32_t dtype = UM_F64, layout = UM_AOS;
 };
 
+// Arguments of the hex element loop: one arity-8 map, x and v read, force
+// incremented, all through every slot.
+struct HexArgs {
+    int32_t map = -1;
+    int32_t dat_x = -1, dat_v = -1, dat_f = -1;
+    int32_t dtype = UM_F64, layout = UM_AOS;
+};
+
 // Per-block layout of a hierarchical plan, in launch order.
 struct BlockInfo {
     int32_t slot_off;   // first slot of the block
@@ -133,9 +141,12 @@ struct HostPlan {
 
 void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
                      const um_plan_opts &o, HostPlan &hp);
+void build_host_plan_hex(const Ctx &ctx, const HexArgs &ha, int32_t iter_set,
+                         const um_plan_opts &o, HostPlan &hp);
 
 // LDS bytes a block needs for the given counts.
 int64_t lf2d_lds_bytes(int32_t staging, int32_t dtype, int64_t n_cells, int64_t n_nodes);
+int64_t hex_lds_bytes(int64_t n_nodes);
 
 // ----------------------------------------------------------------- device
 struct DevicePlan {
@@ -154,6 +165,7 @@ struct Plan {
     int32_t kernel = 0;
     int32_t iter_set = 0;
     EdgeArgs ea;
+    HexArgs ha;
     HostPlan hp;
     DevicePlan dp;
     double build_seconds = 0.0;

@@ -1,0 +1,276 @@
+// gfx950 kernels of the 3D hexahedral element loop (hourglass-type force on
+// the 8 nodes of each element; formula in umesh.h, UM_K_HEX_HOURGLASS_3D).
+//
+//  hex_hier_kernel   two-layer colouring (paper Section 2.2, Algorithm 1):
+//                    one workgroup per block of elements; the staged nodes'
+//                    x, v and (as FP64 accumulators) force are gathered into
+//                    LDS, every lane computes its element's 24 force values
+//                    in registers, the thread colours are applied one at a
+//                    time with ds_add_f64 and a barrier after each, and the
+//                    accumulators are stored back once.
+//  hex_gcol_kernel   global colouring: one launch per colour, plain
+//                    read-modify-write of force.
+//  hex_atomic_kernel one launch, hardware FP64 atomic adds.
+//  hex_debug_kernel  per-element forces with contraction disabled.
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+#include "launch.hpp"
+
+namespace um {
+namespace {
+
+// v times the sign of hourglass base vector i at node a.
+__device__ __forceinline__ double hg_term(int i, int a, double v) {
+    // G_1 = ( 1,  1, -1, -1, -1, -1,  1,  1)
+    // G_2 = ( 1, -1, -1,  1, -1,  1,  1, -1)
+    // G_3 = ( 1, -1,  1, -1,  1, -1,  1, -1)
+    // G_4 = (-1,  1, -1,  1,  1, -1,  1, -1)
+    constexpr int G[4][8] = {{1, 1, -1, -1, -1, -1, 1, 1},
+                             {1, -1, -1, 1, -1, 1, 1, -1},
+                             {1, -1, 1, -1, 1, -1, 1, -1},
+                             {-1, 1, -1, 1, 1, -1, 1, -1}};
+    return G[i][a] > 0 ? v : -v;
+}
+
+// Forces f[a][d] of one element from its nodes' coordinates and
+// velocities; sums left to right as written (same order as the definition).
+#define UM_HEX_FORCE_BODY                                                     \
+    const double dx = x[6][0] - x[0][0];                                      \
+    const double dy = x[6][1] - x[0][1];                                      \
+    const double dz = x[6][2] - x[0][2];                                      \
+    const double h = sqrt(dx * dx + dy * dy + dz * dz);                       \
+    const double c = -kappa * h;                                              \
+    _Pragma("unroll") for (int d = 0; d < 3; ++d) {                           \
+        double m[4];                                                          \
+        _Pragma("unroll") for (int i = 0; i < 4; ++i) {                       \
+            double s = hg_term(i, 0, v[0][d]);                                \
+            _Pragma("unroll") for (int b = 1; b < 8; ++b) s = s + hg_term(i, b, v[b][d]); \
+            m[i] = s;                                                         \
+        }                                                                     \
+        _Pragma("unroll") for (int a = 0; a < 8; ++a) {                       \
+            double s = hg_term(0, a, m[0]);                                   \
+            _Pragma("unroll") for (int i = 1; i < 4; ++i) s = s + hg_term(i, a, m[i]); \
+            f[a][d] = c * s;                                                  \
+        }                                                                     \
+    }
+
+__device__ __forceinline__ void hex_force(const double x[8][3], const double v[8][3],
+                                          double kappa, double f[8][3]) {
+    UM_HEX_FORCE_BODY
+}
+
+__device__ __forceinline__ void hex_force_nocontract(const double x[8][3], const double v[8][3],
+                                                     double kappa, double f[8][3]) {
+#pragma clang fp contract(off)
+    UM_HEX_FORCE_BODY
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void load3(const double *__restrict__ a, int64_t n, int64_t g,
+                                      double v[3]) {
+    if constexpr (LAYOUT == UM_AOS) {
+        v[0] = a[3 * g]; v[1] = a[3 * g + 1]; v[2] = a[3 * g + 2];
+    } else {
+        v[0] = a[g]; v[1] = a[n + g]; v[2] = a[2 * n + g];
+    }
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ int64_t idx3(int64_t n, int64_t g, int d) {
+    return LAYOUT == UM_AOS ? 3 * g + d : d * n + g;
+}
+
+__device__ __forceinline__ void lds_add(double *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int32_t staged_id(const Run *__restrict__ runs, int r0, int nr,
+                                             const int32_t *__restrict__ list, int t) {
+    if (nr == 0) return list[t];
+    int32_t g = runs[r0].start + t;
+    for (int r = 1; r < nr; ++r) {
+        const Run R = runs[r0 + r];
+        if (t >= R.local) g = R.start + (t - R.local);
+    }
+    return g;
+}
+
+struct HexDats {
+    const double *__restrict__ x;
+    const double *__restrict__ v;
+    double *__restrict__ force;
+    int64_t N;
+};
+
+template <int LAYOUT>
+__global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restrict__ binfo,
+                                                        const int32_t *__restrict__ stg,
+                                                        const Run *__restrict__ runs,
+                                                        const uint4 *__restrict__ loc, HexDats d,
+                                                        double kappa, int32_t base) {
+    extern __shared__ double lds[];
+    const int32_t pos = base + int32_t(blockIdx.x);
+    const BlockInfo bi = binfo[pos], bn = binfo[pos + 1];
+    const int ne = bn.slot_off - bi.slot_off;
+    const int nn = bn.cell_off - bi.cell_off;
+    const int nr = bn.crun_off - bi.crun_off;
+    const int32_t *__restrict__ sl = stg + bi.cell_off;
+    double *s_acc = lds;           // [3][nn] force accumulators
+    double *s_x = s_acc + 3 * nn;  // [3][nn]
+    double *s_v = s_x + 3 * nn;    // [3][nn]
+    const int tid = int(threadIdx.x), T = int(blockDim.x);
+
+    const uint4 w = tid < ne ? loc[bi.slot_off + tid] : make_uint4(0, 0, 0, 0);
+    for (int t = tid; t < nn; t += T) {
+        const int64_t g = staged_id(runs, bi.crun_off, nr, sl, t);
+        double xv[3], vv[3], fv[3];
+        load3<LAYOUT>(d.x, d.N, g, xv);
+        load3<LAYOUT>(d.v, d.N, g, vv);
+        load3<LAYOUT>(d.force, d.N, g, fv);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_x[k * nn + t] = xv[k];
+            s_v[k * nn + t] = vv[k];
+            s_acc[k * nn + t] = fv[k];
+        }
+    }
+    __syncthreads();
+
+    int l[8];
+    l[0] = int(w.x & 0x7FFu); l[1] = int(w.x >> 16);
+    l[2] = int(w.y & 0xFFFFu); l[3] = int(w.y >> 16);
+    l[4] = int(w.z & 0xFFFFu); l[5] = int(w.z >> 16);
+    l[6] = int(w.w & 0xFFFFu); l[7] = int(w.w >> 16);
+    const int col = tid < ne ? int((w.x >> 11) & 31u) : -1;
+    double f[8][3] = {};
+    if (col >= 0) {
+        double xe[8][3], ve[8][3];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                xe[a][k] = s_x[k * nn + l[a]];
+                ve[a][k] = s_v[k * nn + l[a]];
+            }
+        hex_force(xe, ve, kappa, f);
+    }
+    const int ncol = bi.ncol;
+    for (int c = 0; c < ncol; ++c) {
+        if (col == c) {
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) lds_add(&s_acc[k * nn + l[a]], f[a][k]);
+        }
+        __syncthreads();
+    }
+    for (int t = tid; t < nn; t += T) {
+        const int64_t g = staged_id(runs, bi.crun_off, nr, sl, t);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d.force[idx3<LAYOUT>(d.N, g, k)] = s_acc[k * nn + t];
+    }
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void gather_element(const HexDats &d, const int32_t *row,
+                                               double xe[8][3], double ve[8][3]) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        load3<LAYOUT>(d.x, d.N, row[a], xe[a]);
+        load3<LAYOUT>(d.v, d.N, row[a], ve[a]);
+    }
+}
+
+template <int LAYOUT>
+__global__ __launch_bounds__(1024) void hex_gcol_kernel(const int32_t *__restrict__ emap,
+                                                       int32_t begin, int32_t end, HexDats d,
+                                                       double kappa) {
+    const int32_t s = begin + int32_t(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= end) return;
+    const int32_t *row = emap + 8 * int64_t(s);
+    double xe[8][3], ve[8][3], f[8][3];
+    gather_element<LAYOUT>(d, row, xe, ve);
+    hex_force(xe, ve, kappa, f);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) d.force[idx3<LAYOUT>(d.N, row[a], k)] += f[a][k];
+}
+
+template <int LAYOUT>
+__global__ __launch_bounds__(1024) void hex_atomic_kernel(const int32_t *__restrict__ emap,
+                                                         int32_t n, HexDats d, double kappa) {
+    const int32_t s = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= n) return;
+    const int32_t *row = emap + 8 * int64_t(s);
+    double xe[8][3], ve[8][3], f[8][3];
+    gather_element<LAYOUT>(d, row, xe, ve);
+    hex_force(xe, ve, kappa, f);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) unsafeAtomicAdd(&d.force[idx3<LAYOUT>(d.N, row[a], k)], f[a][k]);
+}
+
+template <int LAYOUT>
+__global__ __launch_bounds__(1024) void hex_debug_kernel(const int32_t *__restrict__ emap,
+                                                        int32_t n, HexDats d, double kappa,
+                                                        double *__restrict__ out) {
+    const int32_t s = int32_t(blockIdx.x * blockDim.x + threadIdx.x);
+    if (s >= n) return;
+    const int32_t *row = emap + 8 * int64_t(s);
+    double xe[8][3], ve[8][3], f[8][3];
+    gather_element<LAYOUT>(d, row, xe, ve);
+    hex_force_nocontract(xe, ve, kappa, f);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[24 * int64_t(s) + 3 * a + k] = f[a][k];
+}
+
+template <int LAYOUT>
+hipError_t hex_launch_layout(const LaunchArgs &la, int which, int32_t begin, int32_t end,
+                             int64_t lds) {
+    const HexDats d{static_cast<const double *>(la.x), static_cast<const double *>(la.q), la.res,
+                    la.N};
+    const double kappa = la.gm1;
+    if (which == LAUNCH_HIER) {
+        static bool attr = false;
+        if (!attr) {
+            hipFuncSetAttribute(reinterpret_cast<const void *>(hex_hier_kernel<LAYOUT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            attr = true;
+        }
+        hipLaunchKernelGGL((hex_hier_kernel<LAYOUT>), dim3(end - begin), dim3(la.block_size),
+                           size_t(lds), la.stream, la.binfo, la.stg_c, la.crun,
+                           reinterpret_cast<const uint4 *>(la.loc), d, kappa, begin);
+        return hipGetLastError();
+    }
+    const int32_t n = end - begin;
+    if (n <= 0) return hipSuccess;
+    const int tb = la.block_size;
+    dim3 grid((n + tb - 1) / tb), block(tb);
+    if (which == LAUNCH_GCOL)
+        hipLaunchKernelGGL((hex_gcol_kernel<LAYOUT>), grid, block, 0, la.stream, la.emap, begin,
+                           end, d, kappa);
+    else if (which == LAUNCH_ATOMIC)
+        hipLaunchKernelGGL((hex_atomic_kernel<LAYOUT>), grid, block, 0, la.stream, la.emap, n, d,
+                           kappa);
+    else if (which == LAUNCH_DEBUG)
+        hipLaunchKernelGGL((hex_debug_kernel<LAYOUT>), grid, block, 0, la.stream, la.emap, n, d,
+                           kappa, la.out);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t hex_launch_one(const LaunchArgs &la, int which, int32_t begin, int32_t end,
+                          int64_t lds) {
+    return la.layout == UM_AOS ? hex_launch_layout<UM_AOS>(la, which, begin, end, lds)
+                               : hex_launch_layout<UM_SOA>(la, which, begin, end, lds);
+}
+
+}  // namespace um

@@ -34,6 +34,11 @@ struct LaunchArgs {
 hipError_t lf2d_launch_one(const LaunchArgs &la, int which, int32_t begin, int32_t end,
                            int64_t lds_bytes);
 
+// The same for the hex element loop (x in x, v in q, force in res, kappa in
+// gm1; emap holds 8 node ids per slot).
+hipError_t hex_launch_one(const LaunchArgs &la, int which, int32_t begin, int32_t end,
+                          int64_t lds_bytes);
+
 // dst[k] = src[idx[k]] for k < n over dim components (gather).
 hipError_t permute_gather(const void *src, void *dst, const int32_t *idx, int64_t n, int32_t dim,
                           int32_t dtype, int32_t layout, hipStream_t stream);

@@ -9,6 +9,8 @@
 
 namespace um {
 
+int64_t hex_lds_bytes(int64_t nn) { return nn * 9 * 8; }  // x[3], v[3], force acc[3]
+
 int64_t lf2d_lds_bytes(int32_t staging, int32_t dtype, int64_t nc, int64_t nn) {
     const int64_t inc = nc * 4 * 8;  // FP64 increments (res preloaded)
     if (staging == UM_STAGE_INC_ONLY) return inc;
@@ -30,16 +32,17 @@ std::vector<int32_t> counting_order(const std::vector<int32_t> &key, int32_t nke
     return order;
 }
 
-// Global first-fit colouring of elements writing cells (L, R): every cell
-// keeps a bit set of the colours already written there.
+// Global first-fit colouring of elements writing the points of their map
+// row: every point keeps a bit set of the colours already written there.
 int32_t global_colours(const Map &mc, int64_t C, std::vector<int32_t> &colour) {
-    const int64_t E = int64_t(mc.table.size()) / 2;
+    const int k = mc.arity;
+    const int64_t E = int64_t(mc.table.size()) / k;
     colour.assign(E, 0);
     int32_t words = 1;
     std::vector<uint64_t> used(C, 0);
     int32_t ncol = 0;
     for (int64_t e = 0; e < E; ++e) {
-        const int32_t L = mc.table[2 * e], R = mc.table[2 * e + 1];
+        const int32_t *pts = &mc.table[k * e];
         int32_t c = 0;
         for (int32_t w = 0;; ++w) {
             if (w == words) {  // grow the bit sets by one word per point
@@ -49,15 +52,15 @@ int32_t global_colours(const Map &mc, int64_t C, std::vector<int32_t> &colour) {
                 used.swap(grown);
                 ++words;
             }
-            uint64_t taken = used[int64_t(L) * words + w] | used[int64_t(R) * words + w];
+            uint64_t taken = 0;
+            for (int i = 0; i < k; ++i) taken |= used[int64_t(pts[i]) * words + w];
             if (~taken) {
                 c = w * 64 + __builtin_ctzll(~taken);
                 break;
             }
         }
         colour[e] = c;
-        used[int64_t(L) * words + c / 64] |= 1ull << (c % 64);
-        used[int64_t(R) * words + c / 64] |= 1ull << (c % 64);
+        for (int i = 0; i < k; ++i) used[int64_t(pts[i]) * words + c / 64] |= 1ull << (c % 64);
         ncol = std::max(ncol, c + 1);
     }
     return ncol;
@@ -65,41 +68,12 @@ int32_t global_colours(const Map &mc, int64_t C, std::vector<int32_t> &colour) {
 
 }  // namespace
 
-void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
-                     const um_plan_opts &o, HostPlan &hp) {
-    const Map &mc = ctx.maps[ea.map_c];
-    const Map &mn = ctx.maps[ea.map_n];
+// Blocks, layer-1 colouring, launch order and dataflow predecessors: the
+// part of a hierarchical plan that only depends on which points each
+// element writes (wt: [E][arity] into 0..C-1).  Returns the colour count.
+int32_t plan_blocks(const Ctx &ctx, int32_t iter_set, const int32_t *wt, int arity, int64_t C,
+                    const um_plan_opts &o, HostPlan &hp) {
     const int64_t E = ctx.sets[iter_set].size;
-    const int64_t C = ctx.sets[mc.to].size;
-    hp.strategy = o.strategy;
-    hp.block_size = o.block_size;
-    hp.n_elem = E;
-    hp.staging = o.staging;
-    hp.tcmode = o.tcmode;
-    hp.ept = o.elems_per_thread > 0 ? o.elems_per_thread : 1;
-    hp.threads = ((o.block_size + hp.ept - 1) / hp.ept + 63) / 64 * 64;
-    auto pack = [&](int64_t e, int32_t *dst) {
-        dst[0] = mc.table[2 * e];
-        dst[1] = mc.table[2 * e + 1];
-        dst[2] = mn.table[2 * e];
-        dst[3] = mn.table[2 * e + 1];
-    };
-
-    if (o.strategy == UM_STRAT_ATOMIC) {
-        hp.emap.resize(4 * E);
-        for (int64_t e = 0; e < E; ++e) pack(e, &hp.emap[4 * e]);
-        return;
-    }
-    if (o.strategy == UM_STRAT_GLOBAL_COLOUR) {
-        int32_t ncol = global_colours(mc, C, hp.elem_colour);
-        std::vector<int32_t> order = counting_order(hp.elem_colour, ncol, hp.colour_off);
-        hp.emap.resize(4 * E);
-        hp.slot_elem = order;
-        for (int64_t s = 0; s < E; ++s) pack(order[s], &hp.emap[4 * s]);
-        return;
-    }
-    if (o.strategy != UM_STRAT_HIER) fail(UM_ERR_ARG, "unknown strategy %d", o.strategy);
-
     // ---- blocks: the set's partition if built for this size, else chunks
     const Set &is = ctx.sets[iter_set];
     if (is.part_block_size == o.block_size && !is.part_off.empty()) {
@@ -119,8 +93,8 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     std::vector<int32_t> last(C, -1);
     for (int32_t b = 0; b < nb; ++b)
         for (int32_t e = hp.blk_off[b]; e < hp.blk_off[b + 1]; ++e)
-            for (int s = 0; s < 2; ++s) {
-                int32_t c = mc.table[2 * int64_t(e) + s];
+            for (int s = 0; s < arity; ++s) {
+                int32_t c = wt[int64_t(arity) * e + s];
                 if (last[c] != b) {
                     last[c] = b;
                     cb_off[c + 1]++;
@@ -133,8 +107,8 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
         std::fill(last.begin(), last.end(), -1);
         for (int32_t b = 0; b < nb; ++b)
             for (int32_t e = hp.blk_off[b]; e < hp.blk_off[b + 1]; ++e)
-                for (int s = 0; s < 2; ++s) {
-                    int32_t c = mc.table[2 * int64_t(e) + s];
+                for (int s = 0; s < arity; ++s) {
+                    int32_t c = wt[int64_t(arity) * e + s];
                     if (last[c] != b) {
                         last[c] = b;
                         cb[fill[c]++] = b;
@@ -149,8 +123,8 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
         for (int32_t b = 0; b < nb; ++b) {
             nbrs.clear();
             for (int32_t e = hp.blk_off[b]; e < hp.blk_off[b + 1]; ++e)
-                for (int s = 0; s < 2; ++s) {
-                    const int32_t c = mc.table[2 * int64_t(e) + s];
+                for (int s = 0; s < arity; ++s) {
+                    const int32_t c = wt[int64_t(arity) * e + s];
                     for (int64_t i = cb_off[c]; i < cb_off[c + 1]; ++i)
                         if (cb[i] != b) nbrs.push_back(cb[i]);
                 }
@@ -227,6 +201,47 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
         }
     }
 
+    return nbcol;
+}
+
+void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
+                     const um_plan_opts &o, HostPlan &hp) {
+    const Map &mc = ctx.maps[ea.map_c];
+    const Map &mn = ctx.maps[ea.map_n];
+    const int64_t E = ctx.sets[iter_set].size;
+    const int64_t C = ctx.sets[mc.to].size;
+    hp.strategy = o.strategy;
+    hp.block_size = o.block_size;
+    hp.n_elem = E;
+    hp.staging = o.staging;
+    hp.tcmode = o.tcmode;
+    hp.ept = o.elems_per_thread > 0 ? o.elems_per_thread : 1;
+    hp.threads = ((o.block_size + hp.ept - 1) / hp.ept + 63) / 64 * 64;
+    auto pack = [&](int64_t e, int32_t *dst) {
+        dst[0] = mc.table[2 * e];
+        dst[1] = mc.table[2 * e + 1];
+        dst[2] = mn.table[2 * e];
+        dst[3] = mn.table[2 * e + 1];
+    };
+
+    if (o.strategy == UM_STRAT_ATOMIC) {
+        hp.emap.resize(4 * E);
+        for (int64_t e = 0; e < E; ++e) pack(e, &hp.emap[4 * e]);
+        return;
+    }
+    if (o.strategy == UM_STRAT_GLOBAL_COLOUR) {
+        int32_t ncol = global_colours(mc, C, hp.elem_colour);
+        std::vector<int32_t> order = counting_order(hp.elem_colour, ncol, hp.colour_off);
+        hp.emap.resize(4 * E);
+        hp.slot_elem = order;
+        for (int64_t s = 0; s < E; ++s) pack(order[s], &hp.emap[4 * s]);
+        return;
+    }
+    if (o.strategy != UM_STRAT_HIER) fail(UM_ERR_ARG, "unknown strategy %d", o.strategy);
+
+    const int32_t nbcol = plan_blocks(ctx, iter_set, mc.table.data(), 2, C, o, hp);
+    const int32_t nb = int32_t(hp.blk_off.size()) - 1;
+
     // ---- per block in launch order: staged lists, layer 2 colouring, slots
     std::vector<int32_t> cloc(C, -1), nloc(ctx.sets[mn.to].size, -1);
     hp.binfo.resize(nb + 1);
@@ -240,7 +255,7 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     hp.use_runs = o.explicit_lists == 0;
     hp.lds_per_colour.assign(nbcol, 0);
     std::vector<int64_t> lds_all(nb);
-    std::vector<int32_t> mask, ecol, goff;
+    std::vector<int32_t> mask, ecol, goff, order;
     int64_t slot = 0, tcol_sum = 0;
     hp.max_tcol = 0;
     for (int32_t pos = 0; pos < nb; ++pos) {
@@ -353,6 +368,126 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     }
     hp.staged_total = int64_t(hp.stg_c.size() + hp.stg_n.size());
     hp.reuse = hp.stg_c.empty() ? 0.0 : double(2 * E) / double(hp.stg_c.size());
+    hp.avg_tcol = nb ? double(tcol_sum) / nb : 0.0;
+}
+
+}  // namespace um
+
+namespace um {
+
+void build_host_plan_hex(const Ctx &ctx, const HexArgs &ha, int32_t iter_set,
+                         const um_plan_opts &o, HostPlan &hp) {
+    const Map &m = ctx.maps[ha.map];
+    const int64_t E = ctx.sets[iter_set].size;
+    const int64_t N = ctx.sets[m.to].size;
+    hp.strategy = o.strategy;
+    hp.block_size = o.block_size;
+    hp.n_elem = E;
+    hp.staging = o.staging;
+    hp.tcmode = o.tcmode;
+    hp.ept = 1;
+    hp.threads = (o.block_size + 63) / 64 * 64;
+    if (o.strategy == UM_STRAT_ATOMIC) {
+        hp.emap = m.table;
+        return;
+    }
+    if (o.strategy == UM_STRAT_GLOBAL_COLOUR) {
+        int32_t ncol = global_colours(m, N, hp.elem_colour);
+        std::vector<int32_t> order = counting_order(hp.elem_colour, ncol, hp.colour_off);
+        hp.emap.resize(8 * E);
+        hp.slot_elem = order;
+        for (int64_t s = 0; s < E; ++s)
+            std::copy(&m.table[8 * int64_t(order[s])], &m.table[8 * int64_t(order[s]) + 8],
+                      &hp.emap[8 * s]);
+        return;
+    }
+    if (o.strategy != UM_STRAT_HIER) fail(UM_ERR_ARG, "unknown strategy %d", o.strategy);
+    if (o.staging != UM_STAGE_ALL || (o.elems_per_thread > 1))
+        fail(UM_ERR_UNSUPPORTED, "hex loop: only STAGE_ALL with one element per lane");
+    const int32_t nbcol = plan_blocks(ctx, iter_set, m.table.data(), 8, N, o, hp);
+    const int32_t nb = int32_t(hp.blk_off.size()) - 1;
+    if (hp.schedule == UM_SCHED_DATAFLOW)
+        fail(UM_ERR_UNSUPPORTED, "hex loop: dataflow schedule not provided");
+
+    // per block in launch order: staged nodes, layer-2 colouring, slots.
+    // Local index word: 4 x uint32 per slot holding 8 x 16-bit node indices
+    // (< 2048), the thread colour in bits 11..15 of the first one.
+    std::vector<int32_t> nloc(N, -1), mask, ecol, goff, order;
+    hp.binfo.resize(nb + 1);
+    hp.loc.resize(4 * E);
+    hp.slot_elem.resize(E);
+    hp.tcol.assign(E, 0);
+    hp.stg_c.clear(); hp.stg_n.clear(); hp.crun.clear(); hp.nrun.clear();
+    hp.use_runs = o.explicit_lists == 0;
+    hp.lds_per_colour.assign(nbcol, 0);
+    int64_t slot = 0, tcol_sum = 0;
+    hp.max_tcol = 0;
+    const int64_t limit = o.lds_limit_bytes > 0 ? o.lds_limit_bytes : ctx.lds_limit;
+    for (int32_t pos = 0; pos < nb; ++pos) {
+        const int32_t b = hp.blk_order[pos];
+        const int32_t e0 = hp.blk_off[b], e1 = hp.blk_off[b + 1], ne = e1 - e0;
+        BlockInfo &bi = hp.binfo[pos];
+        bi = BlockInfo{int32_t(slot), int32_t(hp.stg_c.size()), 0, 0, 0, 0, 0, 0};
+        const size_t n0 = hp.stg_c.size();
+        hp.stg_c.insert(hp.stg_c.end(), &m.table[8 * int64_t(e0)], &m.table[8 * int64_t(e1)]);
+        std::sort(hp.stg_c.begin() + n0, hp.stg_c.end());
+        hp.stg_c.erase(std::unique(hp.stg_c.begin() + n0, hp.stg_c.end()), hp.stg_c.end());
+        const int32_t nn = int32_t(hp.stg_c.size() - n0);
+        if (nn > 2048) fail(UM_ERR_UNSUPPORTED, "hex block %d stages %d nodes (> 2048)", b, nn);
+        for (int32_t i = 0; i < nn; ++i) nloc[hp.stg_c[n0 + i]] = i;
+        mask.assign(nn, 0);
+        ecol.assign(ne, 0);
+        int32_t ncol = 0;
+        for (int32_t i = 0; i < ne; ++i) {
+            const int32_t *row = &m.table[8 * int64_t(e0 + i)];
+            uint32_t taken = 0;
+            for (int a = 0; a < 8; ++a) taken |= uint32_t(mask[nloc[row[a]]]);
+            if (taken == 0xFFFFFFFFu)
+                fail(UM_ERR_UNSUPPORTED, "hex block %d needs more than 32 thread colours", b);
+            const int32_t c = __builtin_ctz(~taken);
+            ecol[i] = c;
+            for (int a = 0; a < 8; ++a) mask[nloc[row[a]]] |= 1 << c;
+            ncol = std::max(ncol, c + 1);
+        }
+        bi.ncol = ncol;
+        tcol_sum += ncol;
+        hp.max_tcol = std::max(hp.max_tcol, ncol);
+        order = counting_order(ecol, ncol, goff);
+        for (int32_t i = 0; i < ne; ++i) {
+            const int64_t e = e0 + order[i];
+            const int32_t *row = &m.table[8 * e];
+            uint32_t l[8];
+            for (int a = 0; a < 8; ++a) l[a] = uint32_t(nloc[row[a]]);
+            l[0] |= uint32_t(ecol[order[i]]) << 11;
+            for (int w = 0; w < 4; ++w) hp.loc[4 * slot + w] = l[2 * w] | (l[2 * w + 1] << 16);
+            hp.slot_elem[slot] = int32_t(e);
+            hp.tcol[e] = ecol[order[i]];
+            ++slot;
+        }
+        // run encoding of the staged nodes
+        bi.crun_off = int32_t(hp.crun.size());
+        if (hp.use_runs) {
+            int32_t nr = 0;
+            for (int32_t i = 0; i < nn; ++i)
+                if (i == 0 || hp.stg_c[n0 + i] != hp.stg_c[n0 + i - 1] + 1) ++nr;
+            if (nr <= MAX_RUNS)
+                for (int32_t i = 0; i < nn; ++i)
+                    if (i == 0 || hp.stg_c[n0 + i] != hp.stg_c[n0 + i - 1] + 1)
+                        hp.crun.push_back(Run{hp.stg_c[n0 + i], i});
+        }
+        for (int32_t i = 0; i < nn; ++i) nloc[hp.stg_c[n0 + i]] = -1;
+        const int64_t lds = hex_lds_bytes(nn);
+        if (lds > limit)
+            fail(UM_ERR_LDS, "hex block %d needs %lld bytes of LDS, limit %lld", b,
+                 (long long)lds, (long long)limit);
+        hp.lds_per_colour[hp.blk_colour[b]] = std::max(hp.lds_per_colour[hp.blk_colour[b]], lds);
+    }
+    hp.binfo[nb] = BlockInfo{int32_t(slot), int32_t(hp.stg_c.size()), 0, 0,
+                             int32_t(hp.crun.size()), 0, 0, 0};
+    hp.lds_max = 0;
+    for (int64_t v : hp.lds_per_colour) hp.lds_max = std::max(hp.lds_max, v);
+    hp.staged_total = int64_t(hp.stg_c.size());
+    hp.reuse = hp.stg_c.empty() ? 0.0 : double(8 * E) / double(hp.stg_c.size());
     hp.avg_tcol = nb ? double(tcol_sum) / nb : 0.0;
 }
 

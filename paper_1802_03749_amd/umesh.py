@@ -31,7 +31,8 @@ UM_STAGE_ALL, UM_STAGE_INC_ONLY = 0, 1
 UM_TC_BARRIER, UM_TC_LDS_ATOMIC = 0, 1
 UM_BCOL_FIRST_FIT, UM_BCOL_RECOLOUR = 0, 1
 UM_SCHED_COLOUR_LAUNCHES, UM_SCHED_DATAFLOW = 0, 1
-UM_K_EDGE_FLUX_LF2D = 0
+UM_K_EDGE_FLUX_LF2D, UM_K_HEX_HOURGLASS_3D = 0, 1
+UM_ALL_SLOTS = -1
 (UM_EXP_BLOCK_OFFSETS, UM_EXP_BLOCK_COLOURS, UM_EXP_THREAD_COLOURS, UM_EXP_SLOT_ELEMENTS,
  UM_EXP_GLOBAL_COLOURS, UM_EXP_STAGED_OFFSETS_A, UM_EXP_STAGED_POINTS_A,
  UM_EXP_STAGED_OFFSETS_B, UM_EXP_STAGED_POINTS_B, UM_EXP_LOCAL_INDEX,

@@ -348,3 +348,68 @@ def test_fp32_full_size():
     print(f"fp32 2400x1200: vs FP64(rn32) {rel_l2(r, ref_rn):.2e} max {max_rel(r, ref_rn):.2e}; "
           f"vs FP64 oracle {rel_l2(r, ref64):.2e} max {max_rel(r, ref64):.2e}")
     assert rel_l2(r, ref_rn) <= FP32_TOL
+
+
+# ---------------------------------------------------------- hex element loop
+from meshgen import hex_mesh  # noqa: E402
+from paper_1802_03749_amd.hexloop import HexLoop  # noqa: E402
+
+_HEX = {}
+
+
+def hexmesh(n, seed=1):
+    if (n, seed) not in _HEX:
+        m = hex_mesh(n, seed=seed)
+        _HEX[(n, seed)] = (m, native.hex_loop(m.e2n, m.x, m.v))
+    return _HEX[(n, seed)]
+
+
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+@pytest.mark.parametrize("strategy,order", [("atomic", "rcm"), ("global", "rcm"),
+                                            ("hier", "rcm+partition"), ("hier", "rcm")])
+@pytest.mark.parametrize("S", [128, 256])
+def test_hex_parity(layout, strategy, order, S):
+    m, ref = hexmesh(24)
+    print(f"hex 24^3 {strategy} {order} {layout} S={S}", flush=True)
+    L = HexLoop(m.x, m.v, m.e2n, device=0, order=order, block_size=S, layout=layout)
+    p = L.plan(strategy, S)
+    L.run(p)
+    torch.cuda.synchronize()
+    assert rel_l2(L.force_user(), ref) <= TOL
+
+
+def test_hex_contract_off_forces_bit_exact():
+    m, _ = hexmesh(12)
+    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm", block_size=128)
+    p = L.plan("atomic", 128)
+    f = L.debug_forces(p)
+    pe = L.perm(L.s_elems)
+    _, fe = native.hex_loop(m.e2n[pe], m.x, m.v, per_element=True)
+    assert np.array_equal(f.view(np.uint64), fe.view(np.uint64))
+
+
+def test_hex_uniform_velocity_exact_zero_and_determinism():
+    m = hex_mesh(16, seed=4, velocity=[0.5, -0.25, 0.125])
+    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=256)
+    p = L.plan("hier", 256)
+    L.run(p); torch.cuda.synchronize()
+    assert np.all(L.force_user() == 0.0)
+    m2, ref = hexmesh(16, seed=5)
+    L2 = HexLoop(m2.x, m2.v, m2.e2n, device=0, order="rcm+partition", block_size=256)
+    p2 = L2.plan("hier", 256)
+    outs = []
+    for _ in range(2):
+        L2.zero_force(); L2.run(p2); torch.cuda.synchronize(); outs.append(L2.force_user())
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    assert rel_l2(outs[0], ref) <= TOL
+
+
+def test_hex_full_size():
+    """128^3 elements (2.1M), the 3D configuration, hierarchical colouring."""
+    m, ref = hexmesh(128)
+    print("hex 128^3 hier", flush=True)
+    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=256)
+    p = L.plan("hier", 256)
+    L.run(p)
+    torch.cuda.synchronize()
+    assert rel_l2(L.force_user(), ref) <= TOL

@@ -319,3 +319,55 @@ def test_dataflow_plan_options():
         L.plan("hier", 128, schedule="dataflow", elems_per_thread=2)
     # a host-only plan reports no errors without touching a device
     assert U.um_plan_errors(p.handle) == 0
+
+
+# ------------------------------------------------------------ hex element loop
+from meshgen import hex_mesh  # noqa: E402
+from paper_1802_03749_amd.hexloop import HexLoop  # noqa: E402
+
+
+@pytest.mark.parametrize("order,S", [("rcm", 64), ("rcm+partition", 128), ("rcm+partition", 256)])
+def test_hex_plan_matches_oracle(order, S):
+    m = hex_mesh(10, seed=2)
+    L = HexLoop(m.x, m.v, m.e2n, device=-1, order=order, block_size=S)
+    pe, pn = L.perm(L.s_elems), L.perm(L.s_nodes)
+    assert P.is_permutation(pe, L.E) and P.is_permutation(pn, L.N)
+    inv = np.empty_like(pn); inv[pn] = np.arange(pn.size)
+    e2n = L.current_map()
+    assert np.array_equal(e2n, inv[m.e2n[pe]])
+    if order == "rcm":
+        cm = P.cuthill_mckee(m.e2n, m.n_nodes, reverse=True)
+        assert np.array_equal(pn, cm)
+    p = L.plan("hier", S)
+    off = L.export(p, U.UM_EXP_BLOCK_OFFSETS)
+    assert P.check_block_offsets(off, L.E, S) is None
+    bcol = L.export(p, U.UM_EXP_BLOCK_COLOURS)
+    ref, nbc = P.first_fit_blocks(off, e2n)
+    assert np.array_equal(bcol, ref) and P.check_block_colouring(off, bcol, e2n)
+    tcol = L.export(p, U.UM_EXP_THREAD_COLOURS)
+    tref, ntc = P.first_fit_threads(off, e2n)
+    assert np.array_equal(tcol, tref) and P.check_thread_colouring(off, tcol, e2n)
+    assert ntc.max() >= 8 - 1 or L.E < 64   # an interior node is written by 8 elements
+    so, sp = L.export(p, U.UM_EXP_STAGED_OFFSETS_B), L.export(p, U.UM_EXP_STAGED_POINTS_B)
+    for b, r in enumerate(P.staged_points(off, e2n)):
+        assert np.array_equal(sp[so[b]:so[b + 1]], r)
+    loc = L.export(p, U.UM_EXP_LOCAL_INDEX).reshape(-1, 8)
+    slots = L.export(p, U.UM_EXP_SLOT_ELEMENTS)
+    blk = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    for s, e in enumerate(slots):
+        b = blk[e]
+        assert np.array_equal(sp[so[b] + loc[s]], e2n[e])
+    gl = L.plan("global", 128)
+    gcol = L.export(gl, U.UM_EXP_GLOBAL_COLOURS)
+    assert np.array_equal(gcol, P.first_fit_elements(e2n)[0])
+
+
+def test_hex_args_checked():
+    m = hex_mesh(3, seed=1)
+    L = HexLoop(m.x, m.v, m.e2n, device=-1, order="rcm")
+    o = U.um_plan_opts(); o.strategy = U.UM_STRAT_HIER; o.block_size = 64
+    bad = [U.um_arg(L.d_x, L.m_e2n, 0, U.UM_READ), U.um_arg(L.d_v, L.m_e2n, U.UM_ALL_SLOTS, U.UM_READ),
+           U.um_arg(L.d_f, L.m_e2n, U.UM_ALL_SLOTS, U.UM_INC)]
+    with pytest.raises(U.UmeshError) as ei:
+        U.um_plan_build(L.ctx, U.UM_K_HEX_HOURGLASS_3D, bad, L.s_elems, o)
+    assert ei.value.status == U.UM_ERR_ARITY
