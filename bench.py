@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the race-free indirect-increment edge loop on one MI355X.
 
-One step = one execution of the whole loop (every block-colour launch) over
+One step = one execution of the whole loop (all of its kernel launches) over
 the 2D edge-flux workload: a 2400 x 1200 jittered quad mesh (2.88M cells,
 5,756,400 interior edges) in FP64, reordered (reverse Cuthill-McKee, then
 block partitioning with block-signature point grouping) and run with the
@@ -9,10 +9,12 @@ two-layer (hierarchical) colouring.  Inputs are seeded synthetic data
 resident in HBM before timing starts; the plan is built once beforehand and
 its build time is reported separately.
 
-Prints one JSON line (see the keys below) to stdout; progress goes to stderr.
-The global-colouring and atomics baselines run on the same GPU on the same
-mesh (reverse Cuthill-McKee order, their best), and the CPU oracle is timed
-on the host as the CPU baseline.
+Prints one JSON line to stdout; progress goes to stderr.  Besides the
+headline it reports: the global-colouring and atomics baselines on the same
+GPU and mesh (reverse Cuthill-McKee order, their best), the FP32-storage
+variant, the 3D hexahedral element loop (128^3 elements) with its own
+baselines, a plain device-copy bandwidth probe, and the CPU oracle timed on
+the host as the CPU baseline.
 """
 from __future__ import annotations
 
@@ -84,10 +86,14 @@ def main() -> int:
     ap.add_argument("--layout", default="aos", choices=["aos", "soa"])
     ap.add_argument("--staging", default="all", choices=["all", "inc"])
     ap.add_argument("--tcmode", default="barrier", choices=["barrier", "lds_atomic"])
+    ap.add_argument("--schedule", default="dataflow", choices=["colour_launches", "dataflow"])
+    ap.add_argument("--bcol", default="recolour", choices=["first_fit", "recolour"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="host time spent timing the CPU oracle (0 = skip)")
     ap.add_argument("--no-baselines", action="store_true",
                     help="skip the global-colour and atomics baselines")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP32 variant and the 3D hex workload")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -95,14 +101,14 @@ def main() -> int:
               f"(--gpus {args.gpus} requested)", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     sys.path.insert(0, ROOT)
-    from meshgen import quad_mesh
+    from meshgen import hex_mesh, quad_mesh
     from paper_1802_03749_amd import measure
     from paper_1802_03749_amd import umesh as U
-    from paper_1802_03749_amd.edgeloop import PARAMS, EdgeFluxLoop
+    from paper_1802_03749_amd.edgeloop import EdgeFluxLoop
+    from paper_1802_03749_amd.hexloop import HexLoop
 
     U.lib()  # fails loudly if the HIP library is not built
     dev = torch.cuda.get_device_properties(0)
@@ -120,14 +126,18 @@ def main() -> int:
     hier = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0,
                         order="rcm+partition", block_size=S, layout=args.layout)
     reorder_s = time.perf_counter() - t
-    plan = hier.plan("hier", S, staging=args.staging, tcmode=args.tcmode)
+    hopts = dict(staging=args.staging, tcmode=args.tcmode, block_colouring=args.bcol)
+    plan = hier.plan("hier", S, schedule=args.schedule, **hopts)
     st = plan.stats
     log(f"reorder {reorder_s:.1f}s, plan {st['build_seconds']:.2f}s: blocks={st['n_blocks']} "
         f"block colours={st['n_block_colours']} thread colours<={st['max_thread_colours']} "
-        f"reuse={st['reuse_factor']:.3f} lds={st['lds_bytes_max']}")
+        f"reuse={st['reuse_factor']:.3f} lds={st['lds_bytes_max']} launches={st['n_launches']}")
     run = lambda: hier.run(plan)
     sec = time_steps(torch, run, args.steps, args.warmup)
-    log(f"hier: {sec * 1e6:.1f} us/step")
+    if U.um_plan_errors(plan.handle) != 0:
+        log("a dataflow wait timed out: the timed results are invalid")
+        return 3
+    log(f"hier ({args.schedule}): {sec * 1e6:.1f} us/step")
 
     # per-launch kernel time over a second timed pass (HIP events around
     # every launch, recorded by the library on the launch stream)
@@ -150,8 +160,19 @@ def main() -> int:
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if (tr.get("kernel_source_sha256") == kernel_hash() and tr.get("block_size") == S
-                and tr.get("layout") == args.layout and tr.get("staging") == args.staging):
+                and tr.get("layout") == args.layout and tr.get("staging") == args.staging
+                and tr.get("schedule") == args.schedule):
             traffic = tr.get("bytes_per_launch")
+
+    variants = {}
+    other = "colour_launches" if args.schedule == "dataflow" else "dataflow"
+    p2 = hier.plan("hier", S, schedule=other, **hopts)
+    s2 = time_steps(torch, lambda: hier.run(p2), args.steps, args.warmup)
+    variants[f"fp64_{other}"] = {"edges_per_s": E / s2, "ms_per_step": s2 * 1e3,
+                                 "useful_gbps": useful / s2 / 1e9,
+                                 "launches": p2.stats["n_launches"]}
+    log(f"hier ({other}): {s2 * 1e6:.1f} us/step")
+    hier.close()
 
     # ---- baselines on the same GPU and mesh
     baselines = {}
@@ -168,6 +189,37 @@ def main() -> int:
             }
             log(f"{name}: {s * 1e6:.1f} us/step ({useful / s / 1e9:.0f} GB/s)")
         base.close()
+
+    extras = {}
+    if not args.no_extras:
+        # FP32 storage of x, q, adt (res stays FP64)
+        f32 = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0,
+                           order="rcm+partition", block_size=S, layout=args.layout, dtype="f32")
+        useful32 = measure.useful_bytes(N, C, E, real_bytes=4)
+        p = f32.plan("hier", S, schedule=args.schedule, **hopts)
+        s = time_steps(torch, lambda: f32.run(p), args.steps, args.warmup)
+        extras["edge_flux_fp32"] = {"edges_per_s": E / s, "ms_per_step": s * 1e3,
+                                    "useful_bytes_per_step": useful32,
+                                    "useful_gbps": useful32 / s / 1e9,
+                                    "pct_hbm_peak": 100 * useful32 / s / 1e9 / measure.HBM_PEAK_GBPS,
+                                    "speedup_vs_fp64": sec / s}
+        log(f"fp32 hier: {s * 1e6:.1f} us/step ({useful32 / s / 1e9:.0f} GB/s useful)")
+        f32.close()
+        # 3D hexahedral element loop, 128^3 elements
+        hm = hex_mesh(128, seed=1)
+        hb = 96 * hm.n_nodes + 32 * hm.n_elems   # x, v once, force twice, int32 map
+        hx = {"elements": hm.n_elems, "nodes": hm.n_nodes, "useful_bytes_per_step": hb}
+        for order, strat, hS in (("rcm+partition", "hier", 256), ("rcm", "global", 256),
+                                 ("rcm", "atomic", 256)):
+            H = HexLoop(hm.x, hm.v, hm.e2n, device=0, order=order, block_size=hS,
+                        layout=args.layout)
+            p = H.plan(strat, hS, block_colouring="recolour" if strat == "hier" else "first_fit")
+            s = time_steps(torch, lambda: H.run(p), max(args.steps // 2, 1), args.warmup)
+            hx[strat] = {"order": order, "elements_per_s": hm.n_elems / s, "ms_per_step": s * 1e3,
+                         "useful_gbps": hb / s / 1e9, "launches": p.stats["n_launches"]}
+            log(f"hex {strat}: {s * 1e6:.1f} us/step ({hb / s / 1e9:.0f} GB/s)")
+            H.close()
+        extras["hex_hourglass_128cubed"] = hx
 
     # ---- CPU baseline: the oracle's sequential loop on the host
     cpu = None
@@ -208,18 +260,22 @@ def main() -> int:
             "strategy": "hierarchical two-layer colouring",
             "order": "rcm+partition+point-reorder",
             "block_size": S, "layout": args.layout, "staging": args.staging,
-            "tcmode": args.tcmode, "parallelism": "none (one GPU)",
+            "tcmode": args.tcmode, "schedule": args.schedule, "block_colouring": args.bcol,
+            "parallelism": "none (one GPU)",
         },
         "useful_gbps": useful / sec / 1e9,
         "useful_bytes_per_step": useful,
         "pct_hbm_peak_step": 100 * useful / sec / 1e9 / measure.HBM_PEAK_GBPS,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": measure.HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": frac, "traffic": traffic,
-                     "kernel": "hier_kernel", "launches_per_step": launches_per_step,
+                     "kernel": "hier_flow_kernel" if args.schedule == "dataflow" else "hier_kernel",
+                     "launches_per_step": launches_per_step,
                      "avg_launch_us": avg_launch_s * 1e6,
                      "bytes_per_launch": bytes_per_launch},
         "cpu_baseline": cpu,
         "baselines": baselines,
+        "variants": variants,
+        "extras": extras,
         "plan": {k: st[k] for k in ("n_blocks", "n_block_colours", "max_thread_colours",
                                      "avg_thread_colours", "reuse_factor", "lds_bytes_max",
                                      "staged_points", "plan_device_bytes", "build_seconds")},
@@ -227,7 +283,6 @@ def main() -> int:
         "device_copy_gbps": copy_gbps,
     }
     print(json.dumps(out), flush=True)
-    hier.close()
     return 0
 
 

@@ -105,8 +105,10 @@ typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1 } um_bcolouring;
  * multiply-adds into FMAs differently) and each schedule is bitwise
  * reproducible from run to run.
  * A wait that exceeds a time limit sets the plan's error count instead of
- * hanging (um_plan_errors).  Supported for STAGE_ALL with one element per
- * lane; a plan must not execute concurrently with itself. */
+ * hanging (um_plan_errors).  The execution counter that tags the flags is
+ * kept and advanced on the device, so the launch may be captured in a HIP
+ * graph and replayed.  Supported for STAGE_ALL with one element per lane;
+ * a plan must not execute concurrently with itself. */
 typedef enum { UM_SCHED_COLOUR_LAUNCHES = 0, UM_SCHED_DATAFLOW = 1 } um_schedule;
 
 /* Elemental kernels compiled into the library (no run-time code generation).
@@ -381,9 +383,9 @@ um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void
  * since the last reset, then resets. */
 um_status um_plan_set_timing(um_plan plan, int32_t enable);
 
-/* Synchronise the device and return in *n_errors the number of executions
- * of a DATAFLOW plan in which a block gave up waiting for a neighbour
- * (results of those executions are invalid); 0 for other plans. */
+/* Synchronise the device and return in *n_errors the number of block
+ * waits of a DATAFLOW plan that gave up on a neighbour (any non-zero count
+ * makes every later result of the plan invalid); 0 for other plans. */
 um_status um_plan_errors(um_plan plan, int32_t *n_errors);
 um_status um_plan_timing(um_plan plan, double *ms_total, int64_t *n_launches);
 

@@ -500,8 +500,8 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
                     p->dp.preds = upload(p->hp.preds, bytes);
                     std::vector<int32_t> zeros(p->hp.binfo.size(), 0);
                     p->dp.flags = upload(zeros, bytes);
-                    std::vector<int32_t> zero1(1, 0);
-                    p->dp.err = upload(zero1, bytes);
+                    std::vector<int32_t> ctl(4, 0);
+                    p->dp.err = upload(ctl, bytes);
                 }
                 p->dp.bytes = bytes;
                 UM_HIP(hipDeviceSynchronize());
@@ -694,14 +694,7 @@ um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void
             }
         };
         if (hp.strategy == UM_STRAT_HIER && hp.schedule == UM_SCHED_DATAFLOW) {
-            // epochs mark completion flags of this execution; on wrap-around
-            // the flags are cleared with a plain upload first
-            if (p.epoch == INT32_MAX) {
-                std::vector<int32_t> zeros(hp.binfo.size(), 0);
-                UM_HIP(hipMemcpy(p.dp.flags, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice));
-                p.epoch = 0;
-            }
-            la.epoch = ++p.epoch;
+            // the execution number is kept and advanced on the device
             one(LAUNCH_HIER_FLOW, 0, int32_t(hp.blk_order.size()), hp.lds_max);
         } else if (hp.strategy == UM_STRAT_HIER) {
             for (int32_t c = 0; c + 1 < int32_t(hp.bcol_off.size()); ++c)

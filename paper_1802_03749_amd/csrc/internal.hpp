@@ -156,7 +156,8 @@ struct DevicePlan {
     Run *crun = nullptr, *nrun = nullptr;
     uint32_t *loc = nullptr;
     int32_t *pred_off = nullptr, *preds = nullptr;  // DATAFLOW
-    int32_t *flags = nullptr, *err = nullptr;       // DATAFLOW: completion epochs, error count
+    int32_t *flags = nullptr;                       // DATAFLOW: completion epochs per block
+    int32_t *err = nullptr;                         // DATAFLOW: [timeouts, last execution, done, 0]
     int64_t bytes = 0;
 };
 
@@ -174,7 +175,6 @@ struct Plan {
     double timed_ms = 0.0;
     int64_t timed_launches = 0;
     int64_t pending_pairs = 0;
-    int32_t epoch = 0;                         // DATAFLOW: executions so far
 };
 
 }  // namespace um

@@ -350,15 +350,21 @@ constexpr uint64_t FLOW_WAIT_TICKS = 20000000ull;
 // precedes the residual loads.  Blocks are dispatched in increasing
 // blockIdx order and a block only waits for smaller positions, so every
 // awaited block is already running or finished; the wait is bounded in time
-// anyway and a timeout is counted in *err instead of hanging.
+// anyway and a timeout is counted in ctl[0] instead of hanging.
+// The execution number lives on the device (ctl[1] = last completed
+// execution, ctl[2] = blocks finished in the current one), so a captured
+// graph can replay the launch: every block reads ctl[1] + 1 at its start,
+// and the last block to finish advances ctl[1] and clears ctl[2].
 template <int LAYOUT, int TCMODE, typename Real>
 __global__ __launch_bounds__(1024) void hier_flow_kernel(
     const BlockInfo *__restrict__ binfo, const int32_t *__restrict__ stg_c,
     const int32_t *__restrict__ stg_n, const Run *__restrict__ crun, const Run *__restrict__ nrun,
     const uint2 *__restrict__ loc, Dats<Real> d, double gm1d, double epsd,
     const int32_t *__restrict__ pred_off, const int32_t *__restrict__ preds, int32_t *flags,
-    int32_t *err, int32_t epoch) {
+    int32_t *ctl) {
     extern __shared__ double lds[];
+    int32_t *err = ctl;
+    const int32_t epoch = __hip_atomic_load(ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
     const Real gm1 = Real(gm1d), eps = Real(epsd);
     const int32_t pos = int32_t(blockIdx.x);
     const BlockInfo bi = binfo[pos], bn = binfo[pos + 1];
@@ -498,6 +504,12 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     if (tid == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store(flags + pos, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t done =
+            __hip_atomic_fetch_add(ctl + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == int32_t(gridDim.x) - 1) {
+            __hip_atomic_store(ctl + 2, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ctl + 1, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -607,7 +619,7 @@ hipError_t launch_flow(const LaunchArgs &la, int32_t nblocks, int64_t lds, const
     hipLaunchKernelGGL((hier_flow_kernel<LAYOUT, TC, Real>), dim3(nblocks), dim3(la.block_size),
                        size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun,
                        reinterpret_cast<const uint2 *>(la.loc), d, la.gm1, la.eps, la.pred_off,
-                       la.preds, la.flags, la.err, la.epoch);
+                       la.preds, la.flags, la.err);
     return hipGetLastError();
 }
 

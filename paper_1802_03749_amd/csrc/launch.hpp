@@ -23,9 +23,9 @@ struct LaunchArgs {
     int64_t N, C;
     double gm1, eps;
     double *out;  // debug fluxes
-    int32_t schedule, epoch;
+    int32_t schedule;
     const int32_t *pred_off, *preds;
-    int32_t *flags, *err;
+    int32_t *flags, *err;  // DATAFLOW: completion flags; err = control words [4]
 };
 
 // One kernel launch of the LF2D loop: HIER covers launch positions

@@ -413,3 +413,32 @@ def test_hex_full_size():
     L.run(p)
     torch.cuda.synchronize()
     assert rel_l2(L.force_user(), ref) <= TOL
+
+
+@pytest.mark.parametrize("schedule", ["colour_launches", "dataflow"])
+def test_graph_capture_replay(schedule):
+    """The loop captured in a HIP graph (torch.cuda.CUDAGraph on the capture
+    stream) and replayed several times, with eager work and synchronisation
+    in between: every replay adds exactly one more loop's increments."""
+    m, ref = mesh(200, 100)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
+                     block_size=256)
+    p = L.plan("hier", 256, schedule=schedule)
+    L.zero_res()
+    L.run(p)                      # eager run first (kernel attributes set, plan warm)
+    torch.cuda.synchronize()
+    eager = L.res_user()
+    assert rel_l2(eager, ref) <= TOL
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        L.run(p, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    L.zero_res()
+    torch.cuda.synchronize()
+    for k in range(1, 4):
+        g.replay()
+        torch.cuda.synchronize()
+        r = L.res_user()
+        assert rel_l2(r, k * eager) <= TOL, k
+        _ = torch.ones(1000, device="cuda").sum().item()   # eager work between replays
+    assert U.um_plan_errors(p.handle) == 0
