@@ -8,8 +8,10 @@ any of the computation being checked.
 from .rng import splitmix64, uniform01, uniform, random_permutation, STREAM_TAGS
 from .quad2d import QuadMesh, quad_mesh, free_stream_state
 from .hex3d import HexMesh, hex_mesh
+from .batch import QuadUnion, batch_sizes, quad_batch, union
 
 __all__ = [
     "splitmix64", "uniform01", "uniform", "random_permutation", "STREAM_TAGS",
     "QuadMesh", "quad_mesh", "free_stream_state", "HexMesh", "hex_mesh",
+    "QuadUnion", "batch_sizes", "quad_batch", "union",
 ]

@@ -10,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["flux_oracle.c", "hex_oracle.c"]
+SOURCES = ["flux_oracle.c", "hex_oracle.c", "step_oracle.c"]
 OUT = os.path.join(HERE, "liboracle.so")
 
 

@@ -36,6 +36,14 @@ def lib():
         L.oracle_hex_force.restype = None
         L.oracle_hex_loop.argtypes = [ct.c_int64, P, P, P, ct.c_double, P, P]
         L.oracle_hex_loop.restype = None
+        L.oracle_cell_adt.argtypes = [P, P, ct.c_double]
+        L.oracle_cell_adt.restype = ct.c_double
+        L.oracle_adt_loop.argtypes = [ct.c_int64, P, P, P, ct.c_double, P]
+        L.oracle_adt_loop.restype = None
+        L.oracle_bres_loop.argtypes = [ct.c_int64, P, P, P, P, P, P, ct.c_double, ct.c_double, P]
+        L.oracle_bres_loop.restype = None
+        L.oracle_update_loop.argtypes = [ct.c_int64, P, P, P]
+        L.oracle_update_loop.restype = ct.c_double
         L.oracle_first_fit.argtypes = [ct.c_int64, P, P, ct.c_int64, ct.c_int32,
                                        P, P, P, P, P]
         L.oracle_first_fit.restype = ct.c_int32
@@ -134,3 +142,42 @@ def hex_loop(e2n, x, v, kappa=KAPPA, per_element=False):
     lib().oracle_hex_loop(e2n.shape[0], _p(e2n), _p(x), _p(v), float(kappa), _p(force),
                           _p(fe) if per_element else None)
     return (force, fe) if per_element else force
+
+
+def cell_adt(xc, q, gm1=GM1) -> float:
+    xc = _c(xc, np.float64); q = _c(q, np.float64)
+    return float(lib().oracle_cell_adt(_p(xc), _p(q), float(gm1)))
+
+
+def adt_loop(c2n, x, q, gm1=GM1) -> np.ndarray:
+    c2n = _c(c2n, np.int32); x = _c(x, np.float64); q = _c(q, np.float64)
+    adt = np.zeros(q.shape[0])
+    lib().oracle_adt_loop(q.shape[0], _p(c2n), _p(x), _p(q), float(gm1), _p(adt))
+    return adt
+
+
+def bres_loop(b2n, b2c, x, q, adt, qinf, gm1=GM1, eps=EPS_D, res=None) -> np.ndarray:
+    b2n = _c(b2n, np.int32); b2c = _c(b2c, np.int32).ravel()
+    x = _c(x, np.float64); q = _c(q, np.float64); adt = _c(adt, np.float64)
+    qinf = _c(qinf, np.float64)
+    out = np.zeros((q.shape[0], 4)) if res is None else _c(res, np.float64).copy()
+    lib().oracle_bres_loop(b2n.shape[0], _p(b2n), _p(b2c), _p(x), _p(q), _p(adt), _p(qinf),
+                           float(gm1), float(eps), _p(out))
+    return out
+
+
+def update_loop(q, res, adt):
+    """(q_new, res_zeroed, rms) after the update loop."""
+    q = _c(q, np.float64).copy(); res = _c(res, np.float64).copy(); adt = _c(adt, np.float64)
+    rms = lib().oracle_update_loop(q.shape[0], _p(q), _p(res), _p(adt))
+    return q, res, float(rms)
+
+
+def time_step(m, qinf, gm1=GM1, eps=EPS_D):
+    """One time step on a QuadMesh-like object: adt, edge flux, boundary
+    flux, update.  Returns (q_new, adt, rms)."""
+    adt = adt_loop(m.c2n, m.x, m.q, gm1)
+    res = edge_loop(m.e2n, m.e2c, m.x, m.q, adt, gm1, eps)
+    res = bres_loop(m.b2n, m.b2c, m.x, m.q, adt, qinf, gm1, eps, res)
+    q_new, _, rms = update_loop(m.q, res, adt)
+    return q_new, adt, rms

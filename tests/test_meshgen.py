@@ -71,3 +71,37 @@ def test_state_distributions():
     assert -0.2 <= u.min() and u.max() <= 0.2 and -0.2 <= v.min() and v.max() <= 0.2
     assert 0.9 - 1e-12 <= p.min() and p.max() <= 1.1 + 1e-12
     assert np.all(m.adt > 0)
+
+
+def test_batch_sizes_log_uniform_and_deterministic():
+    from meshgen import batch_sizes
+    s1 = batch_sizes(64)
+    assert s1 == batch_sizes(64)
+    cells = np.array([nx * ny for nx, ny in s1])
+    assert cells.min() >= 4000 and cells.max() <= 520000
+    # log-uniform: about half the meshes below the geometric mean of the range
+    gm = np.sqrt(5e3 * 5e5)
+    assert 16 <= int((cells < gm).sum()) <= 48
+
+
+def test_union_offsets_and_maps():
+    from meshgen import union
+    ms = [quad_mesh(3, 2, seed=1), quad_mesh(4, 5, seed=2), quad_mesh(1, 1, seed=3)]
+    u = union(ms, spacing=64.0)
+    assert list(u.cell_off) == [0, 6, 26, 27]
+    assert list(u.node_off) == [0, 12, 42, 46]
+    for k, m in enumerate(ms):
+        c0, c1 = u.cell_off[k], u.cell_off[k + 1]
+        n0, n1 = u.node_off[k], u.node_off[k + 1]
+        e0, e1 = u.edge_off[k], u.edge_off[k + 1]
+        np.testing.assert_array_equal(u.q[c0:c1], m.q)
+        np.testing.assert_array_equal(u.e2c[e0:e1], m.e2c + c0)
+        np.testing.assert_array_equal(u.e2n[e0:e1], m.e2n + n0)
+        # every coordinate difference inside a mesh is unchanged
+        d = u.x[n0:n1] - u.x[n0]
+        np.testing.assert_array_equal(d, m.x - m.x[0])
+        # no map of mesh k leaves its own ranges
+        if e1 > e0:
+            assert u.e2c[e0:e1].min() >= c0 and u.e2c[e0:e1].max() < c1
+        b0, b1 = u.bedge_off[k], u.bedge_off[k + 1]
+        assert u.b2c[b0:b1].min() >= c0 and u.b2c[b0:b1].max() < c1
