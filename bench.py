@@ -86,7 +86,7 @@ def main() -> int:
     ap.add_argument("--layout", default="aos", choices=["aos", "soa"])
     ap.add_argument("--staging", default="all", choices=["all", "inc"])
     ap.add_argument("--tcmode", default="barrier", choices=["barrier", "lds_atomic"])
-    ap.add_argument("--schedule", default="dataflow", choices=["colour_launches", "dataflow"])
+    ap.add_argument("--schedule", default="colour_launches", choices=["colour_launches", "dataflow"])
     ap.add_argument("--bcol", default="recolour", choices=["first_fit", "recolour"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="host time spent timing the CPU oracle (0 = skip)")

@@ -77,7 +77,9 @@ typedef enum {
     UM_REORDER_NONE = 0,
     UM_REORDER_RCM = 1,       /* reverse Cuthill-McKee numbering of points   */
     UM_REORDER_GPS = 2,       /* forward Cuthill-McKee (level order) numbering */
-    UM_REORDER_PARTITION = 3  /* partition elements into blocks, renumber    */
+    UM_REORDER_PARTITION = 3, /* partition elements into blocks, renumber    */
+    UM_REORDER_LEXICOGRAPHIC = 4 /* renumber only the from-set of the map by
+                                    its sorted point ids (secondary loops) */
 } um_reorder;
 /* What a hierarchical block stages in LDS (Section 2.2; increments-only
  * staging is the fallback the paper needed when the staged data did not fit
@@ -98,9 +100,11 @@ typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1 } um_bcolouring;
  * launch per block colour (the kernel boundary orders colours, Section 2.2).
  * DATAFLOW: one launch over all blocks in colour order; each block computes
  * its fluxes, then waits until every neighbouring block of an earlier colour
- * has published its write-back (a per-block completion flag written with
- * device-scope release and read with device-scope acquire), then loads and
- * updates its residuals.  The per-cell order of additions is the same as
+ * has published its write-back, then loads and updates its residuals.  The
+ * schedule's residual loads and stores carry device-scope coherence (they
+ * bypass the per-XCD L2 caches' stale lines), a block's completion flag is
+ * stored once its residual stores have completed and polled with
+ * device-scope loads.  Needs 32 * (cells) < 2^31.  The per-cell order of additions is the same as
  * with colour launches; results agree to rounding (the two kernels may pair
  * multiply-adds into FMAs differently) and each schedule is bitwise
  * reproducible from run to run.
@@ -152,11 +156,62 @@ typedef enum { UM_SCHED_COLOUR_LAUNCHES = 0, UM_SCHED_DATAFLOW = 1 } um_schedule
  *   G_3 = ( 1, -1,  1, -1,  1, -1,  1, -1)    G_4 = (-1,  1, -1,  1,  1, -1,  1, -1)
  *   h = |x_6 - x_0|;  m_i,d = sum_b G_i,b v_b,d;  f_a,d = (-kappa h) sum_i G_i,a m_i,d
  *   force[node a] += f_a.
+ *
+ * The other loops of one explicit time step of the 2D solver (the Airfoil
+ * loops of Section 3.1.1 besides the edge flux; their formulas are this
+ * library's, the paper prints none):
+ *
+ * UM_K_CELL_ADT_2D -- cell loop, per cell the time-step scalar.  Args:
+ *   0: x   dim 2 via a cell->node map of arity 4 (nodes counter-clockwise),
+ *          idx UM_ALL_SLOTS, UM_READ
+ *   1: q   dim 4 direct (map -1), UM_READ
+ *   2: adt dim 1 direct, UM_WRITE
+ * All UM_F64, one layout.  params = {gm1}.  Per cell, with side k from
+ * node k to node k+1 (mod 4) and m = (y_k+1 - y_k, x_k - x_k+1):
+ *   ri = 1/q0, u = q1 ri, v = q2 ri, p = gm1 (q3 - 0.5 (q1 u + q2 v)),
+ *   c = sqrt((1 + gm1) p ri), adt = sum_k |u m_x + v m_y| + c |m|.
+ * Any strategy; one launch of block_size lanes per workgroup.
+ *
+ * UM_K_BOUNDARY_FLUX_2D -- boundary-edge loop, the edge flux between the
+ * edge's cell (left) and a far-field state (right).  Args:
+ *   0: x   dim 2 via boundary-edge->node map (arity 2) slot 0, UM_READ
+ *   1: x   dim 2 via the same map slot 1, UM_READ
+ *   2: q   dim 4 via boundary-edge->cell map (arity 1) slot 0, UM_READ
+ *   3: adt dim 1 via the same map slot 0, UM_READ
+ *   4: res dim 4 via the same map slot 0, UM_INC
+ * All UM_F64, one layout.  params = {gm1, eps, qinf0, qinf1, qinf2, qinf3}.
+ * f = the UM_K_EDGE_FLUX_LF2D flux with q_L = q[cell], q_R = qinf and
+ * adt_L = adt_R = adt[cell]; res[cell] += f.  A cell may have several
+ * boundary edges, so the increment is race-prone: UM_STRAT_ATOMIC or
+ * UM_STRAT_GLOBAL_COLOUR (UM_STRAT_HIER gives UM_ERR_UNSUPPORTED).
+ *
+ * UM_K_UPDATE_2D -- cell loop, explicit update and residual sum of squares.
+ * Args:
+ *   0: q   dim 4 direct, UM_RW
+ *   1: res dim 4 direct, UM_RW
+ *   2: adt dim 1 direct, UM_READ
+ *   3: rms dim 1 global (map UM_GLOBAL, a dat on a set of size 1), UM_INC
+ * All UM_F64, q/res/adt one layout.  No params (nparams 0).  Per cell and
+ * component: d = res/adt, q -= d, res = 0; rms += sum of d^2 over all
+ * cells.  The sum is reduced per workgroup in a fixed tree, the per-
+ * workgroup partials are summed by a second launch in a fixed order and
+ * added to rms, so the result is bitwise reproducible for a given
+ * block_size.  Two launches; the plan owns the partials buffer.
  */
-typedef enum { UM_K_EDGE_FLUX_LF2D = 0, UM_K_HEX_HOURGLASS_3D = 1 } um_kernel;
+typedef enum {
+    UM_K_EDGE_FLUX_LF2D = 0,
+    UM_K_HEX_HOURGLASS_3D = 1,
+    UM_K_CELL_ADT_2D = 2,
+    UM_K_BOUNDARY_FLUX_2D = 3,
+    UM_K_UPDATE_2D = 4
+} um_kernel;
 
 /* Map slot value meaning "every slot of the map" (a vector argument). */
 #define UM_ALL_SLOTS (-1)
+
+/* Map value of an argument that is a global reduction target: a dat
+ * declared on a set of size 1, reduced into once per loop. */
+#define UM_GLOBAL (-2)
 
 /* One loop argument: dat `dat` accessed through slot `idx` of map `map`
  * (map = -1: direct access on the iteration set; idx = UM_ALL_SLOTS: every
@@ -320,7 +375,12 @@ um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr);
  *     block, keeping their previous relative order inside a block.  With point_reorder, every to-set of a map from the from-set
  *     is renumbered by (number of accessing blocks, list of accessing
  *     blocks), ties keeping the previous order.  The blocks are remembered
- *     and used by HIER plans with the same block_size.
+ *     and used by HIER plans with the same block_size, or with a multiple
+ *     k * block_size (k consecutive blocks form one plan block).
+ *   LEXICOGRAPHIC: only the from-set of driving_map is renumbered, by the
+ *     lexicographic order of each element's sorted point ids (ties keep the
+ *     previous order), e.g. boundary edges after their cells were
+ *     renumbered by another loop's reordering.
  * Every map is rewritten into the new numbering. */
 um_status um_reorder_mesh(um_ctx ctx, const um_reorder_opts *opts);
 
@@ -372,10 +432,27 @@ um_status um_plan_destroy(um_plan plan);
 /* Execute the loop once on `stream` (hipStream_t, NULL = default stream),
  * incrementing the INC dats (they are not cleared).  Asynchronous; the
  * dats bound to the plan's args must stay valid until the work completes.
- * params: kernel constants (LF2D: {gm1, eps}).  Errors: UM_ERR_STATE on a
+ * params: kernel constants (listed with each um_kernel).  Errors: UM_ERR_STATE on a
  * host-only context or a dat without device memory, UM_ERR_HIP on launch
  * failure. */
 um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void *stream);
+
+/* Autotuning: build a plan for each of the n_candidates option sets, run
+ * each once untimed and then `reps` times between two HIP events on
+ * `stream`, keep the fastest plan in *out and destroy the others.  The
+ * loop's written dats (INC, WRITE, RW) are modified by the trial runs: the
+ * caller re-initialises them afterwards.  A candidate whose build fails
+ * with UM_ERR_LDS, UM_ERR_COLOURS, UM_ERR_UNSUPPORTED or UM_ERR_ARG, or
+ * whose DATAFLOW waits time out, is skipped (its time is -1).
+ * *best_index receives the chosen candidate; ms_out, if not NULL, receives
+ * n_candidates mean times per execution in ms.  Synchronises the device.
+ * Errors: UM_ERR_UNSUPPORTED when no candidate could be built, others as
+ * um_plan_build and um_loop_exec. */
+um_status um_plan_autotune(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t nargs,
+                           int32_t iter_set, const um_plan_opts *candidates,
+                           int32_t n_candidates, const double *params, int32_t nparams,
+                           void *stream, int32_t reps, int32_t *best_index, double *ms_out,
+                           um_plan *out);
 
 /* Timing of the plan's launches: when enabled, um_loop_exec records a HIP
  * event pair around every kernel launch; um_plan_timing waits for them and

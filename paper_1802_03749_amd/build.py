@@ -24,8 +24,9 @@ LIB = os.path.join(PKG, "libumesh.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = "gfx950"
 
-HOST_SOURCES = ["reorder.cpp", "planner.cpp"]
-HIP_SOURCES = ["api.cpp", "kernels_lf2d.hip", "kernels_hex.hip", "kernels_util.hip"]
+HOST_SOURCES = ["reorder.cpp", "planner.cpp", "planner_step.cpp"]
+HIP_SOURCES = ["api.cpp", "kernels_lf2d.hip", "kernels_hex.hip", "kernels_step.hip",
+               "kernels_util.hip"]
 
 # Device code is built without packed-FP32 instructions (explicitly disabled
 # feature) and without fast-math: division and sqrt stay IEEE-correct.

@@ -76,8 +76,8 @@ T *upload(const std::vector<T> &v, int64_t &bytes) {
 }
 
 void free_device_plan(Plan &p) {
-    void *bufs[11] = {p.dp.emap, p.dp.binfo,    p.dp.stg_c, p.dp.stg_n, p.dp.loc, p.dp.crun,
-                      p.dp.nrun, p.dp.pred_off, p.dp.preds, p.dp.flags, p.dp.err};
+    void *bufs[12] = {p.dp.emap, p.dp.binfo,    p.dp.stg_c, p.dp.stg_n, p.dp.loc,   p.dp.crun,
+                      p.dp.nrun, p.dp.pred_off, p.dp.preds, p.dp.flags, p.dp.err, p.dp.partials};
     for (void *b : bufs)
         if (b) hipFree(b);
     p.dp = DevicePlan{};
@@ -195,8 +195,49 @@ LaunchArgs launch_args_hex(Plan &p, const double *params, int32_t nparams, void 
     return la;
 }
 
+bool is_step_kernel(int32_t k) {
+    return k == UM_K_CELL_ADT_2D || k == UM_K_BOUNDARY_FLUX_2D || k == UM_K_UPDATE_2D;
+}
+
+LaunchArgs launch_args_step(Plan &p, const double *params, int32_t nparams, void *stream) {
+    const Ctx &ctx = *p.ctx;
+    if (ctx.device < 0) fail(UM_ERR_STATE, "host-only context cannot execute");
+    const int want = p.kernel == UM_K_CELL_ADT_2D ? 1 : p.kernel == UM_K_BOUNDARY_FLUX_2D ? 6 : 0;
+    if (nparams != want || (want && !params))
+        fail(UM_ERR_ARG, "kernel %d takes %d params, got %d", p.kernel, want, nparams);
+    LaunchArgs la{};
+    la.stream = static_cast<hipStream_t>(stream);
+    la.layout = p.sa.layout;
+    la.dtype = UM_F64;
+    la.block_size = p.hp.block_size;
+    la.emap = p.dp.emap;
+    const StepArgs &sa = p.sa;
+    const int ids[5] = {sa.dat_x, sa.dat_q, sa.dat_adt, sa.dat_res, sa.dat_rms};
+    if (ctx.sets[p.iter_set].size > 0)
+        for (int id : ids)
+            if (id >= 0 && !ctx.dats[id].ptr) fail(UM_ERR_STATE, "a dat of the loop has no device memory");
+    if (sa.dat_x >= 0) {
+        la.x = ctx.dats[sa.dat_x].ptr;
+        la.N = ctx.sets[ctx.dats[sa.dat_x].set].size;
+    }
+    la.q = ctx.dats[sa.dat_q].ptr;
+    la.C = ctx.sets[ctx.dats[sa.dat_q].set].size;
+    la.adt = ctx.dats[sa.dat_adt].ptr;
+    if (sa.dat_res >= 0) la.res = static_cast<double *>(ctx.dats[sa.dat_res].ptr);
+    if (sa.dat_rms >= 0) la.gbl = static_cast<double *>(ctx.dats[sa.dat_rms].ptr);
+    la.partials = p.dp.partials;
+    la.n_partials = p.hp.n_partials;
+    if (want >= 1) la.gm1 = params[0];
+    if (want == 6) {
+        la.eps = params[1];
+        for (int k = 0; k < 4; ++k) la.qinf[k] = params[2 + k];
+    }
+    return la;
+}
+
 LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *stream) {
     if (p.kernel == UM_K_HEX_HOURGLASS_3D) return launch_args_hex(p, params, nparams, stream);
+    if (is_step_kernel(p.kernel)) return launch_args_step(p, params, nparams, stream);
     const Ctx &ctx = *p.ctx;
     if (ctx.device < 0) fail(UM_ERR_STATE, "host-only context cannot execute");
     if (nparams != 2 || !params) fail(UM_ERR_ARG, "edge flux kernel takes params {gm1, eps}");
@@ -453,7 +494,8 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
         Ctx &c = need(ctx);
         if (!out || !opts) fail(UM_ERR_ARG, "null options or output");
         *out = nullptr;
-        if (kernel != UM_K_EDGE_FLUX_LF2D && kernel != UM_K_HEX_HOURGLASS_3D)
+        if (kernel != UM_K_EDGE_FLUX_LF2D && kernel != UM_K_HEX_HOURGLASS_3D &&
+            !is_step_kernel(kernel))
             fail(UM_ERR_UNSUPPORTED, "unknown kernel %d", kernel);
         if (iter_set < 0 || iter_set >= int32_t(c.sets.size())) fail(UM_ERR_ARG, "bad iteration set");
         const um_plan_opts &o = *opts;
@@ -481,6 +523,9 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
             if (kernel == UM_K_EDGE_FLUX_LF2D) {
                 p->ea = check_lf2d_args(c, args, nargs, iter_set);
                 build_host_plan(c, p->ea, iter_set, o, p->hp);
+            } else if (is_step_kernel(kernel)) {
+                p->sa = check_step_args(c, kernel, args, nargs, iter_set);
+                build_host_plan_step(c, kernel, p->sa, iter_set, o, p->hp);
             } else {
                 p->ha = check_hex_args(c, args, nargs, iter_set);
                 build_host_plan_hex(c, p->ha, iter_set, o, p->hp);
@@ -502,6 +547,10 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
                     p->dp.flags = upload(zeros, bytes);
                     std::vector<int32_t> ctl(4, 0);
                     p->dp.err = upload(ctl, bytes);
+                }
+                if (p->hp.n_partials > 0) {
+                    std::vector<double> zeros(p->hp.n_partials, 0.0);
+                    p->dp.partials = upload(zeros, bytes);
                 }
                 p->dp.bytes = bytes;
                 UM_HIP(hipDeviceSynchronize());
@@ -531,7 +580,14 @@ um_status um_plan_stats_get(um_plan plan, um_plan_stats *out) {
         out->n_elements = hp.n_elem;
         out->plan_device_bytes = p.dp.bytes;
         out->build_seconds = p.build_seconds;
-        if (hp.strategy == UM_STRAT_HIER) {
+        if (is_step_kernel(p.kernel)) {
+            if (p.kernel == UM_K_BOUNDARY_FLUX_2D && hp.strategy == UM_STRAT_GLOBAL_COLOUR) {
+                out->n_global_colours = int32_t(hp.colour_off.size()) - 1;
+                out->n_launches = out->n_global_colours;
+            } else {
+                out->n_launches = hp.n_elem > 0 ? (p.kernel == UM_K_UPDATE_2D ? 2 : 1) : 0;
+            }
+        } else if (hp.strategy == UM_STRAT_HIER) {
             out->n_blocks = int32_t(hp.blk_colour.size());
             out->n_block_colours = int32_t(hp.bcol_off.size()) - 1;
             out->max_thread_colours = hp.max_tcol;
@@ -561,7 +617,11 @@ um_status um_plan_export(um_plan plan, int32_t field, int32_t *host_out, int64_t
         const Ctx &c = *p.ctx;
         std::vector<int32_t> tmp;
         const std::vector<int32_t> *v = &tmp;
-        const bool hier = hp.strategy == UM_STRAT_HIER;
+        const bool hier = hp.strategy == UM_STRAT_HIER && !is_step_kernel(p.kernel);
+        if (is_step_kernel(p.kernel) &&
+            !(p.kernel == UM_K_BOUNDARY_FLUX_2D && hp.strategy == UM_STRAT_GLOBAL_COLOUR &&
+              (field == UM_EXP_SLOT_ELEMENTS || field == UM_EXP_GLOBAL_COLOURS)))
+            fail(UM_ERR_STATE, "field %d is not defined for kernel %d", field, p.kernel);
         auto staged = [&](bool cells, bool offsets) {
             // block id order
             const int32_t nb = int32_t(hp.blk_order.size());
@@ -693,7 +753,40 @@ um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void
                 ++p.pending_pairs;
             }
         };
-        if (hp.strategy == UM_STRAT_HIER && hp.schedule == UM_SCHED_DATAFLOW) {
+        if (is_step_kernel(p.kernel)) {
+            auto step = [&](int which, int32_t b, int32_t e) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (p.timing) {
+                    const size_t need_ev = 2 * size_t(p.pending_pairs + 1);
+                    while (p.events.size() < need_ev) {
+                        hipEvent_t h;
+                        UM_HIP(hipEventCreate(&h));
+                        p.events.push_back(h);
+                    }
+                    e0 = static_cast<hipEvent_t>(p.events[2 * p.pending_pairs]);
+                    e1 = static_cast<hipEvent_t>(p.events[2 * p.pending_pairs + 1]);
+                    UM_HIP(hipEventRecord(e0, la.stream));
+                }
+                UM_HIP(step_launch_one(la, p.kernel, which, b, e));
+                if (p.timing) {
+                    UM_HIP(hipEventRecord(e1, la.stream));
+                    ++p.pending_pairs;
+                }
+            };
+            const int32_t n = int32_t(hp.n_elem);
+            if (p.kernel == UM_K_CELL_ADT_2D) {
+                step(LAUNCH_DIRECT, 0, n);
+            } else if (p.kernel == UM_K_UPDATE_2D) {
+                step(LAUNCH_DIRECT, 0, n);
+                step(LAUNCH_REDUCE, 0, 1);
+            } else if (hp.strategy == UM_STRAT_GLOBAL_COLOUR) {
+                for (int32_t c = 0; c + 1 < int32_t(hp.colour_off.size()); ++c)
+                    if (hp.colour_off[c + 1] > hp.colour_off[c])
+                        step(LAUNCH_GCOL, hp.colour_off[c], hp.colour_off[c + 1]);
+            } else {
+                step(LAUNCH_ATOMIC, 0, n);
+            }
+        } else if (hp.strategy == UM_STRAT_HIER && hp.schedule == UM_SCHED_DATAFLOW) {
             // the execution number is kept and advanced on the device
             one(LAUNCH_HIER_FLOW, 0, int32_t(hp.blk_order.size()), hp.lds_max);
         } else if (hp.strategy == UM_STRAT_HIER) {
@@ -707,6 +800,83 @@ um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void
         } else {
             one(LAUNCH_ATOMIC, 0, int32_t(hp.n_elem), 0);
         }
+    });
+}
+
+um_status um_plan_autotune(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t nargs,
+                           int32_t iter_set, const um_plan_opts *candidates,
+                           int32_t n_candidates, const double *params, int32_t nparams,
+                           void *stream, int32_t reps, int32_t *best_index, double *ms_out,
+                           um_plan *out) {
+    return guarded([&] {
+        Ctx &c = need(ctx);
+        if (!candidates || n_candidates < 1 || reps < 1 || !best_index || !out)
+            fail(UM_ERR_ARG, "autotune: null output, no candidates or reps < 1");
+        if (c.device < 0) fail(UM_ERR_STATE, "host-only context cannot execute");
+        *out = nullptr;
+        *best_index = -1;
+        DeviceGuard g(c.device);
+        struct Events {
+            hipEvent_t e[2] = {nullptr, nullptr};
+            ~Events() {
+                for (hipEvent_t h : e)
+                    if (h) hipEventDestroy(h);
+            }
+        } ev;
+        UM_HIP(hipEventCreate(&ev.e[0]));
+        UM_HIP(hipEventCreate(&ev.e[1]));
+        const hipStream_t s = static_cast<hipStream_t>(stream);
+        um_plan best = nullptr;
+        double best_ms = 0.0;
+        auto check = [](um_status st) {
+            if (st != UM_OK) throw Error{st, g_err};
+        };
+        try {
+            for (int32_t i = 0; i < n_candidates; ++i) {
+                if (ms_out) ms_out[i] = -1.0;
+                um_plan p = nullptr;
+                const um_status st =
+                    um_plan_build(ctx, kernel, args, nargs, iter_set, &candidates[i], &p);
+                if (st == UM_ERR_LDS || st == UM_ERR_COLOURS || st == UM_ERR_UNSUPPORTED ||
+                    st == UM_ERR_ARG)
+                    continue;
+                check(st);
+                try {
+                    check(um_loop_exec(p, params, nparams, stream));
+                    UM_HIP(hipEventRecord(ev.e[0], s));
+                    for (int32_t r = 0; r < reps; ++r) check(um_loop_exec(p, params, nparams, stream));
+                    UM_HIP(hipEventRecord(ev.e[1], s));
+                    UM_HIP(hipEventSynchronize(ev.e[1]));
+                    int32_t nerr = 0;
+                    check(um_plan_errors(p, &nerr));
+                    float ms = 0.f;
+                    UM_HIP(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+                    const double per = double(ms) / reps;
+                    if (nerr != 0) {
+                        um_plan_destroy(p);
+                        continue;
+                    }
+                    if (ms_out) ms_out[i] = per;
+                    if (!best || per < best_ms) {
+                        if (best) um_plan_destroy(best);
+                        best = p;
+                        best_ms = per;
+                        *best_index = i;
+                    } else {
+                        um_plan_destroy(p);
+                    }
+                } catch (...) {
+                    um_plan_destroy(p);
+                    throw;
+                }
+            }
+        } catch (...) {
+            if (best) um_plan_destroy(best);
+            *best_index = -1;
+            throw;
+        }
+        if (!best) fail(UM_ERR_UNSUPPORTED, "autotune: no candidate could be built");
+        *out = best;
     });
 }
 
@@ -750,6 +920,8 @@ um_status um_debug_fluxes(um_plan plan, const double *params, int32_t nparams, v
                           void *stream) {
     return guarded([&] {
         Plan &p = need(plan);
+        if (is_step_kernel(p.kernel))
+            fail(UM_ERR_UNSUPPORTED, "per-element debug output exists for the edge and hex loops only");
         LaunchArgs la = launch_args(p, params, nparams, stream);
         const Ctx &c = *p.ctx;
         const int64_t E = c.sets[p.iter_set].size;

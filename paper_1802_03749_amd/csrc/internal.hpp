@@ -89,6 +89,14 @@ struct HexArgs {
     int32_t dtype = UM_F64, layout = UM_AOS;
 };
 
+// Arguments of the other time-step loops (UM_K_CELL_ADT_2D,
+// UM_K_BOUNDARY_FLUX_2D, UM_K_UPDATE_2D); unused ids stay -1.
+struct StepArgs {
+    int32_t map_n = -1, map_c = -1;              // element->node, element->cell
+    int32_t dat_x = -1, dat_q = -1, dat_adt = -1, dat_res = -1, dat_rms = -1;
+    int32_t layout = UM_AOS;
+};
+
 // Per-block layout of a hierarchical plan, in launch order.
 struct BlockInfo {
     int32_t slot_off;   // first slot of the block
@@ -114,6 +122,7 @@ constexpr int32_t MAX_RUNS = 32;
 struct HostPlan {
     int32_t strategy = 0, staging = 0, tcmode = 0, block_size = 0;
     int32_t ept = 1, threads = 0;              // HIER: elements per lane, lanes per block
+    int32_t n_partials = 0;                    // UPDATE: workgroups of the first launch
     int32_t schedule = 0;                      // HIER: um_schedule
     int64_t n_elem = 0;
     // GLOBAL_COLOUR / ATOMIC: packed (L, R, a, b) per slot, slot order
@@ -144,6 +153,19 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
 void build_host_plan_hex(const Ctx &ctx, const HexArgs &ha, int32_t iter_set,
                          const um_plan_opts &o, HostPlan &hp);
 
+// Stable counting sort of 0..n-1 by small integer keys; returns the order
+// and fills offsets (size nkeys + 1).
+std::vector<int32_t> counting_order(const std::vector<int32_t> &key, int32_t nkeys,
+                                    std::vector<int32_t> &offsets);
+// First-fit colouring of the elements of `mc` (any arity) so that no two
+// elements of one colour share a point; returns the number of colours.
+int32_t global_colours(const Map &mc, int64_t n_points, std::vector<int32_t> &colour);
+
+StepArgs check_step_args(const Ctx &ctx, int32_t kernel, const um_arg *args, int32_t nargs,
+                         int32_t iter_set);
+void build_host_plan_step(const Ctx &ctx, int32_t kernel, const StepArgs &sa, int32_t iter_set,
+                          const um_plan_opts &o, HostPlan &hp);
+
 // LDS bytes a block needs for the given counts.
 int64_t lf2d_lds_bytes(int32_t staging, int32_t dtype, int64_t n_cells, int64_t n_nodes);
 int64_t hex_lds_bytes(int64_t n_nodes);
@@ -158,6 +180,7 @@ struct DevicePlan {
     int32_t *pred_off = nullptr, *preds = nullptr;  // DATAFLOW
     int32_t *flags = nullptr;                       // DATAFLOW: completion epochs per block
     int32_t *err = nullptr;                         // DATAFLOW: [timeouts, last execution, done, 0]
+    double *partials = nullptr;                     // UPDATE: one sum per workgroup
     int64_t bytes = 0;
 };
 
@@ -167,6 +190,7 @@ struct Plan {
     int32_t iter_set = 0;
     EdgeArgs ea;
     HexArgs ha;
+    StepArgs sa;
     HostPlan hp;
     DevicePlan dp;
     double build_seconds = 0.0;

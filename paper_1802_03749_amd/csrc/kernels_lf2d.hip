@@ -23,106 +23,18 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"
+#include "device_lf2d.hpp"
 #include "launch.hpp"
 
 namespace um {
 namespace {
 
-// Flux through an edge from cell L into cell R (formula in umesh.h),
-// evaluated in type Real.
-#define UM_LF2D_FLUX_BODY                                                      \
-    const Real half = Real(0.5), one = Real(1);                                \
-    const Real nx = xb1 - xa1;                                                 \
-    const Real ny = xa0 - xb0;                                                 \
-    Real FL[4], FR[4];                                                         \
-    {                                                                          \
-        const Real ri = one / qL[0];                                           \
-        const Real u = qL[1] * ri;                                             \
-        const Real v = qL[2] * ri;                                             \
-        const Real p = gm1 * (qL[3] - half * (qL[1] * u + qL[2] * v));         \
-        const Real U = u * nx + v * ny;                                        \
-        FL[0] = qL[0] * U;                                                     \
-        FL[1] = qL[1] * U + p * nx;                                            \
-        FL[2] = qL[2] * U + p * ny;                                            \
-        FL[3] = (qL[3] + p) * U;                                               \
-    }                                                                          \
-    {                                                                          \
-        const Real ri = one / qR[0];                                           \
-        const Real u = qR[1] * ri;                                             \
-        const Real v = qR[2] * ri;                                             \
-        const Real p = gm1 * (qR[3] - half * (qR[1] * u + qR[2] * v));         \
-        const Real U = u * nx + v * ny;                                        \
-        FR[0] = qR[0] * U;                                                     \
-        FR[1] = qR[1] * U + p * nx;                                            \
-        FR[2] = qR[2] * U + p * ny;                                            \
-        FR[3] = (qR[3] + p) * U;                                               \
-    }                                                                          \
-    const Real mu = eps * half * (adtL + adtR);                                \
-    _Pragma("unroll") for (int k = 0; k < 4; ++k)                              \
-        f[k] = half * (FL[k] + FR[k]) + half * mu * (qL[k] - qR[k]);
+using dev::lf2d_flux;
+using dev::lf2d_flux_nocontract;
+using dev::load2;
+using dev::load4;
+using dev::store4;
 
-template <typename Real>
-__device__ __forceinline__ void lf2d_flux(Real xa0, Real xa1, Real xb0, Real xb1,
-                                          const Real qL[4], const Real qR[4], Real adtL,
-                                          Real adtR, Real gm1, Real eps, Real f[4]) {
-    UM_LF2D_FLUX_BODY
-}
-
-template <typename Real>
-__device__ __forceinline__ void lf2d_flux_nocontract(Real xa0, Real xa1, Real xb0, Real xb1,
-                                                     const Real qL[4], const Real qR[4],
-                                                     Real adtL, Real adtR, Real gm1, Real eps,
-                                                     Real f[4]) {
-#pragma clang fp contract(off)
-    UM_LF2D_FLUX_BODY
-}
-
-// Element g of a dim-4 / dim-2 dat in AoS ([n][dim]) or SoA ([dim][n])
-// layout; AoS uses 16-byte vector loads.
-template <int LAYOUT, typename Real>
-__device__ __forceinline__ void load4(const Real *__restrict__ a, int64_t n, int64_t g,
-                                      Real v[4]) {
-    if constexpr (LAYOUT == UM_AOS) {
-        if constexpr (sizeof(Real) == 8) {
-            const double2 *p = reinterpret_cast<const double2 *>(a + 4 * g);
-            const double2 lo = p[0], hi = p[1];
-            v[0] = lo.x; v[1] = lo.y; v[2] = hi.x; v[3] = hi.y;
-        } else {
-            const float4 t = reinterpret_cast<const float4 *>(a)[g];
-            v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-        }
-    } else {
-        v[0] = a[g]; v[1] = a[n + g]; v[2] = a[2 * n + g]; v[3] = a[3 * n + g];
-    }
-}
-
-template <int LAYOUT>
-__device__ __forceinline__ void store4(double *__restrict__ a, int64_t n, int64_t g,
-                                       const double v[4]) {
-    if constexpr (LAYOUT == UM_AOS) {
-        double2 *p = reinterpret_cast<double2 *>(a + 4 * g);
-        p[0] = make_double2(v[0], v[1]);
-        p[1] = make_double2(v[2], v[3]);
-    } else {
-        a[g] = v[0]; a[n + g] = v[1]; a[2 * n + g] = v[2]; a[3 * n + g] = v[3];
-    }
-}
-
-template <int LAYOUT, typename Real>
-__device__ __forceinline__ void load2(const Real *__restrict__ a, int64_t n, int64_t g, Real &v0,
-                                      Real &v1) {
-    if constexpr (LAYOUT == UM_AOS) {
-        if constexpr (sizeof(Real) == 8) {
-            const double2 t = reinterpret_cast<const double2 *>(a)[g];
-            v0 = t.x; v1 = t.y;
-        } else {
-            const float2 t = reinterpret_cast<const float2 *>(a)[g];
-            v0 = t.x; v1 = t.y;
-        }
-    } else {
-        v0 = a[g]; v1 = a[n + g];
-    }
-}
 
 // LDS floating-point add without return (ds_add_f64).  Inside one colour
 // round no two lanes touch the same address, so the result equals a plain
@@ -334,6 +246,59 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
     }
 }
 
+// Device-coherent residual accesses of the DATAFLOW schedule.  Blocks that
+// hand residuals to each other may run on different XCDs, whose L2 caches
+// are not coherent with each other.  A device-scope fence pair would make
+// them coherent but writes back (release) and invalidates (acquire) the
+// whole L2 of the XCD, once per block.  Instead every residual load and
+// store of the schedule carries the device-scope cache policy (sc1) through
+// a buffer resource covering res: stores write through to the device
+// coherence point and loads do not return lines cached before, so only the
+// order of completion has to be enforced (s_waitcnt before the flag store,
+// the flag load before the residual loads).  The resource's record count is
+// the byte size of res (at most 2^31 - 1, checked when the plan is built);
+// an access outside it would be dropped by the hardware.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+constexpr int CPOL_SC1 = 16;  // device scope
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t res_rsrc(double *res, int64_t C) {
+    return __builtin_amdgcn_make_buffer_rsrc(res, 0, int32_t(32 * C), 0x00020000);
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void load4_dev(__amdgpu_buffer_rsrc_t r, int64_t C, int64_t g,
+                                          double v[4]) {
+    if constexpr (LAYOUT == UM_AOS) {
+        const int32_t off = int32_t(32 * g);
+        const f64x2 lo = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CPOL_SC1));
+        const f64x2 hi = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, off + 16, 0, CPOL_SC1));
+        v[0] = lo.x; v[1] = lo.y; v[2] = hi.x; v[3] = hi.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            v[k] = __builtin_bit_cast(
+                double, __builtin_amdgcn_raw_buffer_load_b64(r, int32_t(8 * (k * C + g)), 0, CPOL_SC1));
+    }
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void store4_dev(__amdgpu_buffer_rsrc_t r, int64_t C, int64_t g,
+                                           const double v[4]) {
+    if constexpr (LAYOUT == UM_AOS) {
+        const int32_t off = int32_t(32 * g);
+        const f64x2 lo = {v[0], v[1]}, hi = {v[2], v[3]};
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, lo), r, off, 0, CPOL_SC1);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, hi), r, off + 16, 0, CPOL_SC1);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v[k]), r,
+                                                  int32_t(8 * (k * C + g)), 0, CPOL_SC1);
+    }
+}
+
 // Longest a block waits for one predecessor before giving up (s_memrealtime
 // ticks at 100 MHz: 0.2 s).
 constexpr uint64_t FLOW_WAIT_TICKS = 20000000ull;
@@ -342,12 +307,12 @@ constexpr uint64_t FLOW_WAIT_TICKS = 20000000ull;
 // blockIdx.x).  Same per-block work as hier_kernel with STAGE_ALL and one
 // edge per lane, except that the residuals are loaded only after every
 // neighbouring block of an earlier colour has published its write-back.
-// Publication: all lanes finish their stores (s_waitcnt), the workgroup
-// meets at a barrier, then one lane issues a device-scope release fence and
-// stores the execution's epoch into the block's flag.  Consumption: lanes
-// of the first wavefront poll one predecessor flag each until it holds the
-// epoch, then issue a device-scope acquire fence before the barrier that
-// precedes the residual loads.  Blocks are dispatched in increasing
+// Publication: all lanes finish their device-scope residual stores
+// (s_waitcnt), the workgroup meets at a barrier, then one lane stores the
+// execution's epoch into the block's flag (device-scope atomic store).
+// Consumption: lanes of the first wavefront poll one predecessor flag each
+// (device-scope atomic loads) until it holds the epoch; the barrier after
+// the polls precedes the device-scope residual loads.  Blocks are dispatched in increasing
 // blockIdx order and a block only waits for smaller positions, so every
 // awaited block is already running or finished; the wait is bounded in time
 // anyway and a timeout is counted in ctl[0] instead of hanging.
@@ -448,18 +413,18 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
             __builtin_amdgcn_s_sleep(2);
         }
     }
-    if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     __syncthreads();
 
     // residuals as accumulators
+    const __amdgpu_buffer_rsrc_t rres = res_rsrc(d.res, d.C);
     for (int t0 = tid; t0 < nc; t0 += 2 * T) {
         const int t1 = t0 + T;
         const bool has1 = t1 < nc;
         const int64_t g0 = cell_id(t0);
         const int64_t g1 = has1 ? cell_id(t1) : g0;
         double r0[4], r1[4];
-        load4<LAYOUT>(d.res, d.C, g0, r0);
-        load4<LAYOUT>(d.res, d.C, g1, r1);
+        load4_dev<LAYOUT>(rres, d.C, g0, r0);
+        load4_dev<LAYOUT>(rres, d.C, g1, r1);
 #pragma unroll
         for (int k = 0; k < 4; ++k) s_inc[k * nc + t0] = r0[k];
         if (has1) {
@@ -496,13 +461,12 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
         double r[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) r[k] = s_inc[k * nc + t];
-        store4<LAYOUT>(d.res, d.C, cell_id(t), r);
+        store4_dev<LAYOUT>(rres, d.C, cell_id(t), r);
     }
-    // publish: every lane's stores complete, then one release + flag store
+    // publish: every lane's stores complete, then one flag store
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __hip_atomic_store(flags + pos, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const int32_t done =
             __hip_atomic_fetch_add(ctl + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

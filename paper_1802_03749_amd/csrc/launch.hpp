@@ -8,7 +8,7 @@
 namespace um {
 
 enum { LAUNCH_HIER = 0, LAUNCH_GCOL = 1, LAUNCH_ATOMIC = 2, LAUNCH_DEBUG = 3,
-       LAUNCH_HIER_FLOW = 4 };
+       LAUNCH_HIER_FLOW = 4, LAUNCH_DIRECT = 5, LAUNCH_REDUCE = 6 };
 
 struct LaunchArgs {
     hipStream_t stream;
@@ -26,6 +26,10 @@ struct LaunchArgs {
     int32_t schedule;
     const int32_t *pred_off, *preds;
     int32_t *flags, *err;  // DATAFLOW: completion flags; err = control words [4]
+    double qinf[4];        // BOUNDARY_FLUX: far-field state
+    double *partials;      // UPDATE: per-workgroup sums
+    double *gbl;           // UPDATE: the global reduction target
+    int32_t n_partials;
 };
 
 // One kernel launch of the LF2D loop: HIER covers launch positions
@@ -38,6 +42,14 @@ hipError_t lf2d_launch_one(const LaunchArgs &la, int which, int32_t begin, int32
 // gm1; emap holds 8 node ids per slot).
 hipError_t hex_launch_one(const LaunchArgs &la, int which, int32_t begin, int32_t end,
                           int64_t lds_bytes);
+
+// One launch of a time-step loop (`kernel` a um_kernel value).  ADT:
+// DIRECT over cells [0, end).  BOUNDARY_FLUX: GCOL over slots [begin, end)
+// of one colour or ATOMIC over [0, end); emap holds (cell, a, b, 0) per
+// slot.  UPDATE: DIRECT over cells [0, end) writing n_partials sums, then
+// REDUCE adding their sum to gbl.  x, q and adt are double.
+hipError_t step_launch_one(const LaunchArgs &la, int32_t kernel, int which, int32_t begin,
+                           int32_t end);
 
 // dst[k] = src[idx[k]] for k < n over dim components (gather).
 hipError_t permute_gather(const void *src, void *dst, const int32_t *idx, int64_t n, int32_t dim,

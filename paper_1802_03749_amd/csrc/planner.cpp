@@ -2,6 +2,7 @@
 // two-layer (block + thread) colouring with staged point lists and local
 // index maps (paper Section 2.1 and 2.2, Algorithm 1), LDS sizing.
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <numeric>
 
@@ -17,8 +18,6 @@ int64_t lf2d_lds_bytes(int32_t staging, int32_t dtype, int64_t nc, int64_t nn) {
     const int64_t w = dtype == UM_F64 ? 8 : 4;
     return inc + nc * 5 * w + nn * 2 * w;  // q[4], adt per cell; x[2] per node
 }
-
-namespace {
 
 // Stable counting sort of 0..n-1 by small integer keys; returns the order
 // and fills offsets[key] (size nkeys + 1).
@@ -66,18 +65,23 @@ int32_t global_colours(const Map &mc, int64_t C, std::vector<int32_t> &colour) {
     return ncol;
 }
 
-}  // namespace
-
 // Blocks, layer-1 colouring, launch order and dataflow predecessors: the
 // part of a hierarchical plan that only depends on which points each
 // element writes (wt: [E][arity] into 0..C-1).  Returns the colour count.
 int32_t plan_blocks(const Ctx &ctx, int32_t iter_set, const int32_t *wt, int arity, int64_t C,
                     const um_plan_opts &o, HostPlan &hp) {
     const int64_t E = ctx.sets[iter_set].size;
-    // ---- blocks: the set's partition if built for this size, else chunks
+    // ---- blocks: the set's partition if built for this size; groups of k
+    // consecutive partition blocks if built for block_size / k (bisection
+    // order keeps consecutive blocks adjacent in space); else chunks
     const Set &is = ctx.sets[iter_set];
-    if (is.part_block_size == o.block_size && !is.part_off.empty()) {
-        hp.blk_off = is.part_off;
+    const int32_t pbs = is.part_block_size;
+    if (pbs > 0 && !is.part_off.empty() && o.block_size % pbs == 0) {
+        const int32_t k = o.block_size / pbs;
+        const int32_t npb = int32_t(is.part_off.size()) - 1;
+        hp.blk_off.clear();
+        for (int32_t b = 0; b < npb; b += k) hp.blk_off.push_back(is.part_off[b]);
+        hp.blk_off.push_back(is.part_off[npb]);
     } else {
         hp.blk_off.clear();
         for (int64_t s = 0; s < E; s += o.block_size) hp.blk_off.push_back(int32_t(s));
@@ -352,6 +356,9 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     }
     if (hp.schedule == UM_SCHED_DATAFLOW && (hp.staging != UM_STAGE_ALL || hp.ept != 1))
         fail(UM_ERR_UNSUPPORTED, "dataflow schedule needs STAGE_ALL staging and one element per lane");
+    if (hp.schedule == UM_SCHED_DATAFLOW && 32 * C > int64_t(INT32_MAX))
+        fail(UM_ERR_UNSUPPORTED, "dataflow schedule addresses res with 32-bit byte offsets: "
+             "at most %lld cells", (long long)(int64_t(INT32_MAX) / 32));
     if (hp.staging == UM_STAGE_INC_ONLY && need_inc > limit)
         fail(UM_ERR_LDS, "staging increments needs %lld bytes of LDS per block, limit %lld",
              (long long)need_inc, (long long)limit);

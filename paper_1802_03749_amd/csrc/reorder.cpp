@@ -392,6 +392,10 @@ void reorder_mesh(Ctx &ctx, const um_reorder_opts &o) {
         }
         return;
     }
+    if (o.mode == UM_REORDER_LEXICOGRAPHIC) {
+        apply_set_perm(ctx, F, lexicographic_elements(ctx.maps[o.driving_map]));
+        return;
+    }
     if (o.mode != UM_REORDER_PARTITION) fail(UM_ERR_ARG, "reorder: unknown mode %d", o.mode);
     if (o.block_size < 1 || o.block_size > 1024)
         fail(UM_ERR_ARG, "reorder: block_size %d outside 1..1024", o.block_size);

@@ -27,12 +27,15 @@ UM_AOS, UM_SOA = 0, 1
 UM_READ, UM_WRITE, UM_RW, UM_INC = 0, 1, 2, 3
 UM_STRAT_ATOMIC, UM_STRAT_GLOBAL_COLOUR, UM_STRAT_HIER = 0, 1, 2
 UM_REORDER_NONE, UM_REORDER_RCM, UM_REORDER_GPS, UM_REORDER_PARTITION = 0, 1, 2, 3
+UM_REORDER_LEXICOGRAPHIC = 4
 UM_STAGE_ALL, UM_STAGE_INC_ONLY = 0, 1
 UM_TC_BARRIER, UM_TC_LDS_ATOMIC = 0, 1
 UM_BCOL_FIRST_FIT, UM_BCOL_RECOLOUR = 0, 1
 UM_SCHED_COLOUR_LAUNCHES, UM_SCHED_DATAFLOW = 0, 1
 UM_K_EDGE_FLUX_LF2D, UM_K_HEX_HOURGLASS_3D = 0, 1
+UM_K_CELL_ADT_2D, UM_K_BOUNDARY_FLUX_2D, UM_K_UPDATE_2D = 2, 3, 4
 UM_ALL_SLOTS = -1
+UM_GLOBAL = -2
 (UM_EXP_BLOCK_OFFSETS, UM_EXP_BLOCK_COLOURS, UM_EXP_THREAD_COLOURS, UM_EXP_SLOT_ELEMENTS,
  UM_EXP_GLOBAL_COLOURS, UM_EXP_STAGED_OFFSETS_A, UM_EXP_STAGED_POINTS_A,
  UM_EXP_STAGED_OFFSETS_B, UM_EXP_STAGED_POINTS_B, UM_EXP_LOCAL_INDEX,
@@ -106,6 +109,8 @@ _SIGNATURES = {
     "um_get_blocks": [_P, _I32, _PI32, _PI32, _P, _I64],
     "um_permute_dat": [_P, _I32, _I32, _P, _P, _I32, _I32, _I32, _P],
     "um_plan_build": [_P, _I32, ct.POINTER(um_arg), _I32, _I32, ct.POINTER(um_plan_opts), ct.POINTER(_P)],
+    "um_plan_autotune": [_P, _I32, ct.POINTER(um_arg), _I32, _I32, ct.POINTER(um_plan_opts), _I32,
+                         _P, _I32, _P, _I32, _PI32, _P, ct.POINTER(_P)],
     "um_plan_stats_get": [_P, ct.POINTER(um_plan_stats)],
     "um_plan_export": [_P, _I32, _P, _I64, _PI64],
     "um_plan_destroy": [_P],
@@ -241,6 +246,22 @@ def um_plan_build(ctx: int, kernel: int, args, iter_set: int, opts: um_plan_opts
     _check(lib().um_plan_build(ctx, kernel, arr, len(args), iter_set, ct.byref(opts), ct.byref(h)),
            "um_plan_build")
     return h.value
+
+
+def um_plan_autotune(ctx: int, kernel: int, args, iter_set: int, candidates, params, stream: int,
+                     reps: int = 5):
+    """(plan handle, index of the chosen candidate, ms per execution of each)."""
+    arr = (um_arg * len(args))(*args)
+    cand = (um_plan_opts * len(candidates))(*candidates)
+    p = (ct.c_double * max(len(params), 1))(*params)
+    ms = (ct.c_double * len(candidates))()
+    best = ct.c_int32(-1)
+    h = _P()
+    _check(lib().um_plan_autotune(ctx, kernel, arr, len(args), iter_set, cand, len(candidates),
+                                  ct.cast(p, ct.c_void_p), len(params), stream, reps,
+                                  ct.byref(best), ct.cast(ms, ct.c_void_p), ct.byref(h)),
+           "um_plan_autotune")
+    return h.value, best.value, list(ms)
 
 
 def um_plan_stats_get(plan: int) -> um_plan_stats:

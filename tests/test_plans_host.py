@@ -371,3 +371,19 @@ def test_hex_args_checked():
     with pytest.raises(U.UmeshError) as ei:
         U.um_plan_build(L.ctx, U.UM_K_HEX_HOURGLASS_3D, bad, L.s_elems, o)
     assert ei.value.status == U.UM_ERR_ARITY
+
+
+@pytest.mark.parametrize("S,k", [(256, 2), (256, 4), (128, 3)])
+def test_hier_plan_merges_partition_blocks_for_multiples(S, k):
+    """A plan for k * S on a mesh partitioned for S uses groups of k
+    consecutive partition blocks; other sizes fall back to chunks."""
+    m, L = make(nx=48, ny=30, order="rcm+partition", block_size=S)
+    part = L.part_blocks()
+    p = L.plan("hier", k * S)
+    off = L.export(p, U.UM_EXP_BLOCK_OFFSETS)
+    assert P.check_block_offsets(off, L.E, k * S) is None
+    want = np.concatenate([part[:-1][::k], part[-1:]])
+    assert np.array_equal(off, want)
+    p2 = L.plan("hier", S + 64)
+    off2 = L.export(p2, U.UM_EXP_BLOCK_OFFSETS)
+    assert np.array_equal(off2, np.append(np.arange(0, L.E, S + 64), L.E))
