@@ -13,8 +13,10 @@ Prints one JSON line to stdout; progress goes to stderr.  Besides the
 headline it reports: the global-colouring and atomics baselines on the same
 GPU and mesh (reverse Cuthill-McKee order, their best), the FP32-storage
 variant, the 3D hexahedral element loop (128^3 elements) with its own
-baselines, a plain device-copy bandwidth probe, and the CPU oracle timed on
-the host as the CPU baseline.
+baselines, a batch of 64 meshes of uneven size (5k-500k cells) advanced by
+full time steps as one union and one mesh at a time (eager and replayed
+from a captured HIP graph), a plain device-copy bandwidth probe, and the
+CPU oracle timed on the host as the CPU baseline.
 """
 from __future__ import annotations
 
@@ -24,6 +26,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "edges/s and achieved HBM GB/s (% peak) vs atomics/global-colour, FP64 and FP32"
@@ -93,7 +97,9 @@ def main() -> int:
     ap.add_argument("--no-baselines", action="store_true",
                     help="skip the global-colour and atomics baselines")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the FP32 variant and the 3D hex workload")
+                    help="skip the FP32 variant, the 3D hex workload and the batch")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batch of 64 meshes")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -220,6 +226,40 @@ def main() -> int:
             log(f"hex {strat}: {s * 1e6:.1f} us/step ({hb / s / 1e9:.0f} GB/s)")
             H.close()
         extras["hex_hourglass_128cubed"] = hx
+
+    if not args.no_extras and not args.no_batched:
+        # 64 meshes of log-uniform size 5k-500k cells, one full time step
+        # (adt, edge flux, boundary flux, update + sum of squares) per mesh
+        from meshgen import quad_batch
+        from paper_1802_03749_amd.batched import BatchedSteps
+        t = time.perf_counter()
+        ms = quad_batch(64, c_min=5e3, c_max=5e5, size_seed=5)
+        qinf = np.array([1.0, 0.35, 0.05, 2.7])
+        bx = {"meshes": len(ms), "cells": int(sum(m.q.shape[0] for m in ms)),
+              "interior_edges": int(sum(m.e2n.shape[0] for m in ms)),
+              "boundary_edges": int(sum(m.b2n.shape[0] for m in ms))}
+        log(f"batch of {len(ms)} meshes: {bx['cells']} cells, generated in "
+            f"{time.perf_counter() - t:.1f}s")
+        bsteps = max(args.steps // 20, 5)
+        for mode in ("union", "sequential"):
+            t = time.perf_counter()
+            B = BatchedSteps(ms, qinf, mode=mode)
+            setup = time.perf_counter() - t
+            eager = time_steps(torch, B.step, bsteps, 2)
+            B.capture()
+            graph = time_steps(torch, B.replay, bsteps, 2)
+            launches = sum(sum(p.stats["n_launches"] for p in ts.plans.values()) for ts in B.steps)
+            bx[mode] = {"ms_per_step_eager": eager * 1e3, "ms_per_step_graph": graph * 1e3,
+                        "edges_per_s_graph": bx["interior_edges"] / graph,
+                        "cells_per_s_graph": bx["cells"] / graph,
+                        "launches_per_step": launches, "setup_seconds": setup,
+                        "tuned": {str(k): v[0] for k, v in B.tuned.items()}}
+            log(f"batched {mode}: eager {eager * 1e3:.3f} ms, graph {graph * 1e3:.3f} ms per step, "
+                f"{launches} launches")
+            B.close()
+        bx["union_speedup_vs_sequential_graph"] = (bx["sequential"]["ms_per_step_graph"]
+                                                  / bx["union"]["ms_per_step_graph"])
+        extras["batched_64_meshes_fp64"] = bx
 
     # ---- CPU baseline: the oracle's sequential loop on the host
     cpu = None

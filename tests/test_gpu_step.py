@@ -213,3 +213,26 @@ def test_autotuned_flux_plan():
     _, _, rms = o.step()
     assert rel_l2(ts.q_user(), o.q) <= TOL
     assert abs(ts.rms.item() / rms - 1) <= TOL
+
+
+@pytest.mark.parametrize("mode", ["union", "sequential"])
+def test_batched_steps_match_oracle(mode):
+    """Both batched executors, eager and graph-replayed: every mesh's state
+    after two steps equals two oracle steps of that mesh."""
+    from paper_1802_03749_amd.batched import BatchedSteps
+    ms = quad_batch(8, c_min=300, c_max=5000, size_seed=4)
+    bs = BatchedSteps(ms, QINF, mode=mode, tune_reps=2)
+    bs.step()
+    bs.capture()
+    bs.replay()
+    torch.cuda.synchronize()
+    got = bs.q_user()
+    total = 0.0
+    for k, m in enumerate(ms):
+        o = MeshState(m)
+        for _ in range(2):
+            _, _, rms = o.step()
+            total += rms
+        assert rel_l2(got[k], o.q) <= TOL, k
+    assert abs(bs.rms_total() / total - 1) <= TOL
+    bs.close()
