@@ -241,25 +241,28 @@ def main() -> int:
         log(f"batch of {len(ms)} meshes: {bx['cells']} cells, generated in "
             f"{time.perf_counter() - t:.1f}s")
         bsteps = max(args.steps // 20, 5)
-        for mode in ("union", "sequential"):
-            t = time.perf_counter()
-            B = BatchedSteps(ms, qinf, mode=mode)
-            setup = time.perf_counter() - t
-            eager = time_steps(torch, B.step, bsteps, 2)
-            B.capture()
-            graph = time_steps(torch, B.replay, bsteps, 2)
-            launches = sum(sum(p.stats["n_launches"] for p in ts.plans.values()) for ts in B.steps)
-            bx[mode] = {"ms_per_step_eager": eager * 1e3, "ms_per_step_graph": graph * 1e3,
-                        "edges_per_s_graph": bx["interior_edges"] / graph,
-                        "cells_per_s_graph": bx["cells"] / graph,
-                        "launches_per_step": launches, "setup_seconds": setup,
-                        "tuned": {str(k): v[0] for k, v in B.tuned.items()}}
-            log(f"batched {mode}: eager {eager * 1e3:.3f} ms, graph {graph * 1e3:.3f} ms per step, "
-                f"{launches} launches")
-            B.close()
-        bx["union_speedup_vs_sequential_graph"] = (bx["sequential"]["ms_per_step_graph"]
-                                                  / bx["union"]["ms_per_step_graph"])
-        extras["batched_64_meshes_fp64"] = bx
+        for dt in ("f64", "f32"):
+            for mode in ("union", "sequential"):
+                t = time.perf_counter()
+                B = BatchedSteps(ms, qinf, mode=mode, dtype=dt)
+                setup = time.perf_counter() - t
+                eager = time_steps(torch, B.step, bsteps, 2)
+                B.capture()
+                graph = time_steps(torch, B.replay, bsteps, 2)
+                launches = sum(sum(p.stats["n_launches"] for p in ts.plans.values())
+                               for ts in B.steps)
+                bx[f"{mode}_{dt}"] = {
+                    "ms_per_step_eager": eager * 1e3, "ms_per_step_graph": graph * 1e3,
+                    "edges_per_s_graph": bx["interior_edges"] / graph,
+                    "cells_per_s_graph": bx["cells"] / graph,
+                    "launches_per_step": launches, "setup_seconds": setup,
+                    "tuned": {str(k): v[0] for k, v in B.tuned.items()}}
+                log(f"batched {mode} {dt}: eager {eager * 1e3:.3f} ms, graph {graph * 1e3:.3f} ms "
+                    f"per step, {launches} launches")
+                B.close()
+            bx[f"union_speedup_vs_sequential_graph_{dt}"] = (
+                bx[f"sequential_{dt}"]["ms_per_step_graph"] / bx[f"union_{dt}"]["ms_per_step_graph"])
+        extras["batched_64_meshes"] = bx
 
     # ---- CPU baseline: the oracle's sequential loop on the host
     cpu = None

@@ -44,6 +44,14 @@ def lib():
         L.oracle_bres_loop.restype = None
         L.oracle_update_loop.argtypes = [ct.c_int64, P, P, P]
         L.oracle_update_loop.restype = ct.c_double
+        L.oracle_cell_adt_f32.argtypes = [P, P, ct.c_float]
+        L.oracle_cell_adt_f32.restype = ct.c_float
+        L.oracle_adt_loop_f32.argtypes = [ct.c_int64, P, P, P, ct.c_double, P]
+        L.oracle_adt_loop_f32.restype = None
+        L.oracle_bres_loop_f32.argtypes = [ct.c_int64, P, P, P, P, P, P, ct.c_double, ct.c_double, P]
+        L.oracle_bres_loop_f32.restype = None
+        L.oracle_update_loop_f32.argtypes = [ct.c_int64, P, P, P]
+        L.oracle_update_loop_f32.restype = ct.c_double
         L.oracle_first_fit.argtypes = [ct.c_int64, P, P, ct.c_int64, ct.c_int32,
                                        P, P, P, P, P]
         L.oracle_first_fit.restype = ct.c_int32
@@ -180,4 +188,44 @@ def time_step(m, qinf, gm1=GM1, eps=EPS_D):
     res = edge_loop(m.e2n, m.e2c, m.x, m.q, adt, gm1, eps)
     res = bres_loop(m.b2n, m.b2c, m.x, m.q, adt, qinf, gm1, eps, res)
     q_new, _, rms = update_loop(m.q, res, adt)
+    return q_new, adt, rms
+
+
+# ---- binary32 storage variant of the time step (inputs rounded to binary32)
+def cell_adt_f32(xc, q, gm1=GM1) -> float:
+    xc = _c(xc, np.float32); q = _c(q, np.float32)
+    return float(lib().oracle_cell_adt_f32(_p(xc), _p(q), float(np.float32(gm1))))
+
+
+def adt_loop_f32(c2n, x, q, gm1=GM1) -> np.ndarray:
+    c2n = _c(c2n, np.int32); x = _c(x, np.float32); q = _c(q, np.float32)
+    adt = np.zeros(q.shape[0], np.float32)
+    lib().oracle_adt_loop_f32(q.shape[0], _p(c2n), _p(x), _p(q), float(gm1), _p(adt))
+    return adt
+
+
+def bres_loop_f32(b2n, b2c, x, q, adt, qinf, gm1=GM1, eps=EPS_D, res=None) -> np.ndarray:
+    b2n = _c(b2n, np.int32); b2c = _c(b2c, np.int32).ravel()
+    x = _c(x, np.float32); q = _c(q, np.float32); adt = _c(adt, np.float32)
+    qinf = _c(qinf, np.float32)
+    out = np.zeros((q.shape[0], 4)) if res is None else _c(res, np.float64).copy()
+    lib().oracle_bres_loop_f32(b2n.shape[0], _p(b2n), _p(b2c), _p(x), _p(q), _p(adt), _p(qinf),
+                               float(gm1), float(eps), _p(out))
+    return out
+
+
+def update_loop_f32(q, res, adt):
+    """(q_new binary32, res zeroed, rms) after the binary32-storage update."""
+    q = _c(q, np.float32).copy(); res = _c(res, np.float64).copy(); adt = _c(adt, np.float32)
+    rms = lib().oracle_update_loop_f32(q.shape[0], _p(q), _p(res), _p(adt))
+    return q, res, float(rms)
+
+
+def time_step_f32(m, qinf, q=None, gm1=GM1, eps=EPS_D):
+    """One binary32-storage time step: (q_new binary32, adt binary32, rms)."""
+    q = m.q if q is None else q
+    adt = adt_loop_f32(m.c2n, m.x, q, gm1)
+    res, _ = edge_loop_f32(m.e2n, m.e2c, m.x, q, adt, gm1, eps)
+    res = bres_loop_f32(m.b2n, m.b2c, m.x, q, adt, qinf, gm1, eps, res)
+    q_new, _, rms = update_loop_f32(q, res, adt)
     return q_new, adt, rms

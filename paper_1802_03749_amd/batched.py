@@ -41,7 +41,7 @@ def size_bucket(n_edges: int) -> int:
 class BatchedSteps:
     def __init__(self, meshes, qinf, *, mode: str = "union", device: int = 0,
                  partition_block: int = 256, candidates=DEFAULT_CANDIDATES, tune_reps: int = 5,
-                 union_spacing: float = 8192.0):
+                 union_spacing: float = 8192.0, dtype: str = "f64"):
         if mode not in ("union", "sequential"):
             raise ValueError(mode)
         self.mode = mode
@@ -54,7 +54,7 @@ class BatchedSteps:
             u = union(self.meshes, spacing=union_spacing)
             self.union = u
             ts = TimeStep2D(u.x, u.q, u.e2n, u.e2c, u.b2n, u.b2c, u.c2n, qinf, device=device,
-                            block_size=partition_block)
+                            block_size=partition_block, dtype=dtype)
             ts.build_plans(flux_block_size=partition_block)
             ts.run_loop("adt")
             best, ms = ts.autotune_flux(self.candidates, tune_reps)
@@ -64,7 +64,7 @@ class BatchedSteps:
             self.steps = []
             for m in self.meshes:
                 ts = TimeStep2D(m.x, m.q, m.e2n, m.e2c, m.b2n, m.b2c, m.c2n, qinf,
-                                device=device, block_size=partition_block)
+                                device=device, block_size=partition_block, dtype=dtype)
                 b = size_bucket(ts.E)
                 if b not in self.tuned:
                     ts.build_plans(flux_block_size=partition_block)

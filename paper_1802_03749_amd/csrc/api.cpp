@@ -208,7 +208,7 @@ LaunchArgs launch_args_step(Plan &p, const double *params, int32_t nparams, void
     LaunchArgs la{};
     la.stream = static_cast<hipStream_t>(stream);
     la.layout = p.sa.layout;
-    la.dtype = UM_F64;
+    la.dtype = p.sa.dtype;
     la.block_size = p.hp.block_size;
     la.emap = p.dp.emap;
     const StepArgs &sa = p.sa;

@@ -95,6 +95,7 @@ struct StepArgs {
     int32_t map_n = -1, map_c = -1;              // element->node, element->cell
     int32_t dat_x = -1, dat_q = -1, dat_adt = -1, dat_res = -1, dat_rms = -1;
     int32_t layout = UM_AOS;
+    int32_t dtype = UM_F64;                      // of x, q and adt
 };
 
 // Per-block layout of a hierarchical plan, in launch order.

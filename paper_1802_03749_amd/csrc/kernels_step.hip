@@ -27,42 +27,60 @@ using dev::load2;
 using dev::load4;
 using dev::store4;
 
-template <int LAYOUT>
-__global__ __launch_bounds__(1024) void adt_kernel(const double *__restrict__ x,
-                                                   const double *__restrict__ q,
-                                                   double *__restrict__ adt,
+// Store of a dim-4 element in type Real (AoS: 16-byte vector stores).
+template <int LAYOUT, typename Real>
+__device__ __forceinline__ void store4r(Real *__restrict__ a, int64_t n, int64_t g,
+                                        const Real v[4]) {
+    if constexpr (LAYOUT == UM_AOS) {
+        if constexpr (sizeof(Real) == 8) {
+            store4<LAYOUT>(reinterpret_cast<double *>(a), n, g, reinterpret_cast<const double *>(v));
+        } else {
+            reinterpret_cast<float4 *>(a)[g] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+    } else {
+        a[g] = v[0]; a[n + g] = v[1]; a[2 * n + g] = v[2]; a[3 * n + g] = v[3];
+    }
+}
+
+// Cell time-step scalar, evaluated in the storage type Real.
+template <int LAYOUT, typename Real>
+__global__ __launch_bounds__(1024) void adt_kernel(const Real *__restrict__ x,
+                                                   const Real *__restrict__ q,
+                                                   Real *__restrict__ adt,
                                                    const int4 *__restrict__ c2n, int64_t N,
-                                                   int64_t C, double gm1) {
+                                                   int64_t C, double gm1d) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= C) return;
+    const Real gm1 = Real(gm1d), half = Real(0.5), one = Real(1);
     const int4 nd = c2n[c];
-    double px[4], py[4];
+    Real px[4], py[4];
     load2<LAYOUT>(x, N, nd.x, px[0], py[0]);
     load2<LAYOUT>(x, N, nd.y, px[1], py[1]);
     load2<LAYOUT>(x, N, nd.z, px[2], py[2]);
     load2<LAYOUT>(x, N, nd.w, px[3], py[3]);
-    double qc[4];
+    Real qc[4];
     load4<LAYOUT>(q, C, c, qc);
-    const double ri = 1.0 / qc[0];
-    const double u = qc[1] * ri;
-    const double v = qc[2] * ri;
-    const double p = gm1 * (qc[3] - 0.5 * (qc[1] * u + qc[2] * v));
-    const double cs = sqrt((1.0 + gm1) * p * ri);
-    double s = 0.0;
+    const Real ri = one / qc[0];
+    const Real u = qc[1] * ri;
+    const Real v = qc[2] * ri;
+    const Real p = gm1 * (qc[3] - half * (qc[1] * u + qc[2] * v));
+    const Real cs = sqrt((one + gm1) * p * ri);
+    Real s = Real(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int k1 = (k + 1) & 3;
-        const double mx = py[k1] - py[k];
-        const double my = px[k] - px[k1];
+        const Real mx = py[k1] - py[k];
+        const Real my = px[k] - px[k1];
         s = s + (fabs(u * mx + v * my) + cs * sqrt(mx * mx + my * my));
     }
     adt[c] = s;
 }
 
-template <int LAYOUT, bool ATOMIC>
-__global__ __launch_bounds__(1024) void bres_kernel(const double *__restrict__ x,
-                                                    const double *__restrict__ q,
-                                                    const double *__restrict__ adt,
+// Far-field boundary flux, evaluated in Real; increments in double.
+template <int LAYOUT, bool ATOMIC, typename Real>
+__global__ __launch_bounds__(1024) void bres_kernel(const Real *__restrict__ x,
+                                                    const Real *__restrict__ q,
+                                                    const Real *__restrict__ adt,
                                                     double *__restrict__ res,
                                                     const int4 *__restrict__ emap, int32_t begin,
                                                     int32_t end, int64_t N, int64_t C, double gm1,
@@ -72,23 +90,24 @@ __global__ __launch_bounds__(1024) void bres_kernel(const double *__restrict__ x
     if (s >= end) return;
     const int4 m = emap[s];
     const int c = m.x;
-    double qc[4], xa0, xa1, xb0, xb1;
+    Real qc[4], xa0, xa1, xb0, xb1;
     load4<LAYOUT>(q, C, c, qc);
     load2<LAYOUT>(x, N, m.y, xa0, xa1);
     load2<LAYOUT>(x, N, m.z, xb0, xb1);
-    const double a = adt[c];
-    const double qi[4] = {qi0, qi1, qi2, qi3};
-    double f[4];
-    lf2d_flux<double>(xa0, xa1, xb0, xb1, qc, qi, a, a, gm1, eps, f);
+    const Real a = adt[c];
+    const Real qi[4] = {Real(qi0), Real(qi1), Real(qi2), Real(qi3)};
+    Real f[4];
+    lf2d_flux<Real>(xa0, xa1, xb0, xb1, qc, qi, a, a, Real(gm1), Real(eps), f);
     if constexpr (ATOMIC) {
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-            unsafeAtomicAdd(LAYOUT == UM_AOS ? &res[4 * int64_t(c) + k] : &res[k * C + c], f[k]);
+            unsafeAtomicAdd(LAYOUT == UM_AOS ? &res[4 * int64_t(c) + k] : &res[k * C + c],
+                            double(f[k]));
     } else {
         double r[4];
         load4<LAYOUT>(res, C, c, r);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) r[k] += f[k];
+        for (int k = 0; k < 4; ++k) r[k] += double(f[k]);
         store4<LAYOUT>(res, C, c, r);
     }
 }
@@ -115,26 +134,28 @@ __device__ __forceinline__ double block_sum(double v) {
     return t;
 }
 
-template <int LAYOUT>
-__global__ __launch_bounds__(1024) void update_kernel(double *__restrict__ q,
+// Update: d = res / adt in double, q rounded once to its storage type.
+template <int LAYOUT, typename Real>
+__global__ __launch_bounds__(1024) void update_kernel(Real *__restrict__ q,
                                                       double *__restrict__ res,
-                                                      const double *__restrict__ adt,
+                                                      const Real *__restrict__ adt,
                                                       double *__restrict__ partials, int64_t C) {
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     double acc = 0.0;
     if (c < C) {
-        double qc[4], r[4];
+        Real qc[4];
+        double r[4];
         load4<LAYOUT>(q, C, c, qc);
         load4<LAYOUT>(res, C, c, r);
-        const double a = adt[c];
+        const double a = double(adt[c]);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const double d = r[k] / a;
-            qc[k] = qc[k] - d;
+            qc[k] = Real(double(qc[k]) - d);
             acc = acc + d * d;
             r[k] = 0.0;
         }
-        store4<LAYOUT>(q, C, c, qc);
+        store4r<LAYOUT>(q, C, c, qc);
         store4<LAYOUT>(res, C, c, r);
     }
     const double t = block_sum(acc);
@@ -151,31 +172,31 @@ __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__
 
 int32_t grid_for(int64_t n, int32_t bs) { return int32_t((n + bs - 1) / bs); }
 
-template <int LAYOUT>
-hipError_t launch_layout(const LaunchArgs &la, int32_t kernel, int which, int32_t begin,
-                         int32_t end) {
+template <int LAYOUT, typename Real>
+hipError_t launch_typed(const LaunchArgs &la, int32_t kernel, int which, int32_t begin,
+                        int32_t end) {
     const int32_t bs = la.block_size;
-    const double *x = static_cast<const double *>(la.x);
-    const double *q = static_cast<const double *>(la.q);
-    const double *adt = static_cast<const double *>(la.adt);
+    const Real *x = static_cast<const Real *>(la.x);
+    const Real *q = static_cast<const Real *>(la.q);
+    const Real *adt = static_cast<const Real *>(la.adt);
     const int64_t n = int64_t(end) - begin;
     if (n <= 0) return hipSuccess;
     if (kernel == UM_K_CELL_ADT_2D && which == LAUNCH_DIRECT) {
-        adt_kernel<LAYOUT><<<grid_for(n, bs), bs, 0, la.stream>>>(
-            x, q, const_cast<double *>(adt), reinterpret_cast<const int4 *>(la.emap), la.N, la.C,
+        adt_kernel<LAYOUT, Real><<<grid_for(n, bs), bs, 0, la.stream>>>(
+            x, q, const_cast<Real *>(adt), reinterpret_cast<const int4 *>(la.emap), la.N, la.C,
             la.gm1);
     } else if (kernel == UM_K_BOUNDARY_FLUX_2D && which == LAUNCH_GCOL) {
-        bres_kernel<LAYOUT, false><<<grid_for(n, bs), bs, 0, la.stream>>>(
+        bres_kernel<LAYOUT, false, Real><<<grid_for(n, bs), bs, 0, la.stream>>>(
             x, q, adt, la.res, reinterpret_cast<const int4 *>(la.emap), begin, end, la.N, la.C,
             la.gm1, la.eps, la.qinf[0], la.qinf[1], la.qinf[2], la.qinf[3]);
     } else if (kernel == UM_K_BOUNDARY_FLUX_2D && which == LAUNCH_ATOMIC) {
-        bres_kernel<LAYOUT, true><<<grid_for(n, bs), bs, 0, la.stream>>>(
+        bres_kernel<LAYOUT, true, Real><<<grid_for(n, bs), bs, 0, la.stream>>>(
             x, q, adt, la.res, reinterpret_cast<const int4 *>(la.emap), begin, end, la.N, la.C,
             la.gm1, la.eps, la.qinf[0], la.qinf[1], la.qinf[2], la.qinf[3]);
     } else if (kernel == UM_K_UPDATE_2D && which == LAUNCH_DIRECT) {
         if (grid_for(n, bs) != la.n_partials) return hipErrorInvalidValue;
-        update_kernel<LAYOUT><<<la.n_partials, bs, 0, la.stream>>>(
-            const_cast<double *>(q), la.res, adt, la.partials, la.C);
+        update_kernel<LAYOUT, Real><<<la.n_partials, bs, 0, la.stream>>>(
+            const_cast<Real *>(q), la.res, adt, la.partials, la.C);
     } else if (kernel == UM_K_UPDATE_2D && which == LAUNCH_REDUCE) {
         reduce_kernel<<<1, 1024, 0, la.stream>>>(la.partials, la.n_partials, la.gbl);
     } else {
@@ -188,8 +209,11 @@ hipError_t launch_layout(const LaunchArgs &la, int32_t kernel, int which, int32_
 
 hipError_t step_launch_one(const LaunchArgs &la, int32_t kernel, int which, int32_t begin,
                            int32_t end) {
-    return la.layout == UM_AOS ? launch_layout<UM_AOS>(la, kernel, which, begin, end)
-                               : launch_layout<UM_SOA>(la, kernel, which, begin, end);
+    if (la.dtype == UM_F32)
+        return la.layout == UM_AOS ? launch_typed<UM_AOS, float>(la, kernel, which, begin, end)
+                                   : launch_typed<UM_SOA, float>(la, kernel, which, begin, end);
+    return la.layout == UM_AOS ? launch_typed<UM_AOS, double>(la, kernel, which, begin, end)
+                               : launch_typed<UM_SOA, double>(la, kernel, which, begin, end);
 }
 
 }  // namespace um

@@ -47,7 +47,8 @@ hipError_t hex_launch_one(const LaunchArgs &la, int which, int32_t begin, int32_
 // DIRECT over cells [0, end).  BOUNDARY_FLUX: GCOL over slots [begin, end)
 // of one colour or ATOMIC over [0, end); emap holds (cell, a, b, 0) per
 // slot.  UPDATE: DIRECT over cells [0, end) writing n_partials sums, then
-// REDUCE adding their sum to gbl.  x, q and adt are double.
+// REDUCE adding their sum to gbl.  x, q and adt are double or float per
+// dtype; res and gbl are double.
 hipError_t step_launch_one(const LaunchArgs &la, int32_t kernel, int which, int32_t begin,
                            int32_t end);
 

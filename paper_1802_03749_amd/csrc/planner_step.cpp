@@ -18,6 +18,7 @@ struct Want {
     int slot;
     int acc;
     const char *name;
+    bool real;  // UM_F64 or UM_F32 (one type for all such args); else UM_F64 only
 };
 
 void check_pattern(const Ctx &ctx, const um_arg *args, int32_t nargs, int32_t iter,
@@ -31,7 +32,10 @@ void check_pattern(const Ctx &ctx, const um_arg *args, int32_t nargs, int32_t it
         const Dat &d = ctx.dats[a.dat];
         if (d.dim != w.dim)
             fail(UM_ERR_ARITY, "arg %d: %s needs dim %d, dat has %d", i, w.name, w.dim, d.dim);
-        if (d.dtype != UM_F64) fail(UM_ERR_UNSUPPORTED, "%s kernel: %s must be UM_F64", kname, w.name);
+        if (!w.real && d.dtype != UM_F64)
+            fail(UM_ERR_UNSUPPORTED, "%s kernel: %s must be UM_F64", kname, w.name);
+        if (w.real && d.dtype != UM_F64 && d.dtype != UM_F32)
+            fail(UM_ERR_UNSUPPORTED, "%s kernel: %s must be UM_F64 or UM_F32", kname, w.name);
         if (a.acc != w.acc) fail(UM_ERR_ARITY, "arg %d: wrong access mode for %s", i, w.name);
         if (w.arity == 0) {
             if (a.map != -1) fail(UM_ERR_ARITY, "arg %d: %s is accessed directly (map -1)", i, w.name);
@@ -62,27 +66,37 @@ void check_layouts(const Ctx &ctx, std::initializer_list<int32_t> ids, const cha
             fail(UM_ERR_UNSUPPORTED, "%s kernel: all set dats must share one layout", kname);
 }
 
+// x, q and adt share one real type (UM_F64, or UM_F32 for binary32 storage).
+int32_t check_real(const Ctx &ctx, std::initializer_list<int32_t> ids, const char *kname) {
+    const int32_t t = ctx.dats[*ids.begin()].dtype;
+    for (int32_t id : ids)
+        if (ctx.dats[id].dtype != t)
+            fail(UM_ERR_UNSUPPORTED, "%s kernel: x, q and adt must share one dtype", kname);
+    return t;
+}
+
 }  // namespace
 
 StepArgs check_step_args(const Ctx &ctx, int32_t kernel, const um_arg *args, int32_t nargs,
                          int32_t iter) {
     StepArgs sa;
     if (kernel == UM_K_CELL_ADT_2D) {
-        const Want w[3] = {{2, 4, UM_ALL_SLOTS, UM_READ, "x"},
-                           {4, 0, 0, UM_READ, "q"},
-                           {1, 0, 0, UM_WRITE, "adt"}};
+        const Want w[3] = {{2, 4, UM_ALL_SLOTS, UM_READ, "x", true},
+                           {4, 0, 0, UM_READ, "q", true},
+                           {1, 0, 0, UM_WRITE, "adt", true}};
         check_pattern(ctx, args, nargs, iter, w, 3, "cell adt");
         sa.map_n = args[0].map;
         sa.dat_x = args[0].dat;
         sa.dat_q = args[1].dat;
         sa.dat_adt = args[2].dat;
         check_layouts(ctx, {sa.dat_x, sa.dat_q, sa.dat_adt}, "cell adt");
+        sa.dtype = check_real(ctx, {sa.dat_x, sa.dat_q, sa.dat_adt}, "cell adt");
     } else if (kernel == UM_K_BOUNDARY_FLUX_2D) {
-        const Want w[5] = {{2, 2, 0, UM_READ, "x"},
-                           {2, 2, 1, UM_READ, "x"},
-                           {4, 1, 0, UM_READ, "q"},
-                           {1, 1, 0, UM_READ, "adt"},
-                           {4, 1, 0, UM_INC, "res"}};
+        const Want w[5] = {{2, 2, 0, UM_READ, "x", true},
+                           {2, 2, 1, UM_READ, "x", true},
+                           {4, 1, 0, UM_READ, "q", true},
+                           {1, 1, 0, UM_READ, "adt", true},
+                           {4, 1, 0, UM_INC, "res", false}};
         check_pattern(ctx, args, nargs, iter, w, 5, "boundary flux");
         if (args[1].dat != args[0].dat || args[1].map != args[0].map)
             fail(UM_ERR_ARITY, "args 0 and 1 must use the same dat and map");
@@ -95,11 +109,12 @@ StepArgs check_step_args(const Ctx &ctx, int32_t kernel, const um_arg *args, int
         sa.dat_adt = args[3].dat;
         sa.dat_res = args[4].dat;
         check_layouts(ctx, {sa.dat_x, sa.dat_q, sa.dat_adt, sa.dat_res}, "boundary flux");
+        sa.dtype = check_real(ctx, {sa.dat_x, sa.dat_q, sa.dat_adt}, "boundary flux");
     } else if (kernel == UM_K_UPDATE_2D) {
-        const Want w[4] = {{4, 0, 0, UM_RW, "q"},
-                           {4, 0, 0, UM_RW, "res"},
-                           {1, 0, 0, UM_READ, "adt"},
-                           {1, UM_GLOBAL, 0, UM_INC, "rms"}};
+        const Want w[4] = {{4, 0, 0, UM_RW, "q", true},
+                           {4, 0, 0, UM_RW, "res", false},
+                           {1, 0, 0, UM_READ, "adt", true},
+                           {1, UM_GLOBAL, 0, UM_INC, "rms", false}};
         check_pattern(ctx, args, nargs, iter, w, 4, "update");
         sa.dat_q = args[0].dat;
         sa.dat_res = args[1].dat;
@@ -107,6 +122,7 @@ StepArgs check_step_args(const Ctx &ctx, int32_t kernel, const um_arg *args, int
         sa.dat_rms = args[3].dat;
         if (sa.dat_q == sa.dat_res) fail(UM_ERR_ARITY, "update kernel: q and res must differ");
         check_layouts(ctx, {sa.dat_q, sa.dat_res, sa.dat_adt}, "update");
+        sa.dtype = check_real(ctx, {sa.dat_q, sa.dat_adt}, "update");
     } else {
         fail(UM_ERR_UNSUPPORTED, "unknown kernel %d", kernel);
     }

@@ -27,9 +27,15 @@ EPS_D = 0.25
 class TimeStep2D:
     def __init__(self, x, q, e2n, e2c, b2n, b2c, c2n, qinf, *, device: int = 0,
                  order: str = "rcm+partition", block_size: int = 512, point_reorder: bool = True,
-                 layout: str = "aos", geometric_partition: bool = True):
+                 layout: str = "aos", geometric_partition: bool = True, dtype: str = "f64"):
+        """dtype "f32": x, q and adt stored in binary32 (q rounded to nearest
+        from the given values); res and the sum of squares stay binary64."""
         self.device = device
         self.layout = LAYOUTS[layout]
+        if dtype not in ("f64", "f32"):
+            raise ValueError(dtype)
+        self.um_dtype = U.UM_F64 if dtype == "f64" else U.UM_F32
+        self.tdtype = torch.float64 if dtype == "f64" else torch.float32
         self.qinf = tuple(float(v) for v in np.asarray(qinf, np.float64).ravel())
         if len(self.qinf) != 4:
             raise ValueError("qinf must have 4 components")
@@ -75,20 +81,20 @@ class TimeStep2D:
         if device >= 0:
             self.dev = torch.device("cuda", device)
             self.stream = torch.cuda.current_stream(self.dev).cuda_stream
-            self.x = self._upload(x, self.s_nodes)
-            self.q = self._upload(q, self.s_cells)
-            self.adt = self._alloc(self.C, 1)
+            self.x = self._upload(x, self.s_nodes, self.um_dtype)
+            self.q = self._upload(q, self.s_cells, self.um_dtype)
+            self.adt = self._alloc(self.C, 1, self.tdtype)
             self.res = self._alloc(self.C, 4)
             self.rms = torch.zeros(1, dtype=torch.float64, device=self.dev)
             ptr = lambda t: t.data_ptr()
         else:
             self.x = self.q = self.adt = self.res = self.rms = None
             ptr = lambda t: None
-        d = lambda s, dim, t: U.um_decl_dat(ctx, s, dim, U.UM_F64, self.layout, ptr(t))
-        self.d_x = d(self.s_nodes, 2, self.x)
-        self.d_q = d(self.s_cells, 4, self.q)
-        self.d_adt = d(self.s_cells, 1, self.adt)
-        self.d_res = d(self.s_cells, 4, self.res)
+        d = lambda s, dim, t, dt: U.um_decl_dat(ctx, s, dim, dt, self.layout, ptr(t))
+        self.d_x = d(self.s_nodes, 2, self.x, self.um_dtype)
+        self.d_q = d(self.s_cells, 4, self.q, self.um_dtype)
+        self.d_adt = d(self.s_cells, 1, self.adt, self.um_dtype)
+        self.d_res = d(self.s_cells, 4, self.res, U.UM_F64)
         self.d_rms = U.um_decl_dat(ctx, self.s_gbl, 1, U.UM_F64, U.UM_AOS, ptr(self.rms))
 
     # ------------------------------------------------------------ numbering
@@ -99,16 +105,17 @@ class TimeStep2D:
         U.um_get_perm(self.ctx, set_id, out)
         return out
 
-    def _alloc(self, n: int, dim: int) -> torch.Tensor:
+    def _alloc(self, n: int, dim: int, dtype=torch.float64) -> torch.Tensor:
         shape = (n, dim) if self.layout == U.UM_AOS else (dim, n)
-        return torch.zeros(shape, dtype=torch.float64, device=self.dev)
+        return torch.zeros(shape, dtype=dtype, device=self.dev)
 
-    def _upload(self, a: np.ndarray, set_id: int) -> torch.Tensor:
+    def _upload(self, a: np.ndarray, set_id: int, um_dtype: int = U.UM_F64) -> torch.Tensor:
         a = a if self.layout == U.UM_AOS else np.ascontiguousarray(a.T)
-        src = torch.from_numpy(np.ascontiguousarray(a, np.float64)).to(self.dev)
+        npdt = np.float64 if um_dtype == U.UM_F64 else np.float32
+        src = torch.from_numpy(np.ascontiguousarray(a, npdt)).to(self.dev)
         dst = torch.empty_like(src)
         dim = src.shape[1] if self.layout == U.UM_AOS else src.shape[0]
-        U.um_permute_dat(self.ctx, set_id, 0, src.data_ptr(), dst.data_ptr(), dim, U.UM_F64,
+        U.um_permute_dat(self.ctx, set_id, 0, src.data_ptr(), dst.data_ptr(), dim, um_dtype,
                          self.layout, self.stream)
         torch.cuda.synchronize(self.dev)
         return dst
@@ -116,7 +123,8 @@ class TimeStep2D:
     def to_user(self, t: torch.Tensor, set_id: int) -> np.ndarray:
         dim = t.shape[1] if self.layout == U.UM_AOS else t.shape[0]
         dst = torch.empty_like(t)
-        U.um_permute_dat(self.ctx, set_id, 1, t.data_ptr(), dst.data_ptr(), dim, U.UM_F64,
+        dt = U.UM_F64 if t.dtype == torch.float64 else U.UM_F32
+        U.um_permute_dat(self.ctx, set_id, 1, t.data_ptr(), dst.data_ptr(), dim, dt,
                          self.layout, self.stream)
         out = dst.cpu().numpy()
         return out if self.layout == U.UM_AOS else np.ascontiguousarray(out.T)

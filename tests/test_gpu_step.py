@@ -236,3 +236,44 @@ def test_batched_steps_match_oracle(mode):
         assert rel_l2(got[k], o.q) <= TOL, k
     assert abs(bs.rms_total() / total - 1) <= TOL
     bs.close()
+
+
+FP32_TOL = 1e-6
+
+
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+def test_fp32_time_steps_parity(layout):
+    """Binary32 storage of x, q, adt: two chained steps against the oracle's
+    binary32-storage step (FMA contraction and summation order are the
+    only differences), and against the binary64 oracle for the record."""
+    m = quad_mesh(150, 70, seed=21)
+    ts = make(m, layout=layout, block_size=256, dtype="f32")
+    ts.build_plans(flux_block_size=256)
+    q32 = m.q.astype(np.float32)
+    o64 = MeshState(m)
+    for k in range(2):
+        ts.rms.zero_()
+        ts.step()
+        torch.cuda.synchronize()
+        q32, a32, rms32 = native.time_step_f32(m, QINF, q=q32)
+        _, _, rms64 = o64.step()
+        assert ts.q.dtype == torch.float32
+        assert rel_l2(ts.adt_user(), a32) <= FP32_TOL, k
+        assert rel_l2(ts.q_user(), q32) <= FP32_TOL, k
+        assert abs(ts.rms.item() / rms32 - 1) <= 1e-5, k
+        e64 = rel_l2(ts.q_user(), o64.q)
+        print(f"step {k}: q rel L2 vs FP64 oracle {e64:.2e}")
+        assert e64 <= 1e-5
+
+
+def test_fp32_batched_union_parity():
+    from paper_1802_03749_amd.batched import BatchedSteps
+    ms = quad_batch(6, c_min=300, c_max=4000, size_seed=8)
+    bs = BatchedSteps(ms, QINF, mode="union", tune_reps=2, dtype="f32")
+    bs.step()
+    torch.cuda.synchronize()
+    got = bs.q_user()
+    for k, m in enumerate(ms):
+        q32, _, _ = native.time_step_f32(m, QINF)
+        assert rel_l2(got[k], q32) <= FP32_TOL, k
+    bs.close()

@@ -53,3 +53,63 @@ def test_f32_loop_error_at_binary32_level():
     r64 = native.edge_loop(m.e2n, m.e2c, m.x, m.q, m.adt)
     err = np.sqrt(((r32 - r64) ** 2).sum() / (r64 ** 2).sum())
     assert 1e-9 < err < 1e-5      # rounding is visible, but only at binary32 level
+
+
+# ---------------------------------------------- binary32 time-step loops
+GM1_SQRT = 0.5625       # 1 + gm1 = 25/16: the sound speed stays exact
+
+
+@pytest.mark.parametrize("rect,prim", [
+    ((0.0, 0.0, 1.0, 1.0), (1.0, 0.0, 0.0, 2.25)),
+    ((2.0, -1.0, 0.5, 2.0), (0.25, 0.5, -0.25, 0.5625)),
+    ((-3.0, 5.0, 1.25, 0.75), (4.0, -0.125, 0.375, 9.0)),
+])
+def test_f32_cell_adt_equals_f64_on_exact_rectangles(rect, prim):
+    """p / gm1 is an integer and (1 + gm1) p / rho = 225/64, so the energy,
+    the pressure and the sound speed (15/8) are exact in both formats."""
+    x0, y0, a, b = rect
+    rho, u, v, p = prim
+    q = np.array([rho, rho * u, rho * v, p / GM1_SQRT + 0.5 * rho * (u * u + v * v)])
+    xc = np.array([[x0, y0], [x0 + a, y0], [x0 + a, y0 + b], [x0, y0 + b]])
+    assert native.cell_adt_f32(xc, q, GM1_SQRT) == native.cell_adt(xc, q, GM1_SQRT)
+
+
+def test_f32_step_equals_f64_step_on_exact_mesh():
+    """Integer mesh, dyadic states, gm1 = 0.375, dyadic far field, adt given
+    exactly: boundary flux and update match the binary64 loops bit for bit
+    (the update rounds q once; here q - d is exact in binary32)."""
+    m = quad_mesh(5, 4, seed=3, jitter=0.0)
+    rng = np.random.default_rng(5)
+    q = dyadic_state(rng, m.q.shape[0])
+    adt = 2.0 ** rng.integers(-1, 3, m.q.shape[0]).astype(np.float64)
+    qinf = np.array([1.0, 0.25, -0.125, 2.5])
+    b32 = native.bres_loop_f32(m.b2n, m.b2c, m.x, q, adt, qinf, gm1=GM1_DYADIC)
+    b64 = native.bres_loop(m.b2n, m.b2c, m.x, q, adt, qinf, gm1=GM1_DYADIC)
+    np.testing.assert_array_equal(b32, b64)
+    res = np.round(rng.uniform(-1, 1, (m.q.shape[0], 4)) * 64) / 64 * adt[:, None]
+    q32, r32, s32 = native.update_loop_f32(q, res, adt)
+    q64, r64, s64 = native.update_loop(q, res, adt)
+    np.testing.assert_array_equal(q32, q64)
+    np.testing.assert_array_equal(r32, r64)
+    assert s32 == s64
+
+
+def test_f32_update_rounds_once():
+    """q - d not representable in binary32: the stored value is the binary32
+    value nearest to the binary64 difference (one rounding)."""
+    q = np.array([[1.0, 1.0, 1.0, 1.0]])
+    adt = np.array([3.0])
+    res = np.array([[1.0, 2.0, -1.0, 1e-9]])
+    q32, _, _ = native.update_loop_f32(q, res, adt)
+    want = (q.astype(np.float32).astype(np.float64) - res / 3.0).astype(np.float32)
+    np.testing.assert_array_equal(q32, want)
+
+
+def test_f32_time_step_error_at_binary32_level():
+    m = quad_mesh(30, 20, seed=9)
+    qinf = [1.0, 0.35, 0.05, 2.7]
+    q32, a32, r32 = native.time_step_f32(m, qinf)
+    q64, a64, r64 = native.time_step(m, qinf)
+    assert np.abs(a32 / a64 - 1).max() < 1e-5
+    assert 1e-9 < np.abs(q32 - q64).max() < 1e-5
+    assert abs(r32 / r64 - 1) < 1e-4
