@@ -79,6 +79,65 @@ def copy_probe(torch, nbytes: int = 512 << 20, reps: int = 20):
     return 2 * nbytes / sec / 1e9, sec
 
 
+def tile_blocks(mesh, tx: int, ty: int) -> np.ndarray:
+    """Hand-made geometric edge blocks (the paper's reuse upper bound): tiles
+    of tx x ty cells of the natural grid; an interior edge belongs to the
+    tile of its right cell (a cell takes its left and bottom edges)."""
+    nat = mesh.cell_nat[mesh.e2c[:, 1]]
+    i, j = nat % mesh.nx, nat // mesh.nx
+    return ((j // ty) * ((mesh.nx + tx - 1) // tx) + i // tx).astype(np.int32)
+
+
+def run_ablations(torch, mesh, S, args, useful, E):
+    """One knob at a time around the headline configuration."""
+    from paper_1802_03749_amd.edgeloop import EdgeFluxLoop
+    steps, warm = max(args.steps // 4, 10), max(args.warmup // 4, 2)
+    out = {}
+
+    def entry(L, p):
+        s = time_steps(torch, lambda: L.run(p), steps, warm)
+        st = p.stats
+        return {"us_per_sweep": s * 1e6, "useful_gbps": useful / s / 1e9,
+                "pct_hbm_peak": 100 * useful / s / 1e9 / 8000.0, "launches": st["n_launches"],
+                "block_colours": st["n_block_colours"], "global_colours": st["n_global_colours"],
+                "reuse_factor": st["reuse_factor"]}
+
+    base = dict(staging=args.staging, tcmode=args.tcmode, block_colouring=args.bcol,
+                schedule=args.schedule)
+    tx = 16
+    ty = max(S // (2 * tx), 1)
+    parts = (("chunks_of_rcm", "rcm", {}),
+             ("recursive_bisection", "rcm+partition", {}),
+             (f"geometric_tiles_{tx}x{ty}", "rcm+user", {"edge_blocks": tile_blocks(mesh, tx, ty)}))
+    for name, order, kw in parts:
+        for layout in ("aos", "soa"):
+            L = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0, order=order,
+                             block_size=S, layout=layout, **kw)
+            out[f"hier_{name}_{layout}"] = entry(L, L.plan("hier", S, **base))
+            if name == "recursive_bisection" and layout == args.layout:
+                for knob, val in (("staging", "inc"), ("tcmode", "lds_atomic"),
+                                  ("block_colouring", "first_fit"), ("block_colouring", "recolour"),
+                                  ("schedule", "colour_launches"), ("schedule", "dataflow")):
+                    if base[knob] == val:
+                        continue
+                    o = dict(base); o[knob] = val
+                    try:
+                        out[f"hier_partition_{knob}_{val}"] = entry(L, L.plan("hier", S, **o))
+                    except Exception as e:  # an unsupported combination
+                        out[f"hier_partition_{knob}_{val}"] = {"error": str(e)}
+            L.close()
+            log(f"ablation {name} {layout} done")
+    for order in ("none", "rcm", "gps", "rcm+partition"):
+        for layout in ("aos", "soa"):
+            L = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0, order=order,
+                             block_size=S, layout=layout)
+            out[f"global_{order}_{layout}"] = entry(L, L.plan("global", 256))
+            out[f"atomic_{order}_{layout}"] = entry(L, L.plan("atomic", 256))
+            L.close()
+        log(f"ablation global/atomic {order} done")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +159,9 @@ def main() -> int:
                     help="skip the FP32 variant, the 3D hex workload and the batch")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batch of 64 meshes")
+    ap.add_argument("--ablations", action="store_true",
+                    help="also run the ablation matrix (partitioner, order, layout, staging, "
+                         "colour rounds, block colouring, schedule)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -264,6 +326,8 @@ def main() -> int:
                 bx[f"sequential_{dt}"]["ms_per_step_graph"] / bx[f"union_{dt}"]["ms_per_step_graph"])
         extras["batched_64_meshes"] = bx
 
+    ablations = run_ablations(torch, mesh, S, args, useful, E) if args.ablations else None
+
     # ---- CPU baseline: the oracle's sequential loop on the host
     cpu = None
     if args.cpu_seconds > 0:
@@ -319,6 +383,7 @@ def main() -> int:
         "baselines": baselines,
         "variants": variants,
         "extras": extras,
+        "ablations": ablations,
         "plan": {k: st[k] for k in ("n_blocks", "n_block_colours", "max_thread_colours",
                                      "avg_thread_colours", "reuse_factor", "lds_bytes_max",
                                      "staged_points", "plan_device_bytes", "build_seconds")},

@@ -78,8 +78,9 @@ typedef enum {
     UM_REORDER_RCM = 1,       /* reverse Cuthill-McKee numbering of points   */
     UM_REORDER_GPS = 2,       /* forward Cuthill-McKee (level order) numbering */
     UM_REORDER_PARTITION = 3, /* partition elements into blocks, renumber    */
-    UM_REORDER_LEXICOGRAPHIC = 4 /* renumber only the from-set of the map by
-                                    its sorted point ids (secondary loops) */
+    UM_REORDER_LEXICOGRAPHIC = 4, /* renumber only the from-set of the map by
+                                     its sorted point ids (secondary loops) */
+    UM_REORDER_USER_BLOCKS = 5    /* blocks given by the caller (block_of)   */
 } um_reorder;
 /* What a hierarchical block stages in LDS (Section 2.2; increments-only
  * staging is the fallback the paper needed when the staged data did not fit
@@ -236,6 +237,9 @@ typedef struct {
     int32_t coord_dim;     /* 1..3                                           */
     const double *coords;  /* host [size(to-set of coord_map)][coord_dim],
                               current numbering; read during the call only   */
+    const int32_t *block_of; /* USER_BLOCKS: host [size(from-set)], the block
+                              id (>= 0) of every element in the current
+                              numbering; read during the call only           */
     int32_t reserved[2];
 } um_reorder_opts;
 
@@ -377,6 +381,11 @@ um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr);
  *     blocks), ties keeping the previous order.  The blocks are remembered
  *     and used by HIER plans with the same block_size, or with a multiple
  *     k * block_size (k consecutive blocks form one plan block).
+ *   USER_BLOCKS: as PARTITION, but the blocks are the caller's: elements
+ *     are renumbered by ascending block_of (stable), empty block ids are
+ *     dropped, and every block must hold at most block_size elements
+ *     (else UM_ERR_ARG); then the same point reordering and the same use
+ *     by HIER plans.
  *   LEXICOGRAPHIC: only the from-set of driving_map is renumbered, by the
  *     lexicographic order of each element's sorted point ids (ties keep the
  *     previous order), e.g. boundary edges after their cells were

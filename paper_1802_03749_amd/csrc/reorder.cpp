@@ -396,18 +396,43 @@ void reorder_mesh(Ctx &ctx, const um_reorder_opts &o) {
         apply_set_perm(ctx, F, lexicographic_elements(ctx.maps[o.driving_map]));
         return;
     }
-    if (o.mode != UM_REORDER_PARTITION) fail(UM_ERR_ARG, "reorder: unknown mode %d", o.mode);
+    if (o.mode != UM_REORDER_PARTITION && o.mode != UM_REORDER_USER_BLOCKS)
+        fail(UM_ERR_ARG, "reorder: unknown mode %d", o.mode);
     if (o.block_size < 1 || o.block_size > 1024)
         fail(UM_ERR_ARG, "reorder: block_size %d outside 1..1024", o.block_size);
-    if (o.coord_map >= 0) {
+    std::vector<int32_t> off;
+    std::vector<int32_t> perm;
+    if (o.mode == UM_REORDER_USER_BLOCKS) {
+        if (!o.block_of) fail(UM_ERR_ARG, "reorder: USER_BLOCKS needs block_of");
+        const int64_t n = ctx.sets[F].size;
+        int32_t nbid = 0;
+        for (int64_t e = 0; e < n; ++e) {
+            if (o.block_of[e] < 0) fail(UM_ERR_ARG, "reorder: negative block id at %lld", (long long)e);
+            nbid = std::max(nbid, o.block_of[e] + 1);
+        }
+        std::vector<int32_t> cnt(int64_t(nbid) + 1, 0);
+        for (int64_t e = 0; e < n; ++e) cnt[o.block_of[e] + 1]++;
+        for (int32_t b = 0; b < nbid; ++b)
+            if (cnt[b + 1] > o.block_size)
+                fail(UM_ERR_ARG, "reorder: block %d holds %d elements > block_size %d", b, cnt[b + 1],
+                     o.block_size);
+        for (int32_t b = 0; b < nbid; ++b) cnt[b + 1] += cnt[b];
+        perm.resize(n);
+        std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+        for (int64_t e = 0; e < n; ++e) perm[fill[o.block_of[e]]++] = int32_t(e);
+        off.push_back(0);
+        for (int32_t b = 0; b < nbid; ++b)
+            if (cnt[b + 1] > cnt[b]) off.push_back(cnt[b + 1]);
+    }
+    if (o.mode == UM_REORDER_PARTITION && o.coord_map >= 0) {
         if (o.coord_map >= int32_t(ctx.maps.size()) || ctx.maps[o.coord_map].from != F)
             fail(UM_ERR_ARG, "reorder: coord_map must be a map from the partitioned set");
         if (!o.coords || o.coord_dim < 1 || o.coord_dim > 3)
             fail(UM_ERR_ARG, "reorder: coords missing or coord_dim outside 1..3");
     }
-    std::vector<int32_t> off;
-    std::vector<int32_t> perm = partition_elements(ctx, o.driving_map, o.block_size, o.coord_map,
-                                                   o.coord_dim, o.coords, off);
+    if (o.mode == UM_REORDER_PARTITION)
+        perm = partition_elements(ctx, o.driving_map, o.block_size, o.coord_map, o.coord_dim,
+                                  o.coords, off);
     apply_set_perm(ctx, F, perm);
     ctx.sets[F].part_block_size = o.block_size;
     ctx.sets[F].part_off = off;

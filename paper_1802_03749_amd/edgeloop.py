@@ -29,10 +29,11 @@ SCHEDULES = {"colour_launches": U.UM_SCHED_COLOUR_LAUNCHES, "dataflow": U.UM_SCH
 
 
 def parse_order(order: str):
-    """"none" | "rcm" | "gps" | "partition" | "rcm+partition" (steps joined by '+')."""
+    """"none" | "rcm" | "gps" | "partition" | "user" | "rcm+partition" ... (steps
+    joined by '+'; "user" = the caller's edge blocks)."""
     steps = [] if order in ("", "none", "random") else order.split("+")
     for s in steps:
-        if s not in ("rcm", "gps", "partition"):
+        if s not in ("rcm", "gps", "partition", "user"):
             raise ValueError(f"unknown reordering step {s!r}")
     return steps
 
@@ -55,9 +56,11 @@ class EdgeFluxLoop:
 
     def __init__(self, x, q, adt, e2n, e2c, *, device: int = 0, order: str = "rcm+partition",
                  block_size: int = 512, point_reorder: bool = True, layout: str = "aos",
-                 geometric_partition: bool = True, dtype: str = "f64"):
+                 geometric_partition: bool = True, dtype: str = "f64", edge_blocks=None):
         """dtype: "f64", or "f32" to store x, q and adt in binary32 (rounded to
-        nearest from the given binary64 values); res is always binary64."""
+        nearest from the given binary64 values); res is always binary64.
+        edge_blocks: block id of every edge (user numbering) for the "user"
+        reordering step."""
         self.device = device
         self.layout = LAYOUTS[layout]
         if dtype not in ("f64", "f32"):
@@ -79,17 +82,27 @@ class EdgeFluxLoop:
             o = U.um_reorder_opts()
             o.driving_map = self.m_e2c
             o.coord_map = -1
+            keep = None
             if step in ("rcm", "gps"):
                 o.mode = U.UM_REORDER_RCM if step == "rcm" else U.UM_REORDER_GPS
+            elif step == "user":
+                if edge_blocks is None:
+                    raise ValueError('order step "user" needs edge_blocks')
+                keep = np.ascontiguousarray(
+                    np.asarray(edge_blocks, np.int32)[self.perm(self.s_edges)])
+                o.mode = U.UM_REORDER_USER_BLOCKS
+                o.block_size = block_size
+                o.point_reorder = 1 if point_reorder else 0
+                o.block_of = keep.ctypes.data
             else:
                 o.mode = U.UM_REORDER_PARTITION
                 o.block_size = block_size
                 o.point_reorder = 1 if point_reorder else 0
                 if geometric_partition:
-                    xc = np.ascontiguousarray(x[self.perm(self.s_nodes)])
+                    keep = np.ascontiguousarray(x[self.perm(self.s_nodes)])
                     o.coord_map = self.m_e2n
                     o.coord_dim = 2
-                    o.coords = xc.ctypes.data
+                    o.coords = keep.ctypes.data
             U.um_reorder_mesh(self.ctx, o)
         self.part_block_size, self.n_part_blocks = U.um_get_blocks(self.ctx, self.s_edges)
         self.dats = {}

@@ -28,6 +28,7 @@ UM_READ, UM_WRITE, UM_RW, UM_INC = 0, 1, 2, 3
 UM_STRAT_ATOMIC, UM_STRAT_GLOBAL_COLOUR, UM_STRAT_HIER = 0, 1, 2
 UM_REORDER_NONE, UM_REORDER_RCM, UM_REORDER_GPS, UM_REORDER_PARTITION = 0, 1, 2, 3
 UM_REORDER_LEXICOGRAPHIC = 4
+UM_REORDER_USER_BLOCKS = 5
 UM_STAGE_ALL, UM_STAGE_INC_ONLY = 0, 1
 UM_TC_BARRIER, UM_TC_LDS_ATOMIC = 0, 1
 UM_BCOL_FIRST_FIT, UM_BCOL_RECOLOUR = 0, 1
@@ -61,7 +62,7 @@ class um_arg(ct.Structure):
 class um_reorder_opts(ct.Structure):
     _fields_ = [("mode", ct.c_int32), ("driving_map", ct.c_int32), ("block_size", ct.c_int32),
                 ("point_reorder", ct.c_int32), ("coord_map", ct.c_int32), ("coord_dim", ct.c_int32),
-                ("coords", ct.c_void_p), ("reserved", ct.c_int32 * 2)]
+                ("coords", ct.c_void_p), ("block_of", ct.c_void_p), ("reserved", ct.c_int32 * 2)]
 
 
 class um_plan_opts(ct.Structure):

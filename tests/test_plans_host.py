@@ -387,3 +387,35 @@ def test_hier_plan_merges_partition_blocks_for_multiples(S, k):
     p2 = L.plan("hier", S + 64)
     off2 = L.export(p2, U.UM_EXP_BLOCK_OFFSETS)
     assert np.array_equal(off2, np.append(np.arange(0, L.E, S + 64), L.E))
+
+
+def tile_blocks(m, tx, ty):
+    """Tile id of every edge: tiles of tx x ty cells, an edge in its right
+    cell's tile (a cell takes its left and bottom interior edges)."""
+    nat = m.cell_nat[m.e2c[:, 1]]
+    i, j = nat % m.nx, nat // m.nx
+    return ((j // ty) * ((m.nx + tx - 1) // tx) + i // tx).astype(np.int32)
+
+
+def test_user_blocks_reorder_and_plan():
+    """Caller-given blocks (geometric tiles): elements grouped by block id in
+    ascending order, empty ids dropped, the plan uses exactly these blocks."""
+    m = quad_mesh(40, 24, seed=4)
+    tiles = tile_blocks(m, 8, 8)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=-1, order="rcm+user",
+                     block_size=128, edge_blocks=tiles)
+    off = L.part_blocks()
+    pe = L.perm(L.s_edges)
+    assert P.is_permutation(pe, L.E)
+    t_cur = tiles[pe]
+    assert np.all(np.diff(t_cur) >= 0)
+    want = np.concatenate([[0], np.cumsum(np.bincount(tiles)[np.unique(tiles)])])
+    assert np.array_equal(off, want)
+    p = L.plan("hier", 128)
+    assert np.array_equal(L.export(p, U.UM_EXP_BLOCK_OFFSETS), off)
+    e2c = L.current_map("e2c")
+    assert P.check_block_colouring(off, L.export(p, U.UM_EXP_BLOCK_COLOURS), e2c)
+    assert p.stats["reuse_factor"] == pytest.approx(P.reuse_factor(off, e2c))
+    with pytest.raises(U.UmeshError):        # a tile larger than block_size
+        EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=-1, order="user", block_size=100,
+                     edge_blocks=tiles)
