@@ -240,6 +240,18 @@ def main() -> int:
                                  "useful_gbps": useful / s2 / 1e9,
                                  "launches": p2.stats["n_launches"]}
     log(f"hier ({other}): {s2 * 1e6:.1f} us/step")
+    # the headline plan's launches captured in one HIP graph and replayed
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        hier.run(plan, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    s3 = time_steps(torch, graph.replay, args.steps, args.warmup)
+    variants[f"fp64_{args.schedule}_graph"] = {"edges_per_s": E / s3, "ms_per_step": s3 * 1e3,
+                                               "useful_gbps": useful / s3 / 1e9,
+                                               "launches": st["n_launches"]}
+    log(f"hier ({args.schedule}, graph replay): {s3 * 1e6:.1f} us/step")
+    del graph
     hier.close()
 
     # ---- baselines on the same GPU and mesh

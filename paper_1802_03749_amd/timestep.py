@@ -197,7 +197,7 @@ class TimeStep2D:
         (dicts of block_size, schedule, staging, block_colouring, tcmode) and
         keep the fastest as the step's flux plan.  adt must be valid (run the
         adt loop first); res is zeroed afterwards.  Returns (index, ms list)."""
-        opts = [self._opts("hier", c["block_size"], **c) for c in candidates]
+        opts = [self._opts("hier", **c) for c in candidates]
         h, best, ms = U.um_plan_autotune(self.ctx, U.UM_K_EDGE_FLUX_LF2D, self.flux_args(),
                                          self.s_edges, opts, self.params("flux"), self.stream,
                                          reps)
