@@ -6,9 +6,11 @@ and ny = max(1, round(C_k / nx)) cells and is generated with seed
 `mesh_seed0 + k`.
 
 The union renumbers mesh k's cells, nodes and edges after those of meshes
-0..k-1 and shifts its coordinates by (k * spacing, 0) so meshes never
-overlap in space; the shift is an integer, so every coordinate difference
-(the only way coordinates enter a flux) is unchanged and exact.
+0..k-1 and keeps every mesh's own coordinates (so each mesh's data is
+bit-identical to the mesh alone, in any storage precision); `x_layout`
+additionally places mesh k at (k * spacing, 0), so that a geometric
+partitioner given those coordinates never mixes meshes that would
+otherwise overlap in space.
 """
 from __future__ import annotations
 
@@ -40,7 +42,8 @@ def quad_batch(n_meshes: int = 64, c_min: float = 5e3, c_max: float = 5e5, size_
 
 @dataclass
 class QuadUnion:
-    x: np.ndarray
+    x: np.ndarray          # every mesh at its own coordinates
+    x_layout: np.ndarray   # mesh k shifted by (k * spacing, 0)
     q: np.ndarray
     adt: np.ndarray
     e2n: np.ndarray
@@ -62,7 +65,8 @@ def union(meshes, spacing: float = 8192.0) -> QuadUnion:
     shift = lambda k, m: m.x + np.array([k * spacing, 0.0])
     cat = lambda parts, dt: np.ascontiguousarray(np.concatenate(parts).astype(dt))
     return QuadUnion(
-        x=cat([shift(k, m) for k, m in enumerate(meshes)], np.float64),
+        x=cat([m.x for m in meshes], np.float64),
+        x_layout=cat([shift(k, m) for k, m in enumerate(meshes)], np.float64),
         q=cat([m.q for m in meshes], np.float64),
         adt=cat([m.adt for m in meshes], np.float64),
         e2n=cat([m.e2n + ns[k] for k, m in enumerate(meshes)], np.int32),

@@ -54,7 +54,7 @@ class BatchedSteps:
             u = union(self.meshes, spacing=union_spacing)
             self.union = u
             ts = TimeStep2D(u.x, u.q, u.e2n, u.e2c, u.b2n, u.b2c, u.c2n, qinf, device=device,
-                            block_size=partition_block, dtype=dtype)
+                            block_size=partition_block, dtype=dtype, partition_coords=u.x_layout)
             ts.build_plans(flux_block_size=partition_block)
             ts.run_loop("adt")
             best, ms = ts.autotune_flux(self.candidates, tune_reps)

@@ -27,9 +27,12 @@ EPS_D = 0.25
 class TimeStep2D:
     def __init__(self, x, q, e2n, e2c, b2n, b2c, c2n, qinf, *, device: int = 0,
                  order: str = "rcm+partition", block_size: int = 512, point_reorder: bool = True,
-                 layout: str = "aos", geometric_partition: bool = True, dtype: str = "f64"):
+                 layout: str = "aos", geometric_partition: bool = True, dtype: str = "f64",
+                 partition_coords=None):
         """dtype "f32": x, q and adt stored in binary32 (q rounded to nearest
-        from the given values); res and the sum of squares stay binary64."""
+        from the given values); res and the sum of squares stay binary64.
+        partition_coords: node coordinates the geometric partitioner uses
+        instead of x (e.g. meshes of a union placed side by side)."""
         self.device = device
         self.layout = LAYOUTS[layout]
         if dtype not in ("f64", "f32"):
@@ -66,7 +69,8 @@ class TimeStep2D:
                 o.block_size = block_size
                 o.point_reorder = 1 if point_reorder else 0
                 if geometric_partition:
-                    xc = np.ascontiguousarray(x[self.perm(self.s_nodes)])
+                    pc = x if partition_coords is None else np.asarray(partition_coords, np.float64)
+                    xc = np.ascontiguousarray(pc[self.perm(self.s_nodes)])
                     o.coord_map = self.m_e2n
                     o.coord_dim = 2
                     o.coords = xc.ctypes.data

@@ -139,7 +139,8 @@ def test_union_step_equals_per_mesh_steps():
     state equals its own oracle step; the sum of squares is their sum."""
     ms = quad_batch(6, c_min=200, c_max=6000, size_seed=3)
     u = union(ms)
-    ts = TimeStep2D(u.x, u.q, u.e2n, u.e2c, u.b2n, u.b2c, u.c2n, QINF, device=0, block_size=256)
+    ts = TimeStep2D(u.x, u.q, u.e2n, u.e2c, u.b2n, u.b2c, u.c2n, QINF, device=0, block_size=256,
+                    partition_coords=u.x_layout)
     ts.build_plans(flux_block_size=256)
     ts.step()
     torch.cuda.synchronize()

@@ -97,9 +97,9 @@ def test_union_offsets_and_maps():
         np.testing.assert_array_equal(u.q[c0:c1], m.q)
         np.testing.assert_array_equal(u.e2c[e0:e1], m.e2c + c0)
         np.testing.assert_array_equal(u.e2n[e0:e1], m.e2n + n0)
-        # every coordinate difference inside a mesh is unchanged
-        d = u.x[n0:n1] - u.x[n0]
-        np.testing.assert_array_equal(d, m.x - m.x[0])
+        # own coordinates kept; the layout copy only shifts along x
+        np.testing.assert_array_equal(u.x[n0:n1], m.x)
+        np.testing.assert_array_equal(u.x_layout[n0:n1] - [k * 64.0, 0.0], m.x)
         # no map of mesh k leaves its own ranges
         if e1 > e0:
             assert u.e2c[e0:e1].min() >= c0 and u.e2c[e0:e1].max() < c1
