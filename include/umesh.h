@@ -110,9 +110,9 @@ typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1 } um_bcolouring;
  * multiply-adds into FMAs differently) and each schedule is bitwise
  * reproducible from run to run.
  * A wait that exceeds a time limit sets the plan's error count instead of
- * hanging (um_plan_errors).  The execution counter that tags the flags is
- * kept and advanced on the device, so the launch may be captured in a HIP
- * graph and replayed.  Supported for STAGE_ALL with one element per lane;
+ * hanging (um_plan_errors).  Each block's flag counts the executions it has
+ * completed (all flags advance together), so the launch needs no host-side
+ * counter and may be captured in a HIP graph and replayed.  Supported for STAGE_ALL with one element per lane;
  * a plan must not execute concurrently with itself. */
 typedef enum { UM_SCHED_COLOUR_LAUNCHES = 0, UM_SCHED_DATAFLOW = 1 } um_schedule;
 

@@ -180,7 +180,7 @@ struct DevicePlan {
     uint32_t *loc = nullptr;
     int32_t *pred_off = nullptr, *preds = nullptr;  // DATAFLOW
     int32_t *flags = nullptr;                       // DATAFLOW: completion epochs per block
-    int32_t *err = nullptr;                         // DATAFLOW: [timeouts, last execution, done, 0]
+    int32_t *err = nullptr;                         // DATAFLOW: [timeouts, unused x3]
     double *partials = nullptr;                     // UPDATE: one sum per workgroup
     int64_t bytes = 0;
 };

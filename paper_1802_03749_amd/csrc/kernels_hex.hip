@@ -103,7 +103,7 @@ struct HexDats {
     int64_t N;
 };
 
-template <int LAYOUT>
+template <int LAYOUT, int TCMODE>
 __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restrict__ binfo,
                                                         const int32_t *__restrict__ stg,
                                                         const Run *__restrict__ runs,
@@ -155,9 +155,20 @@ __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restr
             }
         hex_force(xe, ve, kappa, f);
     }
-    const int ncol = bi.ncol;
-    for (int c = 0; c < ncol; ++c) {
-        if (col == c) {
+    if constexpr (TCMODE == UM_TC_BARRIER) {
+        const int ncol = bi.ncol;
+        for (int c = 0; c < ncol; ++c) {
+            if (col == c) {
+#pragma unroll
+                for (int a = 0; a < 8; ++a)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) lds_add(&s_acc[k * nn + l[a]], f[a][k]);
+            }
+            __syncthreads();
+        }
+    } else {
+        // LDS atomics without thread colours: one round, order not fixed
+        if (col >= 0) {
 #pragma unroll
             for (int a = 0; a < 8; ++a)
 #pragma unroll
@@ -236,15 +247,18 @@ hipError_t hex_launch_layout(const LaunchArgs &la, int which, int32_t begin, int
                     la.N};
     const double kappa = la.gm1;
     if (which == LAUNCH_HIER) {
-        static bool attr = false;
-        if (!attr) {
-            hipFuncSetAttribute(reinterpret_cast<const void *>(hex_hier_kernel<LAYOUT>),
+        static bool attr[2] = {false, false};
+        const bool atom = la.tcmode == UM_TC_LDS_ATOMIC;
+        auto kern = atom ? hex_hier_kernel<LAYOUT, UM_TC_LDS_ATOMIC>
+                         : hex_hier_kernel<LAYOUT, UM_TC_BARRIER>;
+        if (!attr[atom]) {
+            hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr = true;
+            attr[atom] = true;
         }
-        hipLaunchKernelGGL((hex_hier_kernel<LAYOUT>), dim3(end - begin), dim3(la.block_size),
-                           size_t(lds), la.stream, la.binfo, la.stg_c, la.crun,
-                           reinterpret_cast<const uint4 *>(la.loc), d, kappa, begin);
+        hipLaunchKernelGGL(kern, dim3(end - begin), dim3(la.block_size), size_t(lds), la.stream,
+                           la.binfo, la.stg_c, la.crun, reinterpret_cast<const uint4 *>(la.loc), d,
+                           kappa, begin);
         return hipGetLastError();
     }
     const int32_t n = end - begin;

@@ -316,10 +316,12 @@ constexpr uint64_t FLOW_WAIT_TICKS = 20000000ull;
 // blockIdx order and a block only waits for smaller positions, so every
 // awaited block is already running or finished; the wait is bounded in time
 // anyway and a timeout is counted in ctl[0] instead of hanging.
-// The execution number lives on the device (ctl[1] = last completed
-// execution, ctl[2] = blocks finished in the current one), so a captured
-// graph can replay the launch: every block reads ctl[1] + 1 at its start,
-// and the last block to finish advances ctl[1] and clears ctl[2].
+// Execution numbers: a block's flag holds the number of executions it has
+// completed, and every execution runs every block once, so all flags move
+// in lockstep; a block's epoch is its own flag + 1 and a predecessor is done
+// when its flag equals that epoch.  Nothing global is counted (a device-
+// scope atomic per block on one shared counter serialises the whole launch)
+// and a captured graph can replay the launch.
 template <int LAYOUT, int TCMODE, typename Real>
 __global__ __launch_bounds__(1024) void hier_flow_kernel(
     const BlockInfo *__restrict__ binfo, const int32_t *__restrict__ stg_c,
@@ -329,9 +331,10 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     int32_t *ctl) {
     extern __shared__ double lds[];
     int32_t *err = ctl;
-    const int32_t epoch = __hip_atomic_load(ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-    const Real gm1 = Real(gm1d), eps = Real(epsd);
     const int32_t pos = int32_t(blockIdx.x);
+    const int32_t epoch =
+        __hip_atomic_load(flags + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    const Real gm1 = Real(gm1d), eps = Real(epsd);
     const BlockInfo bi = binfo[pos], bn = binfo[pos + 1];
     const int ne = bn.slot_off - bi.slot_off;
     const int nc = bn.cell_off - bi.cell_off;
@@ -466,15 +469,7 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     // publish: every lane's stores complete, then one flag store
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (tid == 0) {
-        __hip_atomic_store(flags + pos, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int32_t done =
-            __hip_atomic_fetch_add(ctl + 2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (done == int32_t(gridDim.x) - 1) {
-            __hip_atomic_store(ctl + 2, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(ctl + 1, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
+    if (tid == 0) __hip_atomic_store(flags + pos, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int LAYOUT, typename Real>

@@ -105,12 +105,12 @@ class HexLoop:
 
     def plan(self, strategy: str = "hier", block_size: int = 256, max_block_colours: int = 256,
              lds_limit_bytes: int = 0, explicit_lists: bool = False,
-             block_colouring: str = "first_fit") -> Plan:
+             block_colouring: str = "first_fit", tcmode: str = "barrier") -> Plan:
         o = U.um_plan_opts()
         o.strategy = STRATEGIES[strategy]
         o.block_size = block_size
         o.staging = STAGING["all"]
-        o.tcmode = TCMODES["barrier"]
+        o.tcmode = TCMODES[tcmode]
         o.max_block_colours = max_block_colours
         o.lds_limit_bytes = lds_limit_bytes
         o.explicit_lists = 1 if explicit_lists else 0

@@ -378,6 +378,17 @@ def test_hex_parity(layout, strategy, order, S):
     assert rel_l2(L.force_user(), ref) <= TOL
 
 
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+def test_hex_lds_atomic_rounds(layout):
+    """LDS atomics instead of thread-colour rounds: same result to rounding."""
+    m, ref = hexmesh(24)
+    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=256, layout=layout)
+    p = L.plan("hier", 256, tcmode="lds_atomic", block_colouring="recolour")
+    L.run(p)
+    torch.cuda.synchronize()
+    assert rel_l2(L.force_user(), ref) <= TOL
+
+
 def test_hex_contract_off_forces_bit_exact():
     m, _ = hexmesh(12)
     L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm", block_size=128)
