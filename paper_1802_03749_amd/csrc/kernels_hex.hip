@@ -122,17 +122,38 @@ __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restr
     const int tid = int(threadIdx.x), T = int(blockDim.x);
 
     const uint4 w = tid < ne ? loc[bi.slot_off + tid] : make_uint4(0, 0, 0, 0);
-    for (int t = tid; t < nn; t += T) {
-        const int64_t g = staged_id(runs, bi.crun_off, nr, sl, t);
-        double xv[3], vv[3], fv[3];
-        load3<LAYOUT>(d.x, d.N, g, xv);
-        load3<LAYOUT>(d.v, d.N, g, vv);
-        load3<LAYOUT>(d.force, d.N, g, fv);
+    // gather: two staged nodes per lane per pass (a block of S elements
+    // stages up to about 2 S nodes), all loads of a pass issued before its
+    // LDS stores
+    for (int t0 = tid; t0 < nn; t0 += 2 * T) {
+        const int t1 = t0 + T;
+        const bool has1 = t1 < nn;
+        double xv[2][3], vv[2][3], fv[2][3];
+        {
+            const int64_t g = staged_id(runs, bi.crun_off, nr, sl, t0);
+            load3<LAYOUT>(d.x, d.N, g, xv[0]);
+            load3<LAYOUT>(d.v, d.N, g, vv[0]);
+            load3<LAYOUT>(d.force, d.N, g, fv[0]);
+        }
+        if (has1) {
+            const int64_t g = staged_id(runs, bi.crun_off, nr, sl, t1);
+            load3<LAYOUT>(d.x, d.N, g, xv[1]);
+            load3<LAYOUT>(d.v, d.N, g, vv[1]);
+            load3<LAYOUT>(d.force, d.N, g, fv[1]);
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            s_x[k * nn + t] = xv[k];
-            s_v[k * nn + t] = vv[k];
-            s_acc[k * nn + t] = fv[k];
+            s_x[k * nn + t0] = xv[0][k];
+            s_v[k * nn + t0] = vv[0][k];
+            s_acc[k * nn + t0] = fv[0][k];
+        }
+        if (has1) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                s_x[k * nn + t1] = xv[1][k];
+                s_v[k * nn + t1] = vv[1][k];
+                s_acc[k * nn + t1] = fv[1][k];
+            }
         }
     }
     __syncthreads();

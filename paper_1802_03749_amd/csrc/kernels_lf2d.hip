@@ -144,34 +144,22 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
         w[j] = s < ne ? loc[bi.slot_off + s] : make_uint2(0, 0);
     }
 
-    // gather: two staged cells and two staged nodes per lane per pass, all
-    // loads of a pass issued before its LDS stores
-    for (int t0 = tid; t0 < nc; t0 += 2 * T) {
-        const int t1 = t0 + T;
-        const bool has1 = t1 < nc;
-        const int64_t g0 = cell_id(t0);
-        const int64_t g1 = has1 ? cell_id(t1) : g0;
-        CellRegs<Real> c0, c1;
-        fetch_cell<LAYOUT, STAGING>(d, g0, c0);
-        fetch_cell<LAYOUT, STAGING>(d, g1, c1);
-        put_cell<STAGING>(s_inc, s_q, s_adt, nc, t0, c0);
-        if (has1) put_cell<STAGING>(s_inc, s_q, s_adt, nc, t1, c1);
-    }
-    if constexpr (STAGING == UM_STAGE_ALL) {
-        for (int t0 = tid; t0 < nn; t0 += 2 * T) {
-            const int t1 = t0 + T;
-            const bool has1 = t1 < nn;
-            const int64_t g0 = node_id(t0);
-            const int64_t g1 = has1 ? node_id(t1) : g0;
-            Real a0, a1, b0, b1;
-            load2<LAYOUT>(d.x, d.N, g0, a0, a1);
-            load2<LAYOUT>(d.x, d.N, g1, b0, b1);
-            s_x[t0] = a0;
-            s_x[nn + t0] = a1;
-            if (has1) {
-                s_x[t1] = b0;
-                s_x[nn + t1] = b1;
-            }
+    // gather: per pass every lane fetches at most one staged cell and one
+    // staged node, issuing all their loads before any LDS store (one memory
+    // wait per pass; a block of S edges has fewer than S staged cells and
+    // nodes, so with one edge per lane a single pass covers it)
+    const int npass = STAGING == UM_STAGE_ALL ? (nc > nn ? nc : nn) : nc;
+    for (int t = tid; t < npass; t += T) {
+        const bool hc = t < nc;
+        const bool hn = STAGING == UM_STAGE_ALL && t < nn;
+        CellRegs<Real> c;
+        Real xa = Real(0), xb = Real(0);
+        if (hc) fetch_cell<LAYOUT, STAGING>(d, cell_id(t), c);
+        if (hn) load2<LAYOUT>(d.x, d.N, node_id(t), xa, xb);
+        if (hc) put_cell<STAGING>(s_inc, s_q, s_adt, nc, t, c);
+        if (hn) {
+            s_x[t] = xa;
+            s_x[nn + t] = xb;
         }
     }
     __syncthreads();
@@ -352,38 +340,27 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     const int p0 = pred_off[pos], np = pred_off[pos + 1] - p0;
 
     const uint2 w = tid < ne ? loc[bi.slot_off + tid] : make_uint2(0, 0);
-    // gather the read-only data (q, adt, x); residuals come after the wait
-    for (int t0 = tid; t0 < nc; t0 += 2 * T) {
-        const int t1 = t0 + T;
-        const bool has1 = t1 < nc;
-        const int64_t g0 = cell_id(t0);
-        const int64_t g1 = has1 ? cell_id(t1) : g0;
-        Real q0[4], q1[4];
-        load4<LAYOUT>(d.q, d.C, g0, q0);
-        load4<LAYOUT>(d.q, d.C, g1, q1);
-        const Real a0 = d.adt[g0], a1 = d.adt[g1];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s_q[k * nc + t0] = q0[k];
-        s_adt[t0] = a0;
-        if (has1) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) s_q[k * nc + t1] = q1[k];
-            s_adt[t1] = a1;
+    // gather the read-only data (q, adt, x) in fused passes as in
+    // hier_kernel; residuals come after the wait
+    const int npass = nc > nn ? nc : nn;
+    for (int t = tid; t < npass; t += T) {
+        const bool hc = t < nc, hn = t < nn;
+        Real qv[4] = {Real(0), Real(0), Real(0), Real(0)}, av = Real(0);
+        Real xa = Real(0), xb = Real(0);
+        if (hc) {
+            const int64_t g = cell_id(t);
+            load4<LAYOUT>(d.q, d.C, g, qv);
+            av = d.adt[g];
         }
-    }
-    for (int t0 = tid; t0 < nn; t0 += 2 * T) {
-        const int t1 = t0 + T;
-        const bool has1 = t1 < nn;
-        const int64_t g0 = node_id(t0);
-        const int64_t g1 = has1 ? node_id(t1) : g0;
-        Real a0, a1, b0, b1;
-        load2<LAYOUT>(d.x, d.N, g0, a0, a1);
-        load2<LAYOUT>(d.x, d.N, g1, b0, b1);
-        s_x[t0] = a0;
-        s_x[nn + t0] = a1;
-        if (has1) {
-            s_x[t1] = b0;
-            s_x[nn + t1] = b1;
+        if (hn) load2<LAYOUT>(d.x, d.N, node_id(t), xa, xb);
+        if (hc) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_q[k * nc + t] = qv[k];
+            s_adt[t] = av;
+        }
+        if (hn) {
+            s_x[t] = xa;
+            s_x[nn + t] = xb;
         }
     }
     __syncthreads();
@@ -420,20 +397,11 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
 
     // residuals as accumulators
     const __amdgpu_buffer_rsrc_t rres = res_rsrc(d.res, d.C);
-    for (int t0 = tid; t0 < nc; t0 += 2 * T) {
-        const int t1 = t0 + T;
-        const bool has1 = t1 < nc;
-        const int64_t g0 = cell_id(t0);
-        const int64_t g1 = has1 ? cell_id(t1) : g0;
-        double r0[4], r1[4];
-        load4_dev<LAYOUT>(rres, d.C, g0, r0);
-        load4_dev<LAYOUT>(rres, d.C, g1, r1);
+    for (int t = tid; t < nc; t += T) {
+        double r[4];
+        load4_dev<LAYOUT>(rres, d.C, cell_id(t), r);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s_inc[k * nc + t0] = r0[k];
-        if (has1) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) s_inc[k * nc + t1] = r1[k];
-        }
+        for (int k = 0; k < 4; ++k) s_inc[k * nc + t] = r[k];
     }
     __syncthreads();
 
