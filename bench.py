@@ -207,21 +207,26 @@ def main() -> int:
         return 3
     log(f"hier ({args.schedule}): {sec * 1e6:.1f} us/step")
 
-    # per-launch kernel time over a second timed pass (HIP events around
-    # every launch, recorded by the library on the launch stream)
+    # roofline: the timed region above was bracketed by HIP events on the
+    # stream the library launches on (torch's current stream); its launches
+    # run back to back, so the average launch takes sec / launches_per_step
+    useful = measure.useful_bytes(N, C, E)
+    launches_per_step = st["n_launches"]
+    avg_launch_s = sec / launches_per_step
+    bytes_per_launch = useful / launches_per_step
+    achieved, frac = measure.roofline(bytes_per_launch, avg_launch_s)
+    # per-launch durations from event pairs the library records around every
+    # launch (a second pass; the extra event packets between launches make
+    # these slightly longer, so they are a diagnostic only)
     U.um_plan_set_timing(plan.handle, True)
     for _ in range(args.steps):
         run()
     kern_ms, n_launch = U.um_plan_timing(plan.handle)
     U.um_plan_set_timing(plan.handle, False)
     torch.cuda.synchronize()
-    useful = measure.useful_bytes(N, C, E)
-    launches_per_step = st["n_launches"]
-    avg_launch_s = kern_ms * 1e-3 / n_launch
-    bytes_per_launch = useful / launches_per_step
-    achieved, frac = measure.roofline(bytes_per_launch, avg_launch_s)
-    log(f"kernel time/step {kern_ms / args.steps * 1e3:.1f} us over {launches_per_step} launches; "
-        f"achieved {achieved:.0f} GB/s ({100 * frac:.1f}% of peak)")
+    log(f"avg launch {avg_launch_s * 1e6:.1f} us ({launches_per_step} per step), achieved "
+        f"{achieved:.0f} GB/s ({100 * frac:.1f}% of peak); per-launch events: "
+        f"{kern_ms / n_launch * 1e3:.1f} us")
 
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -390,6 +395,7 @@ def main() -> int:
                      "kernel": "hier_flow_kernel" if args.schedule == "dataflow" else "hier_kernel",
                      "launches_per_step": launches_per_step,
                      "avg_launch_us": avg_launch_s * 1e6,
+                     "avg_launch_us_event_pairs": kern_ms / n_launch * 1e3,
                      "bytes_per_launch": bytes_per_launch},
         "cpu_baseline": cpu,
         "baselines": baselines,
