@@ -189,10 +189,26 @@ int32_t plan_blocks(const Ctx &ctx, int32_t iter_set, const int32_t *wt, int ari
     hp.blk_order = counting_order(hp.blk_colour, nbcol, hp.bcol_off);
     hp.schedule = o.schedule;
     if (o.schedule == UM_SCHED_DATAFLOW) {
-        // predecessors of a launch position: its neighbours launched earlier,
-        // which are exactly its neighbours of smaller colour
+        // inside each colour after the first, launch first the blocks whose
+        // earlier-coloured neighbours were launched earliest (stable sort by
+        // the latest such neighbour's position), so that the blocks the
+        // dispatcher starts first rarely find a neighbour still running
         std::vector<int32_t> pos_of(nb);
         for (int32_t pos = 0; pos < nb; ++pos) pos_of[hp.blk_order[pos]] = pos;
+        std::vector<int32_t> key(nb, -1);
+        for (int32_t c = 1; c < nbcol; ++c) {
+            const int32_t p0 = hp.bcol_off[c], p1 = hp.bcol_off[c + 1];
+            for (int32_t pos = p0; pos < p1; ++pos) {
+                const int32_t b = hp.blk_order[pos];
+                for (int64_t i = adj_off[b]; i < adj_off[b + 1]; ++i)
+                    if (hp.blk_colour[adj[i]] < c) key[b] = std::max(key[b], pos_of[adj[i]]);
+            }
+            std::stable_sort(hp.blk_order.begin() + p0, hp.blk_order.begin() + p1,
+                             [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+            for (int32_t pos = p0; pos < p1; ++pos) pos_of[hp.blk_order[pos]] = pos;
+        }
+        // predecessors of a launch position: its neighbours launched earlier,
+        // which are exactly its neighbours of smaller colour
         hp.pred_off.assign(nb + 1, 0);
         hp.preds.clear();
         for (int32_t pos = 0; pos < nb; ++pos) {

@@ -319,6 +319,20 @@ def test_dataflow_plan_options():
         L.plan("hier", 128, schedule="dataflow", elems_per_thread=2)
     # a host-only plan reports no errors without touching a device
     assert U.um_plan_errors(p.handle) == 0
+    # launch order: colour by colour; inside a colour, by the latest launch
+    # position among the block's earlier-coloured neighbours
+    off = L.export(p, U.UM_EXP_BLOCK_OFFSETS)
+    bcol = L.export(p, U.UM_EXP_BLOCK_COLOURS)
+    order = L.export(p, U.UM_EXP_BLOCK_ORDER)
+    e2c = L.current_map("e2c")
+    assert P.check_block_colouring(off, bcol, e2c)
+    assert np.all(np.diff(bcol[order]) >= 0)
+    nbrs = P.block_neighbours(off, e2c)
+    pos = np.empty_like(order); pos[order] = np.arange(order.size)
+    key = np.array([max([pos[n] for n in nbrs[b] if bcol[n] < bcol[b]], default=-1) for b in order])
+    for c in range(1, bcol.max() + 1):
+        k = key[bcol[order] == c]
+        assert np.all(np.diff(k) >= 0)
 
 
 # ------------------------------------------------------------ hex element loop
