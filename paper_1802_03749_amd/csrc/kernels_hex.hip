@@ -14,6 +14,7 @@
 //  hex_debug_kernel  per-element forces with contraction disabled.
 #include <hip/hip_runtime.h>
 
+#include "device_staged.hpp"
 #include "internal.hpp"
 #include "launch.hpp"
 
@@ -85,17 +86,6 @@ __device__ __forceinline__ void lds_add(double *p, double v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ int32_t staged_id(const Run *__restrict__ runs, int r0, int nr,
-                                             const int32_t *__restrict__ list, int t) {
-    if (nr == 0) return list[t];
-    int32_t g = runs[r0].start + t;
-    for (int r = 1; r < nr; ++r) {
-        const Run R = runs[r0 + r];
-        if (t >= R.local) g = R.start + (t - R.local);
-    }
-    return g;
-}
-
 struct HexDats {
     const double *__restrict__ x;
     const double *__restrict__ v;
@@ -116,6 +106,8 @@ __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restr
     const int nn = bn.cell_off - bi.cell_off;
     const int nr = bn.crun_off - bi.crun_off;
     const int32_t *__restrict__ sl = stg + bi.cell_off;
+    dev::StagedIds staged_id;
+    staged_id.init(runs, bi.crun_off, nr, sl);
     double *s_acc = lds;           // [3][nn] force accumulators
     double *s_x = s_acc + 3 * nn;  // [3][nn]
     double *s_v = s_x + 3 * nn;    // [3][nn]
@@ -130,13 +122,13 @@ __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restr
         const bool has1 = t1 < nn;
         double xv[2][3], vv[2][3], fv[2][3];
         {
-            const int64_t g = staged_id(runs, bi.crun_off, nr, sl, t0);
+            const int64_t g = staged_id(t0);
             load3<LAYOUT>(d.x, d.N, g, xv[0]);
             load3<LAYOUT>(d.v, d.N, g, vv[0]);
             load3<LAYOUT>(d.force, d.N, g, fv[0]);
         }
         if (has1) {
-            const int64_t g = staged_id(runs, bi.crun_off, nr, sl, t1);
+            const int64_t g = staged_id(t1);
             load3<LAYOUT>(d.x, d.N, g, xv[1]);
             load3<LAYOUT>(d.v, d.N, g, vv[1]);
             load3<LAYOUT>(d.force, d.N, g, fv[1]);
@@ -198,7 +190,7 @@ __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restr
         __syncthreads();
     }
     for (int t = tid; t < nn; t += T) {
-        const int64_t g = staged_id(runs, bi.crun_off, nr, sl, t);
+        const int64_t g = staged_id(t);
 #pragma unroll
         for (int k = 0; k < 3; ++k) d.force[idx3<LAYOUT>(d.N, g, k)] = s_acc[k * nn + t];
     }

@@ -24,6 +24,7 @@
 
 #include "internal.hpp"
 #include "device_lf2d.hpp"
+#include "device_staged.hpp"
 #include "launch.hpp"
 
 namespace um {
@@ -33,6 +34,7 @@ using dev::lf2d_flux;
 using dev::lf2d_flux_nocontract;
 using dev::load2;
 using dev::load4;
+using dev::StagedIds;
 using dev::store4;
 
 
@@ -93,20 +95,6 @@ __device__ __forceinline__ void put_cell(double *s_inc, Real *s_q, Real *s_adt, 
     }
 }
 
-// Point id at staged position t of a block: from the block's run
-// descriptors (uniform, scalar loads) when it has any, else from its explicit
-// list.  Runs are ordered by `local`, the first one starts at 0.
-__device__ __forceinline__ int32_t staged_id(const Run *__restrict__ runs, int r0, int nr,
-                                             const int32_t *__restrict__ list, int t) {
-    if (nr == 0) return list[t];
-    int32_t g = runs[r0].start + t;
-    for (int r = 1; r < nr; ++r) {
-        const Run R = runs[r0 + r];
-        if (t >= R.local) g = R.start + (t - R.local);
-    }
-    return g;
-}
-
 // EPT = elements (edges) per lane: the workgroup has T lanes and handles a
 // block of up to EPT*T edges; lane l computes slots l, l+T, ...
 template <int LAYOUT, int STAGING, int TCMODE, int EPT, typename Real>
@@ -127,8 +115,9 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
     const int ncr = bn.crun_off - bi.crun_off, nnr = bn.nrun_off - bi.nrun_off;
     const int32_t *__restrict__ sc = stg_c + bi.cell_off;
     const int32_t *__restrict__ sn = stg_n + bi.node_off;
-    auto cell_id = [&](int t) { return staged_id(crun, bi.crun_off, ncr, sc, t); };
-    auto node_id = [&](int t) { return staged_id(nrun, bi.nrun_off, nnr, sn, t); };
+    StagedIds cell_id, node_id;
+    cell_id.init(crun, bi.crun_off, ncr, sc);
+    node_id.init(nrun, bi.nrun_off, nnr, sn);
     double *s_inc = lds;                                      // [4][nc] accumulators
     Real *s_q = reinterpret_cast<Real *>(s_inc + 4 * nc);     // [4][nc]
     Real *s_adt = s_q + 4 * nc;                               // [nc]
@@ -330,8 +319,9 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     const int ncr = bn.crun_off - bi.crun_off, nnr = bn.nrun_off - bi.nrun_off;
     const int32_t *__restrict__ sc = stg_c + bi.cell_off;
     const int32_t *__restrict__ sn = stg_n + bi.node_off;
-    auto cell_id = [&](int t) { return staged_id(crun, bi.crun_off, ncr, sc, t); };
-    auto node_id = [&](int t) { return staged_id(nrun, bi.nrun_off, nnr, sn, t); };
+    StagedIds cell_id, node_id;
+    cell_id.init(crun, bi.crun_off, ncr, sc);
+    node_id.init(nrun, bi.nrun_off, nnr, sn);
     double *s_inc = lds;
     Real *s_q = reinterpret_cast<Real *>(s_inc + 4 * nc);
     Real *s_adt = s_q + 4 * nc;
