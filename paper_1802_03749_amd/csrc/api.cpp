@@ -254,6 +254,7 @@ LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *str
     la.crun = p.dp.crun;
     la.nrun = p.dp.nrun;
     la.loc = p.dp.loc;
+    la.n_slots = p.hp.n_elem;
     la.emap = p.dp.emap;
     const Dat &x = ctx.dats[p.ea.dat_x], &q = ctx.dats[p.ea.dat_q];
     const Dat &adt = ctx.dats[p.ea.dat_adt], &res = ctx.dats[p.ea.dat_res];
@@ -695,11 +696,12 @@ um_status um_plan_export(um_plan plan, int32_t field, int32_t *host_out, int64_t
             }
             tmp.resize(4 * hp.n_elem);
             for (int64_t s = 0; s < hp.n_elem; ++s) {
-                const uint32_t w0 = hp.loc[2 * s], w1 = hp.loc[2 * s + 1];
-                tmp[4 * s] = int32_t(w0 & 0x7FFu);
-                tmp[4 * s + 1] = int32_t((w0 >> 16) & 0x7FFu);
-                tmp[4 * s + 2] = int32_t(w1 & 0xFFFFu);
-                tmp[4 * s + 3] = int32_t(w1 >> 16);
+                const uint32_t a = hp.loc[s];
+                const uint32_t h = (hp.loc[hp.n_elem + s / 2] >> (16 * (s & 1))) & 0xFFFFu;
+                tmp[4 * s] = int32_t(a & 0x7FFu);
+                tmp[4 * s + 1] = int32_t((a >> 11) & 0x7FFu);
+                tmp[4 * s + 2] = int32_t(((a >> 22) & 0x3FFu) | ((h & 1u) << 10));
+                tmp[4 * s + 3] = int32_t((h >> 1) & 0x7FFu);
             }
             break;
         default: fail(UM_ERR_ARG, "unknown export field %d", field);

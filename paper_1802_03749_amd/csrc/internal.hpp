@@ -139,7 +139,7 @@ struct HostPlan {
     std::vector<int32_t> stg_c, stg_n;         // launch order
     std::vector<Run> crun, nrun;               // run encoding of stg_c, stg_n
     int32_t use_runs = 1;
-    std::vector<uint32_t> loc;                 // [n_slots][2]: (lL|lR<<16 | col<<11), (nA|nB<<16)
+    std::vector<uint32_t> loc;                 // LF2D: [n_slots] words + [n_slots] halves; hex: [n_slots][4]
     std::vector<int32_t> slot_elem;            // slot -> element
     std::vector<int32_t> tcol;                 // element -> thread colour
     std::vector<int64_t> lds_per_colour;       // max LDS bytes per block colour

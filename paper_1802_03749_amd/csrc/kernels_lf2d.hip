@@ -103,7 +103,8 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
                                                     const int32_t *__restrict__ stg_n,
                                                     const Run *__restrict__ crun,
                                                     const Run *__restrict__ nrun,
-                                                    const uint2 *__restrict__ loc, Dats<Real> d,
+                                                    const uint32_t *__restrict__ loc,
+                                                    int64_t n_slots, Dats<Real> d,
                                                     double gm1d, double epsd, int32_t base) {
     extern __shared__ double lds[];
     const Real gm1 = Real(gm1d), eps = Real(epsd);
@@ -126,11 +127,13 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
 
     // local index words of this lane's slots: issued first, used after the
     // barrier
-    uint2 w[EPT];
+    const uint16_t *__restrict__ loc16 = reinterpret_cast<const uint16_t *>(loc + n_slots);
+    uint32_t wa[EPT], wb[EPT];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const int s = tid + j * T;
-        w[j] = s < ne ? loc[bi.slot_off + s] : make_uint2(0, 0);
+        wa[j] = s < ne ? loc[bi.slot_off + s] : 0u;
+        wb[j] = s < ne ? uint32_t(loc16[bi.slot_off + s]) : 0u;
     }
 
     // gather: per pass every lane fetches at most one staged cell and one
@@ -158,10 +161,11 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
     Real f[EPT][4];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-        lL[j] = int(w[j].x & 0x7FFu);
-        col[j] = (tid + j * T) < ne ? int((w[j].x >> 11) & 31u) : -1;
-        lR[j] = int((w[j].x >> 16) & 0x7FFu);
-        const int nA = int(w[j].y & 0xFFFFu), nB = int(w[j].y >> 16);
+        lL[j] = int(wa[j] & 0x7FFu);
+        lR[j] = int((wa[j] >> 11) & 0x7FFu);
+        col[j] = (tid + j * T) < ne ? int(wb[j] >> 12) : -1;
+        const int nA = int((wa[j] >> 22) | ((wb[j] & 1u) << 10));
+        const int nB = int((wb[j] >> 1) & 0x7FFu);
 #pragma unroll
         for (int k = 0; k < 4; ++k) f[j][k] = Real(0);
         if (col[j] >= 0) {
@@ -303,7 +307,7 @@ template <int LAYOUT, int TCMODE, typename Real>
 __global__ __launch_bounds__(1024) void hier_flow_kernel(
     const BlockInfo *__restrict__ binfo, const int32_t *__restrict__ stg_c,
     const int32_t *__restrict__ stg_n, const Run *__restrict__ crun, const Run *__restrict__ nrun,
-    const uint2 *__restrict__ loc, Dats<Real> d, double gm1d, double epsd,
+    const uint32_t *__restrict__ loc, int64_t n_slots, Dats<Real> d, double gm1d, double epsd,
     const int32_t *__restrict__ pred_off, const int32_t *__restrict__ preds, int32_t *flags,
     int32_t *ctl) {
     extern __shared__ double lds[];
@@ -329,7 +333,9 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     const int tid = int(threadIdx.x), T = int(blockDim.x);
     const int p0 = pred_off[pos], np = pred_off[pos + 1] - p0;
 
-    const uint2 w = tid < ne ? loc[bi.slot_off + tid] : make_uint2(0, 0);
+    const uint16_t *__restrict__ loc16 = reinterpret_cast<const uint16_t *>(loc + n_slots);
+    const uint32_t wa = tid < ne ? loc[bi.slot_off + tid] : 0u;
+    const uint32_t wb = tid < ne ? uint32_t(loc16[bi.slot_off + tid]) : 0u;
     // gather the read-only data (q, adt, x) in fused passes as in
     // hier_kernel; residuals come after the wait
     const int npass = nc > nn ? nc : nn;
@@ -355,11 +361,12 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     }
     __syncthreads();
 
-    const int lL = int(w.x & 0x7FFu), lR = int((w.x >> 16) & 0x7FFu);
-    const int col = tid < ne ? int((w.x >> 11) & 31u) : -1;
+    const int lL = int(wa & 0x7FFu), lR = int((wa >> 11) & 0x7FFu);
+    const int col = tid < ne ? int(wb >> 12) : -1;
     Real f[4] = {Real(0), Real(0), Real(0), Real(0)};
     if (col >= 0) {
-        const int nA = int(w.y & 0xFFFFu), nB = int(w.y >> 16);
+        const int nA = int((wa >> 22) | ((wb & 1u) << 10));
+        const int nB = int((wb >> 1) & 0x7FFu);
         Real qL[4], qR[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -497,7 +504,7 @@ hipError_t launch_hier_one(const LaunchArgs &la, int32_t nblocks, int32_t base, 
     }
     hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, EPT, Real>), dim3(nblocks),
                        dim3(la.block_size), size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n,
-                       la.crun, la.nrun, reinterpret_cast<const uint2 *>(la.loc), d, la.gm1,
+                       la.crun, la.nrun, la.loc, la.n_slots, d, la.gm1,
                        la.eps, base);
     return hipGetLastError();
 }
@@ -535,7 +542,7 @@ hipError_t launch_flow(const LaunchArgs &la, int32_t nblocks, int64_t lds, const
     }
     hipLaunchKernelGGL((hier_flow_kernel<LAYOUT, TC, Real>), dim3(nblocks), dim3(la.block_size),
                        size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun,
-                       reinterpret_cast<const uint2 *>(la.loc), d, la.gm1, la.eps, la.pred_off,
+                       la.loc, la.n_slots, d, la.gm1, la.eps, la.pred_off,
                        la.preds, la.flags, la.err);
     return hipGetLastError();
 }

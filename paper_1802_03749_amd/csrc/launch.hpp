@@ -17,6 +17,7 @@ struct LaunchArgs {
     const int32_t *stg_c, *stg_n;
     const Run *crun, *nrun;
     const uint32_t *loc;
+    int64_t n_slots;          // LF2D: slots of the plan (the 16-bit halves follow the words)
     const int32_t *emap;
     const void *x, *q, *adt;  // UM_F64 or UM_F32 per dtype
     double *res;

@@ -265,7 +265,10 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     // ---- per block in launch order: staged lists, layer 2 colouring, slots
     std::vector<int32_t> cloc(C, -1), nloc(ctx.sets[mn.to].size, -1);
     hp.binfo.resize(nb + 1);
-    hp.loc.resize(2 * E);
+    // local index words: E 32-bit words (lL | lR << 11 | nA[0:10) << 22),
+    // then E 16-bit halves (nA >> 10 | nB << 1 | colour << 12), packed two
+    // per 32-bit word: 6 bytes per edge
+    hp.loc.assign(E + (E + 1) / 2, 0u);
     hp.slot_elem.resize(E);
     hp.tcol.assign(E, 0);
     hp.stg_c.clear();
@@ -299,7 +302,7 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
         const int32_t nc = int32_t(hp.stg_c.size() - c0), nn = int32_t(hp.stg_n.size() - n0);
         for (int32_t i = 0; i < nc; ++i) cloc[hp.stg_c[c0 + i]] = i;
         for (int32_t i = 0; i < nn; ++i) nloc[hp.stg_n[n0 + i]] = i;
-        if (nc > 2048 || nn > 65535)
+        if (nc > 2048 || nn > 2048)
             fail(UM_ERR_UNSUPPORTED, "block %d stages %d cells / %d nodes", b, nc, nn);
 
         // layer 2: first-fit over the block's edges with per-cell bit masks
@@ -310,8 +313,8 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
             const int64_t e = e0 + i;
             const int32_t lL = cloc[mc.table[2 * e]], lR = cloc[mc.table[2 * e + 1]];
             uint32_t taken = uint32_t(mask[lL]) | uint32_t(mask[lR]);
-            if (taken == 0xFFFFFFFFu)
-                fail(UM_ERR_UNSUPPORTED, "block %d needs more than 32 thread colours", b);
+            if ((taken & 0xFFFFu) == 0xFFFFu)
+                fail(UM_ERR_UNSUPPORTED, "block %d needs more than 16 thread colours", b);
             int32_t c = __builtin_ctz(~taken);
             ecol[i] = c;
             mask[lL] |= 1 << c;
@@ -343,8 +346,8 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
             const uint32_t lL = cloc[mc.table[2 * e]], lR = cloc[mc.table[2 * e + 1]];
             const uint32_t nA = nloc[mn.table[2 * e]], nB = nloc[mn.table[2 * e + 1]];
             const uint32_t c = uint32_t(ecol[order[i]]);
-            hp.loc[2 * slot] = lL | (c << 11) | (lR << 16);
-            hp.loc[2 * slot + 1] = nA | (nB << 16);
+            hp.loc[slot] = lL | (lR << 11) | ((nA & 0x3FFu) << 22);
+            hp.loc[E + slot / 2] |= ((nA >> 10) | (nB << 1) | (c << 12)) << (16 * (slot & 1));
             hp.slot_elem[slot] = int32_t(e);
             hp.tcol[e] = int32_t(c);
             ++slot;
