@@ -95,8 +95,12 @@ typedef enum { UM_TC_BARRIER = 0, UM_TC_LDS_ATOMIC = 1 } um_tcmode;
  * decreasing colour, first-fit again; never more colours) and one balancing
  * pass (in block order a block moves to the least used colour none of its
  * neighbours holds when that class is smaller by two or more); fewer and
- * more even launches. */
-typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1 } um_bcolouring;
+ * more even launches.
+ * MIN: as RECOLOUR, but before the balancing pass also a DSatur colouring
+ * (Brelaz) and then a tabu search (Hertz and de Werra's TabuCol,
+ * deterministic, bounded to 100 moves per block) for one colour fewer at a
+ * time; the plan keeps the fewest colours found.  Slower to build. */
+typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1, UM_BCOL_MIN = 2 } um_bcolouring;
 /* How block colours are ordered in time (HIER).  COLOUR_LAUNCHES: one kernel
  * launch per block colour (the kernel boundary orders colours, Section 2.2).
  * DATAFLOW: one launch over all blocks in colour order; each block computes

@@ -511,7 +511,8 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
         if (o.max_block_colours < 0 || o.lds_limit_bytes < 0) fail(UM_ERR_ARG, "negative limit");
         if (o.elems_per_thread != 0 && o.elems_per_thread != 1 && o.elems_per_thread != 2)
             fail(UM_ERR_ARG, "elems_per_thread %d not in {1, 2}", o.elems_per_thread);
-        if (o.block_colouring != UM_BCOL_FIRST_FIT && o.block_colouring != UM_BCOL_RECOLOUR)
+        if (o.block_colouring != UM_BCOL_FIRST_FIT && o.block_colouring != UM_BCOL_RECOLOUR &&
+            o.block_colouring != UM_BCOL_MIN)
             fail(UM_ERR_ARG, "bad block_colouring %d", o.block_colouring);
         if (o.schedule != UM_SCHED_COLOUR_LAUNCHES && o.schedule != UM_SCHED_DATAFLOW)
             fail(UM_ERR_ARG, "bad schedule %d", o.schedule);

@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <cstring>
 #include <numeric>
+#include <set>
 
 #include "internal.hpp"
 
@@ -63,6 +64,130 @@ int32_t global_colours(const Map &mc, int64_t C, std::vector<int32_t> &colour) {
         ncol = std::max(ncol, c + 1);
     }
     return ncol;
+}
+
+// DSatur (Brelaz): repeatedly colour, with its smallest free colour, the
+// uncoloured block whose neighbours hold the most distinct colours (ties:
+// more uncoloured neighbours, then the smaller id).  Returns the number of
+// colours, or 0 if it would need more than 64.
+static int32_t dsatur(const std::vector<int64_t> &adj_off, const std::vector<int32_t> &adj,
+                      std::vector<int32_t> &col) {
+    const int32_t nb = int32_t(adj_off.size()) - 1;
+    col.assign(nb, -1);
+    std::vector<uint64_t> seen(nb, 0);
+    std::vector<int32_t> sat(nb, 0), deg(nb);
+    for (int32_t b = 0; b < nb; ++b) deg[b] = int32_t(adj_off[b + 1] - adj_off[b]);
+    struct Key {
+        int32_t sat, deg, id;
+        bool operator<(const Key &o) const {
+            if (sat != o.sat) return sat > o.sat;
+            if (deg != o.deg) return deg > o.deg;
+            return id < o.id;
+        }
+    };
+    std::set<Key> q;
+    for (int32_t b = 0; b < nb; ++b) q.insert(Key{0, deg[b], b});
+    int32_t ncol = 0;
+    while (!q.empty()) {
+        const int32_t b = q.begin()->id;
+        q.erase(q.begin());
+        if (~seen[b] == 0) return 0;
+        const int32_t c = __builtin_ctzll(~seen[b]);
+        col[b] = c;
+        ncol = std::max(ncol, c + 1);
+        for (int64_t i = adj_off[b]; i < adj_off[b + 1]; ++i) {
+            const int32_t n = adj[i];
+            if (col[n] >= 0) continue;
+            q.erase(Key{sat[n], deg[n], n});
+            if (!(seen[n] >> c & 1)) {
+                seen[n] |= 1ull << c;
+                sat[n]++;
+            }
+            deg[n]--;
+            q.insert(Key{sat[n], deg[n], n});
+        }
+    }
+    return ncol;
+}
+
+// Tabu search for a proper k-colouring of the block graph (Hertz and de
+// Werra's TabuCol), starting from `col` with colour x folded onto x mod k:
+// each step moves one conflicting block (among at most 40 sampled) to the
+// colour that removes the most conflicts (ties broken at random), never back
+// to a colour it left in the last 10-15 steps.  Deterministic (fixed-seed SplitMix64).  On success
+// `col` holds the k-colouring; otherwise it is unchanged.
+static bool tabu_colouring(const std::vector<int64_t> &adj_off, const std::vector<int32_t> &adj,
+                           int32_t k, int64_t max_iter, std::vector<int32_t> &col) {
+    const int32_t nb = int32_t(col.size());
+    uint64_t rng = 0x243F6A8885A308D3ull;
+    auto next = [&rng]() {
+        uint64_t z = (rng += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    std::vector<int32_t> c(nb);
+    for (int32_t b = 0; b < nb; ++b) c[b] = col[b] % k;
+    std::vector<int32_t> g(int64_t(nb) * k, 0);  // neighbours of b holding colour x
+    for (int32_t b = 0; b < nb; ++b)
+        for (int64_t i = adj_off[b]; i < adj_off[b + 1]; ++i) g[int64_t(b) * k + c[adj[i]]]++;
+    std::vector<int32_t> cl, where(nb, -1);   // conflicting blocks
+    auto refresh = [&](int32_t b) {
+        const bool in = g[int64_t(b) * k + c[b]] > 0;
+        if (in && where[b] < 0) {
+            where[b] = int32_t(cl.size());
+            cl.push_back(b);
+        } else if (!in && where[b] >= 0) {
+            const int32_t last = cl.back();
+            cl[where[b]] = last;
+            where[last] = where[b];
+            cl.pop_back();
+            where[b] = -1;
+        }
+    };
+    int64_t conf = 0;
+    for (int32_t b = 0; b < nb; ++b) {
+        conf += g[int64_t(b) * k + c[b]];
+        refresh(b);
+    }
+    conf /= 2;
+    std::vector<int64_t> tabu(int64_t(nb) * k, 0);
+    for (int64_t it = 1; conf > 0 && it <= max_iter; ++it) {
+        int32_t mb = -1, mc = -1;
+        int64_t md = 0;
+        uint64_t ties = 0;  // equal best moves seen: one is kept uniformly
+        const size_t ns = std::min<size_t>(cl.size(), 40);
+        for (size_t j = 0; j < ns; ++j) {
+            const int32_t b = cl.size() <= 40 ? cl[j] : cl[next() % cl.size()];
+            for (int32_t x = 0; x < k; ++x) {
+                if (x == c[b] || tabu[int64_t(b) * k + x] > it) continue;
+                const int64_t d = int64_t(g[int64_t(b) * k + x]) - g[int64_t(b) * k + c[b]];
+                if (mb < 0 || d < md) {
+                    mb = b;
+                    mc = x;
+                    md = d;
+                    ties = 1;
+                } else if (d == md && next() % ++ties == 0) {
+                    mb = b;
+                    mc = x;
+                }
+            }
+        }
+        if (mb < 0) continue;
+        const int32_t old = c[mb];
+        tabu[int64_t(mb) * k + old] = it + 10 + int64_t(next() % 6);
+        c[mb] = mc;
+        for (int64_t i = adj_off[mb]; i < adj_off[mb + 1]; ++i) {
+            g[int64_t(adj[i]) * k + old]--;
+            g[int64_t(adj[i]) * k + mc]++;
+        }
+        conf += md;
+        refresh(mb);
+        for (int64_t i = adj_off[mb]; i < adj_off[mb + 1]; ++i) refresh(adj[i]);
+    }
+    if (conf != 0) return false;
+    col = c;
+    return true;
 }
 
 // Blocks, layer-1 colouring, launch order and dataflow predecessors: the
@@ -161,13 +286,28 @@ int32_t plan_blocks(const Ctx &ctx, int32_t iter_set, const int32_t *wt, int ari
     std::vector<int32_t> order(nb);
     std::iota(order.begin(), order.end(), 0);
     int32_t nbcol = first_fit(order, hp.blk_colour);
-    if (o.block_colouring == UM_BCOL_RECOLOUR && nb > 0) {
+    if ((o.block_colouring == UM_BCOL_RECOLOUR || o.block_colouring == UM_BCOL_MIN) && nb > 0) {
         // one iterated-greedy pass: colour classes revisited from the last to
         // the first (ties by block id) never need more colours
         std::vector<int32_t> prev = hp.blk_colour;
         std::stable_sort(order.begin(), order.end(),
                          [&](int32_t x, int32_t y) { return prev[x] > prev[y]; });
         nbcol = first_fit(order, hp.blk_colour);
+        if (o.block_colouring == UM_BCOL_MIN) {
+            // DSatur, then tabu search for one colour fewer at a time
+            std::vector<int32_t> ds;
+            const int32_t nds = dsatur(adj_off, adj, ds);
+            if (nds > 0 && nds < nbcol) {
+                hp.blk_colour = ds;
+                nbcol = nds;
+            }
+            std::vector<int32_t> cur = nds > 0 ? ds : hp.blk_colour;
+            while (nbcol > 1 &&
+                   tabu_colouring(adj_off, adj, nbcol - 1, 100 * int64_t(nb) + 100000, cur)) {
+                hp.blk_colour = cur;
+                --nbcol;
+            }
+        }
         // balancing: in block order, move a block to the least used colour
         // none of its neighbours holds, if that class is smaller by two or more
         std::vector<int64_t> count(nbcol, 0);

@@ -24,7 +24,8 @@ STRATEGIES = {"atomic": U.UM_STRAT_ATOMIC, "global": U.UM_STRAT_GLOBAL_COLOUR,
 LAYOUTS = {"aos": U.UM_AOS, "soa": U.UM_SOA}
 STAGING = {"all": U.UM_STAGE_ALL, "inc": U.UM_STAGE_INC_ONLY}
 TCMODES = {"barrier": U.UM_TC_BARRIER, "lds_atomic": U.UM_TC_LDS_ATOMIC}
-BCOLOURING = {"first_fit": U.UM_BCOL_FIRST_FIT, "recolour": U.UM_BCOL_RECOLOUR}
+BCOLOURING = {"first_fit": U.UM_BCOL_FIRST_FIT, "recolour": U.UM_BCOL_RECOLOUR,
+              "min": U.UM_BCOL_MIN}
 SCHEDULES = {"colour_launches": U.UM_SCHED_COLOUR_LAUNCHES, "dataflow": U.UM_SCHED_DATAFLOW}
 
 

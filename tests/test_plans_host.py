@@ -433,3 +433,19 @@ def test_user_blocks_reorder_and_plan():
     with pytest.raises(U.UmeshError):        # a tile larger than block_size
         EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=-1, order="user", block_size=100,
                      edge_blocks=tiles)
+
+
+def test_min_block_colouring_is_valid_and_no_worse():
+    """DSatur + tabu search: a valid block colouring with at most as many
+    colours as RECOLOUR (here 4 on a mesh where first-fit needs more)."""
+    m, L = make(nx=200, ny=100, order="rcm+partition", block_size=512)
+    pr = L.plan("hier", 512, block_colouring="recolour")
+    pm = L.plan("hier", 512, block_colouring="min")
+    off = L.export(pm, U.UM_EXP_BLOCK_OFFSETS)
+    bcol = L.export(pm, U.UM_EXP_BLOCK_COLOURS)
+    assert P.check_block_colouring(off, bcol, L.current_map("e2c"))
+    assert pm.stats["n_block_colours"] <= pr.stats["n_block_colours"]
+    assert pm.stats["n_block_colours"] == 4
+    # deterministic
+    pm2 = L.plan("hier", 512, block_colouring="min")
+    assert np.array_equal(L.export(pm2, U.UM_EXP_BLOCK_COLOURS), bcol)
