@@ -245,6 +245,17 @@ def main() -> int:
                                  "useful_gbps": useful / s2 / 1e9,
                                  "launches": p2.stats["n_launches"]}
     log(f"hier ({other}): {s2 * 1e6:.1f} us/step")
+    # LDS atomics instead of thread-colour rounds (an extension; the order of
+    # additions inside a block is then not fixed)
+    if args.tcmode != "lds_atomic":
+        o4 = dict(hopts); o4["tcmode"] = "lds_atomic"
+        p4 = hier.plan("hier", S, schedule=args.schedule, **o4)
+        s4 = time_steps(torch, lambda: hier.run(p4), args.steps, args.warmup)
+        variants[f"fp64_{args.schedule}_lds_atomic"] = {
+            "edges_per_s": E / s4, "ms_per_step": s4 * 1e3, "useful_gbps": useful / s4 / 1e9,
+            "pct_hbm_peak": 100 * useful / s4 / 1e9 / measure.HBM_PEAK_GBPS,
+            "launches": p4.stats["n_launches"]}
+        log(f"hier ({args.schedule}, lds atomics): {s4 * 1e6:.1f} us/step")
     # the headline plan's launches captured in one HIP graph and replayed
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
@@ -298,11 +309,18 @@ def main() -> int:
                                  ("rcm", "atomic", 256)):
             H = HexLoop(hm.x, hm.v, hm.e2n, device=0, order=order, block_size=hS,
                         layout=args.layout)
-            p = H.plan(strat, hS, block_colouring="recolour" if strat == "hier" else "first_fit")
+            p = H.plan(strat, hS, block_colouring="min" if strat == "hier" else "first_fit")
             s = time_steps(torch, lambda: H.run(p), max(args.steps // 2, 1), args.warmup)
             hx[strat] = {"order": order, "elements_per_s": hm.n_elems / s, "ms_per_step": s * 1e3,
                          "useful_gbps": hb / s / 1e9, "launches": p.stats["n_launches"]}
             log(f"hex {strat}: {s * 1e6:.1f} us/step ({hb / s / 1e9:.0f} GB/s)")
+            if strat == "hier":
+                p2 = H.plan(strat, hS, block_colouring="min", tcmode="lds_atomic")
+                s2 = time_steps(torch, lambda: H.run(p2), max(args.steps // 2, 1), args.warmup)
+                hx["hier_lds_atomic"] = {"order": order, "elements_per_s": hm.n_elems / s2,
+                                         "ms_per_step": s2 * 1e3, "useful_gbps": hb / s2 / 1e9,
+                                         "launches": p2.stats["n_launches"]}
+                log(f"hex hier lds atomics: {s2 * 1e6:.1f} us/step")
             H.close()
         extras["hex_hourglass_128cubed"] = hx
 
