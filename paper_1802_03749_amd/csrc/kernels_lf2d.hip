@@ -425,11 +425,24 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
         __syncthreads();
     }
 
-    for (int t = tid; t < nc; t += T) {
-        double r[4];
+    if constexpr (LAYOUT == UM_AOS) {
+        // write-through stores: lane pairs write the two 16-byte halves of a
+        // cell, so that one store instruction covers whole lines of a run of
+        // consecutive cells (a partly written line costs a second write)
+        for (int u = tid; u < 2 * nc; u += T) {
+            const int t = u >> 1, h = u & 1;
+            const f64x2 v = {s_inc[(2 * h) * nc + t], s_inc[(2 * h + 1) * nc + t]};
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rres,
+                                                   int32_t(32 * int64_t(cell_id(t)) + 16 * h), 0,
+                                                   CPOL_SC1);
+        }
+    } else {
+        for (int t = tid; t < nc; t += T) {
+            double r[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) r[k] = s_inc[k * nc + t];
-        store4_dev<LAYOUT>(rres, d.C, cell_id(t), r);
+            for (int k = 0; k < 4; ++k) r[k] = s_inc[k * nc + t];
+            store4_dev<LAYOUT>(rres, d.C, cell_id(t), r);
+        }
     }
     // publish: every lane's stores complete, then one flag store
     __builtin_amdgcn_s_waitcnt(0);
