@@ -192,6 +192,11 @@ LaunchArgs launch_args_hex(Plan &p, const double *params, int32_t nparams, void 
     la.res = static_cast<double *>(f.ptr);
     la.N = ctx.sets[x.set].size;
     la.gm1 = params[0];
+    la.schedule = p.hp.schedule;
+    la.pred_off = p.dp.pred_off;
+    la.preds = p.dp.preds;
+    la.flags = p.dp.flags;
+    la.err = p.dp.err;
     return la;
 }
 

@@ -10,6 +10,8 @@
 //                    accumulators are stored back once.
 //  hex_gcol_kernel   global colouring: one launch per colour, plain
 //                    read-modify-write of force.
+//  hex_flow_kernel   the dataflow schedule: one launch, each block waits for
+//                    its earlier-coloured neighbours before its write-back.
 //  hex_atomic_kernel one launch, hardware FP64 atomic adds.
 //  hex_debug_kernel  per-element forces with contraction disabled.
 #include <hip/hip_runtime.h>
@@ -196,6 +198,155 @@ __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restr
     }
 }
 
+// DATAFLOW schedule of the hex loop (the protocol of hier_flow_kernel in
+// kernels_lf2d.hip: one launch over all blocks in colour order; a block
+// gathers x and v and computes its forces, waits until the completion flags
+// of its earlier-coloured neighbours hold this execution's epoch (its own
+// flag + 1), then loads, updates and stores the force accumulators of its
+// staged nodes with device-scope (sc1) accesses and publishes its flag).
+// Force accesses go through a buffer resource over force (24 N bytes);
+// with AoS, consecutive lanes handle consecutive doubles, so one instruction
+// covers whole lines of a run of consecutive nodes.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int HEX_CPOL_SC1 = 16;
+constexpr uint64_t HEX_FLOW_WAIT_TICKS = 20000000ull;  // s_memrealtime at 100 MHz: 0.2 s
+
+template <int LAYOUT, int TCMODE>
+__global__ __launch_bounds__(1024) void hex_flow_kernel(
+    const BlockInfo *__restrict__ binfo, const int32_t *__restrict__ stg,
+    const Run *__restrict__ runs, const uint4 *__restrict__ loc, HexDats d, double kappa,
+    const int32_t *__restrict__ pred_off, const int32_t *__restrict__ preds, int32_t *flags,
+    int32_t *ctl) {
+    extern __shared__ double lds[];
+    const int32_t pos = int32_t(blockIdx.x);
+    const int32_t epoch =
+        __hip_atomic_load(flags + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    const BlockInfo bi = binfo[pos], bn = binfo[pos + 1];
+    const int ne = bn.slot_off - bi.slot_off;
+    const int nn = bn.cell_off - bi.cell_off;
+    const int nr = bn.crun_off - bi.crun_off;
+    const int32_t *__restrict__ sl = stg + bi.cell_off;
+    dev::StagedIds staged_id;
+    staged_id.init(runs, bi.crun_off, nr, sl);
+    double *s_acc = lds;           // [3][nn] force accumulators
+    double *s_x = s_acc + 3 * nn;  // [3][nn]
+    double *s_v = s_x + 3 * nn;    // [3][nn]
+    const int tid = int(threadIdx.x), T = int(blockDim.x);
+    const int p0 = pred_off[pos], np = pred_off[pos + 1] - p0;
+
+    const uint4 w = tid < ne ? loc[bi.slot_off + tid] : make_uint4(0, 0, 0, 0);
+    for (int t0 = tid; t0 < nn; t0 += 2 * T) {
+        const int t1 = t0 + T;
+        const bool has1 = t1 < nn;
+        double xv[2][3], vv[2][3];
+        {
+            const int64_t g = staged_id(t0);
+            load3<LAYOUT>(d.x, d.N, g, xv[0]);
+            load3<LAYOUT>(d.v, d.N, g, vv[0]);
+        }
+        if (has1) {
+            const int64_t g = staged_id(t1);
+            load3<LAYOUT>(d.x, d.N, g, xv[1]);
+            load3<LAYOUT>(d.v, d.N, g, vv[1]);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_x[k * nn + t0] = xv[0][k];
+            s_v[k * nn + t0] = vv[0][k];
+        }
+        if (has1) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                s_x[k * nn + t1] = xv[1][k];
+                s_v[k * nn + t1] = vv[1][k];
+            }
+        }
+    }
+    __syncthreads();
+
+    int l[8];
+    l[0] = int(w.x & 0x7FFu); l[1] = int(w.x >> 16);
+    l[2] = int(w.y & 0xFFFFu); l[3] = int(w.y >> 16);
+    l[4] = int(w.z & 0xFFFFu); l[5] = int(w.z >> 16);
+    l[6] = int(w.w & 0xFFFFu); l[7] = int(w.w >> 16);
+    const int col = tid < ne ? int((w.x >> 11) & 31u) : -1;
+    double f[8][3] = {};
+    if (col >= 0) {
+        double xe[8][3], ve[8][3];
+#pragma unroll
+        for (int a = 0; a < 8; ++a)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                xe[a][k] = s_x[k * nn + l[a]];
+                ve[a][k] = s_v[k * nn + l[a]];
+            }
+        hex_force(xe, ve, kappa, f);
+    }
+
+    // wait for the earlier-coloured neighbours (np <= 64: first wavefront)
+    if (tid < np) {
+        const int32_t *fl = flags + preds[p0 + tid];
+        const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+            if (__hip_atomic_load(ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+            if (__builtin_amdgcn_s_memrealtime() - t_begin > HEX_FLOW_WAIT_TICKS) {
+                __hip_atomic_fetch_add(ctl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+    __syncthreads();
+
+    // force accumulators: device-scope loads
+    const __amdgpu_buffer_rsrc_t rf =
+        __builtin_amdgcn_make_buffer_rsrc(d.force, 0, int32_t(24 * d.N), 0x00020000);
+    auto foff = [&](int t, int k) {
+        const int64_t g = staged_id(t);
+        return int32_t(8 * (LAYOUT == UM_AOS ? 3 * g + k : k * d.N + g));
+    };
+    for (int u = tid; u < 3 * nn; u += T) {
+        const int t = LAYOUT == UM_AOS ? u / 3 : u % nn;
+        const int k = LAYOUT == UM_AOS ? u % 3 : u / nn;
+        s_acc[k * nn + t] = __builtin_bit_cast(
+            double, __builtin_amdgcn_raw_buffer_load_b64(rf, foff(t, k), 0, HEX_CPOL_SC1));
+    }
+    __syncthreads();
+
+    if constexpr (TCMODE == UM_TC_BARRIER) {
+        const int ncol = bi.ncol;
+        for (int c = 0; c < ncol; ++c) {
+            if (col == c) {
+#pragma unroll
+                for (int a = 0; a < 8; ++a)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) lds_add(&s_acc[k * nn + l[a]], f[a][k]);
+            }
+            __syncthreads();
+        }
+    } else {
+        if (col >= 0) {
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) lds_add(&s_acc[k * nn + l[a]], f[a][k]);
+        }
+        __syncthreads();
+    }
+
+    // device-scope stores, consecutive lanes on consecutive doubles
+    for (int u = tid; u < 3 * nn; u += T) {
+        const int t = LAYOUT == UM_AOS ? u / 3 : u % nn;
+        const int k = LAYOUT == UM_AOS ? u % 3 : u / nn;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, s_acc[k * nn + t]), rf,
+                                              foff(t, k), 0, HEX_CPOL_SC1);
+    }
+    // publish: every lane's stores complete, then one flag store
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(flags + pos, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int LAYOUT>
 __device__ __forceinline__ void gather_element(const HexDats &d, const int32_t *row,
                                                double xe[8][3], double ve[8][3]) {
@@ -272,6 +423,21 @@ hipError_t hex_launch_layout(const LaunchArgs &la, int which, int32_t begin, int
         hipLaunchKernelGGL(kern, dim3(end - begin), dim3(la.block_size), size_t(lds), la.stream,
                            la.binfo, la.stg_c, la.crun, reinterpret_cast<const uint4 *>(la.loc), d,
                            kappa, begin);
+        return hipGetLastError();
+    }
+    if (which == LAUNCH_HIER_FLOW) {
+        static bool fattr[2] = {false, false};
+        const bool atom = la.tcmode == UM_TC_LDS_ATOMIC;
+        auto kern = atom ? hex_flow_kernel<LAYOUT, UM_TC_LDS_ATOMIC>
+                         : hex_flow_kernel<LAYOUT, UM_TC_BARRIER>;
+        if (!fattr[atom]) {
+            hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            fattr[atom] = true;
+        }
+        hipLaunchKernelGGL(kern, dim3(end - begin), dim3(la.block_size), size_t(lds), la.stream,
+                           la.binfo, la.stg_c, la.crun, reinterpret_cast<const uint4 *>(la.loc), d,
+                           kappa, la.pred_off, la.preds, la.flags, la.err);
         return hipGetLastError();
     }
     const int32_t n = end - begin;

@@ -572,8 +572,9 @@ void build_host_plan_hex(const Ctx &ctx, const HexArgs &ha, int32_t iter_set,
         fail(UM_ERR_UNSUPPORTED, "hex loop: only STAGE_ALL with one element per lane");
     const int32_t nbcol = plan_blocks(ctx, iter_set, m.table.data(), 8, N, o, hp);
     const int32_t nb = int32_t(hp.blk_off.size()) - 1;
-    if (hp.schedule == UM_SCHED_DATAFLOW)
-        fail(UM_ERR_UNSUPPORTED, "hex loop: dataflow schedule not provided");
+    if (hp.schedule == UM_SCHED_DATAFLOW && 24 * N > int64_t(INT32_MAX))
+        fail(UM_ERR_UNSUPPORTED, "dataflow schedule addresses force with 32-bit byte offsets: "
+             "at most %lld nodes", (long long)(int64_t(INT32_MAX) / 24));
 
     // per block in launch order: staged nodes, layer-2 colouring, slots.
     // Local index word: 4 x uint32 per slot holding 8 x 16-bit node indices

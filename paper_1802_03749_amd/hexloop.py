@@ -105,7 +105,8 @@ class HexLoop:
 
     def plan(self, strategy: str = "hier", block_size: int = 256, max_block_colours: int = 256,
              lds_limit_bytes: int = 0, explicit_lists: bool = False,
-             block_colouring: str = "first_fit", tcmode: str = "barrier") -> Plan:
+             block_colouring: str = "first_fit", tcmode: str = "barrier",
+             schedule: str = "colour_launches") -> Plan:
         o = U.um_plan_opts()
         o.strategy = STRATEGIES[strategy]
         o.block_size = block_size
@@ -115,7 +116,7 @@ class HexLoop:
         o.lds_limit_bytes = lds_limit_bytes
         o.explicit_lists = 1 if explicit_lists else 0
         o.block_colouring = BCOLOURING[block_colouring]
-        o.schedule = SCHEDULES["colour_launches"]
+        o.schedule = SCHEDULES[schedule]
         h = U.um_plan_build(self.ctx, U.UM_K_HEX_HOURGLASS_3D, self.args(), self.s_elems, o)
         return Plan(h, strategy, block_size, U.um_plan_stats_get(h).as_dict())
 
@@ -126,8 +127,8 @@ class HexLoop:
             U.um_plan_export(plan.handle, field, out, n)
         return out
 
-    def run(self, plan: Plan, params=PARAMS) -> None:
-        U.um_loop_exec(plan.handle, params, self.stream)
+    def run(self, plan: Plan, params=PARAMS, stream: int | None = None) -> None:
+        U.um_loop_exec(plan.handle, params, self.stream if stream is None else stream)
 
     def debug_forces(self, plan: Plan, params=PARAMS) -> np.ndarray:
         f = torch.empty((self.E, 8, 3), dtype=torch.float64, device=self.dev)

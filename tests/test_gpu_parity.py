@@ -389,6 +389,43 @@ def test_hex_lds_atomic_rounds(layout):
     assert rel_l2(L.force_user(), ref) <= TOL
 
 
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+@pytest.mark.parametrize("tcmode", ["barrier", "lds_atomic"])
+def test_hex_dataflow(layout, tcmode):
+    """The hex loop's dataflow schedule: one launch, results equal to the
+    colour-launch plan to rounding, reproducible, and replayable from a HIP
+    graph (every replay adds one more loop's forces)."""
+    m, ref = hexmesh(24)
+    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=256, layout=layout)
+    p = L.plan("hier", 256, block_colouring="min", tcmode=tcmode, schedule="dataflow")
+    assert p.stats["n_launches"] == 1
+    outs = []
+    for _ in range(2):
+        L.zero_force(); L.run(p); torch.cuda.synchronize(); outs.append(L.force_user())
+    assert rel_l2(outs[0], ref) <= TOL
+    if tcmode == "barrier":
+        assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        L.run(p, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    L.zero_force(); torch.cuda.synchronize()
+    for k in range(1, 3):
+        g.replay(); torch.cuda.synchronize()
+        assert rel_l2(L.force_user(), k * ref) <= TOL, k
+    assert U.um_plan_errors(p.handle) == 0
+
+
+def test_hex_dataflow_full_size():
+    m, ref = hexmesh(128)
+    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=256)
+    p = L.plan("hier", 256, block_colouring="min", schedule="dataflow")
+    L.run(p)
+    torch.cuda.synchronize()
+    assert rel_l2(L.force_user(), ref) <= TOL
+    assert U.um_plan_errors(p.handle) == 0
+
+
 def test_hex_contract_off_forces_bit_exact():
     m, _ = hexmesh(12)
     L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm", block_size=128)
