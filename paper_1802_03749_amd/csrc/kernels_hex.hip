@@ -415,11 +415,9 @@ hipError_t hex_launch_layout(const LaunchArgs &la, int which, int32_t begin, int
         const bool atom = la.tcmode == UM_TC_LDS_ATOMIC;
         auto kern = atom ? hex_hier_kernel<LAYOUT, UM_TC_LDS_ATOMIC>
                          : hex_hier_kernel<LAYOUT, UM_TC_BARRIER>;
-        if (!attr[atom]) {
-            hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            attr[atom] = true;
-        }
+        clear_stale_error();
+        const hipError_t ea = allow_full_lds(reinterpret_cast<const void *>(kern), attr[atom]);
+        if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL(kern, dim3(end - begin), dim3(la.block_size), size_t(lds), la.stream,
                            la.binfo, la.stg_c, la.crun, reinterpret_cast<const uint4 *>(la.loc), d,
                            kappa, begin);
@@ -430,11 +428,9 @@ hipError_t hex_launch_layout(const LaunchArgs &la, int which, int32_t begin, int
         const bool atom = la.tcmode == UM_TC_LDS_ATOMIC;
         auto kern = atom ? hex_flow_kernel<LAYOUT, UM_TC_LDS_ATOMIC>
                          : hex_flow_kernel<LAYOUT, UM_TC_BARRIER>;
-        if (!fattr[atom]) {
-            hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-            fattr[atom] = true;
-        }
+        clear_stale_error();
+        const hipError_t ea = allow_full_lds(reinterpret_cast<const void *>(kern), fattr[atom]);
+        if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL(kern, dim3(end - begin), dim3(la.block_size), size_t(lds), la.stream,
                            la.binfo, la.stg_c, la.crun, reinterpret_cast<const uint4 *>(la.loc), d,
                            kappa, la.pred_off, la.preds, la.flags, la.err);
@@ -444,6 +440,7 @@ hipError_t hex_launch_layout(const LaunchArgs &la, int which, int32_t begin, int
     if (n <= 0) return hipSuccess;
     const int tb = la.block_size;
     dim3 grid((n + tb - 1) / tb), block(tb);
+    clear_stale_error();
     if (which == LAUNCH_GCOL)
         hipLaunchKernelGGL((hex_gcol_kernel<LAYOUT>), grid, block, 0, la.stream, la.emap, begin,
                            end, d, kappa);

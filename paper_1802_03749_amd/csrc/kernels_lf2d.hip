@@ -336,23 +336,40 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     const uint16_t *__restrict__ loc16 = reinterpret_cast<const uint16_t *>(loc + n_slots);
     const uint32_t wa = tid < ne ? loc[bi.slot_off + tid] : 0u;
     const uint32_t wb = tid < ne ? uint32_t(loc16[bi.slot_off + tid]) : 0u;
-    // gather the read-only data (q, adt, x) in fused passes as in
-    // hier_kernel; residuals come after the wait
+    // one early look at the predecessors' flags: if all of them have already
+    // published (the usual case, blocks are launched in colour order), the
+    // residuals are loaded together with the other gathers, one memory
+    // latency fewer on the block's critical path; the flag loads complete
+    // before the barrier, so every residual load is issued after them
+    bool mine = true;
+    if (tid < np)
+        mine = __hip_atomic_load(flags + preds[p0 + tid], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) == epoch;
+    const bool ready = __syncthreads_and(mine) != 0;
+    const __amdgpu_buffer_rsrc_t rres = res_rsrc(d.res, d.C);
+    // gather q, adt, x (and, when ready, the residuals) in fused passes as in
+    // hier_kernel
     const int npass = nc > nn ? nc : nn;
     for (int t = tid; t < npass; t += T) {
         const bool hc = t < nc, hn = t < nn;
         Real qv[4] = {Real(0), Real(0), Real(0), Real(0)}, av = Real(0);
+        double rv[4] = {0.0, 0.0, 0.0, 0.0};
         Real xa = Real(0), xb = Real(0);
         if (hc) {
             const int64_t g = cell_id(t);
             load4<LAYOUT>(d.q, d.C, g, qv);
             av = d.adt[g];
+            if (ready) load4_dev<LAYOUT>(rres, d.C, g, rv);
         }
         if (hn) load2<LAYOUT>(d.x, d.N, node_id(t), xa, xb);
         if (hc) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) s_q[k * nc + t] = qv[k];
             s_adt[t] = av;
+            if (ready) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) s_inc[k * nc + t] = rv[k];
+            }
         }
         if (hn) {
             s_x[t] = xa;
@@ -377,30 +394,30 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
                   eps, f);
     }
 
-    // wait for the earlier-coloured neighbours (np <= 64: first wavefront)
-    if (tid < np) {
-        const int32_t *fl = flags + preds[p0 + tid];
-        const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
-        while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-            if (__builtin_amdgcn_s_memrealtime() - t_begin > FLOW_WAIT_TICKS) {
-                __hip_atomic_fetch_add(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
+    if (!ready) {  // uniform over the block
+        // wait for the earlier-coloured neighbours (np <= 64: first wavefront)
+        if (tid < np) {
+            const int32_t *fl = flags + preds[p0 + tid];
+            const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
+            while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+                if (__builtin_amdgcn_s_memrealtime() - t_begin > FLOW_WAIT_TICKS) {
+                    __hip_atomic_fetch_add(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
             }
-            __builtin_amdgcn_s_sleep(2);
         }
-    }
-    __syncthreads();
-
-    // residuals as accumulators
-    const __amdgpu_buffer_rsrc_t rres = res_rsrc(d.res, d.C);
-    for (int t = tid; t < nc; t += T) {
-        double r[4];
-        load4_dev<LAYOUT>(rres, d.C, cell_id(t), r);
+        __syncthreads();
+        // residuals as accumulators
+        for (int t = tid; t < nc; t += T) {
+            double r[4];
+            load4_dev<LAYOUT>(rres, d.C, cell_id(t), r);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s_inc[k * nc + t] = r[k];
+            for (int k = 0; k < 4; ++k) s_inc[k * nc + t] = r[k];
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     if constexpr (TCMODE == UM_TC_BARRIER) {
         const int ncol = bi.ncol;
@@ -510,11 +527,10 @@ template <int LAYOUT, int ST, int TC, int EPT, typename Real>
 hipError_t launch_hier_one(const LaunchArgs &la, int32_t nblocks, int32_t base, int64_t lds,
                            const Dats<Real> &d) {
     static bool attr = false;
-    if (!attr) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(hier_kernel<LAYOUT, ST, TC, EPT, Real>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr = true;
-    }
+    clear_stale_error();
+    const hipError_t ea = allow_full_lds(
+        reinterpret_cast<const void *>(hier_kernel<LAYOUT, ST, TC, EPT, Real>), attr);
+    if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, EPT, Real>), dim3(nblocks),
                        dim3(la.block_size), size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n,
                        la.crun, la.nrun, la.loc, la.n_slots, d, la.gm1,
@@ -548,11 +564,10 @@ hipError_t launch_hier(const LaunchArgs &la, int32_t nblocks, int32_t base, int6
 template <int LAYOUT, int TC, typename Real>
 hipError_t launch_flow(const LaunchArgs &la, int32_t nblocks, int64_t lds, const Dats<Real> &d) {
     static bool attr = false;
-    if (!attr) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(hier_flow_kernel<LAYOUT, TC, Real>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr = true;
-    }
+    clear_stale_error();
+    const hipError_t ea =
+        allow_full_lds(reinterpret_cast<const void *>(hier_flow_kernel<LAYOUT, TC, Real>), attr);
+    if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL((hier_flow_kernel<LAYOUT, TC, Real>), dim3(nblocks), dim3(la.block_size),
                        size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun,
                        la.loc, la.n_slots, d, la.gm1, la.eps, la.pred_off,
@@ -577,6 +592,7 @@ hipError_t launch_typed(const LaunchArgs &la, int which, int32_t begin, int32_t 
     const int tb = la.block_size;
     dim3 grid((n + tb - 1) / tb), block(tb);
     const int4 *em = reinterpret_cast<const int4 *>(la.emap);
+    clear_stale_error();
     if (which == LAUNCH_GCOL)
         hipLaunchKernelGGL((gcol_kernel<LAYOUT, Real>), grid, block, 0, la.stream, em, begin, end,
                            d, la.gm1, la.eps);

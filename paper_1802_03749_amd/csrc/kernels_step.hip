@@ -181,6 +181,7 @@ hipError_t launch_typed(const LaunchArgs &la, int32_t kernel, int which, int32_t
     const Real *adt = static_cast<const Real *>(la.adt);
     const int64_t n = int64_t(end) - begin;
     if (n <= 0) return hipSuccess;
+    clear_stale_error();
     if (kernel == UM_K_CELL_ADT_2D && which == LAUNCH_DIRECT) {
         adt_kernel<LAYOUT, Real><<<grid_for(n, bs), bs, 0, la.stream>>>(
             x, q, const_cast<Real *>(adt), reinterpret_cast<const int4 *>(la.emap), la.N, la.C,

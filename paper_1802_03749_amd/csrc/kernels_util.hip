@@ -28,6 +28,7 @@ hipError_t gather(const void *src, void *dst, const int32_t *idx, int64_t n, int
     const int64_t total = n * dim;
     if (total == 0) return hipSuccess;
     dim3 block(256), grid(unsigned((total + 255) / 256));
+    clear_stale_error();
     if (layout == UM_AOS)
         hipLaunchKernelGGL((gather_kernel<T, UM_AOS>), grid, block, 0, stream,
                            static_cast<const T *>(src), static_cast<T *>(dst), idx, n, dim);

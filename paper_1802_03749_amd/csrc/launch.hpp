@@ -33,6 +33,21 @@ struct LaunchArgs {
     int32_t n_partials;
 };
 
+// Clears an error left in the thread's HIP state by an earlier, unrelated
+// runtime call, so that hipGetLastError() after a launch reports that
+// launch only.
+inline void clear_stale_error() { (void)hipGetLastError(); }
+
+// Raises a kernel's dynamic LDS limit to the workgroup maximum once per
+// process; returns the runtime's error if it refuses.
+inline hipError_t allow_full_lds(const void *kernel, bool &done) {
+    if (done) return hipSuccess;
+    const hipError_t e =
+        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
 // One kernel launch of the LF2D loop: HIER covers launch positions
 // [begin, end) of one block colour; GCOL covers slots [begin, end) of one
 // colour; ATOMIC and DEBUG cover elements [0, end - begin).
