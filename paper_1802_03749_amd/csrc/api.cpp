@@ -754,8 +754,15 @@ um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void
                 e1 = static_cast<hipEvent_t>(p.events[2 * p.pending_pairs + 1]);
                 UM_HIP(hipEventRecord(e0, la.stream));
             }
-            UM_HIP(p.kernel == UM_K_HEX_HOURGLASS_3D ? hex_launch_one(la, which, b, e, lds)
-                                                    : lf2d_launch_one(la, which, b, e, lds));
+            const hipError_t le = p.kernel == UM_K_HEX_HOURGLASS_3D
+                                      ? hex_launch_one(la, which, b, e, lds)
+                                      : lf2d_launch_one(la, which, b, e, lds);
+            if (le != hipSuccess)
+                fail(UM_ERR_HIP,
+                     "launch %d of kernel %d (range [%d, %d), %d lanes per workgroup, %lld bytes "
+                     "of LDS, dtype %d, layout %d, staging %d, schedule %d) failed: %s",
+                     which, p.kernel, b, e, la.block_size, (long long)lds, la.dtype, la.layout,
+                     la.staging, la.schedule, hipGetErrorString(le));
             if (p.timing) {
                 UM_HIP(hipEventRecord(e1, la.stream));
                 ++p.pending_pairs;
@@ -775,7 +782,11 @@ um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void
                     e1 = static_cast<hipEvent_t>(p.events[2 * p.pending_pairs + 1]);
                     UM_HIP(hipEventRecord(e0, la.stream));
                 }
-                UM_HIP(step_launch_one(la, p.kernel, which, b, e));
+                const hipError_t le = step_launch_one(la, p.kernel, which, b, e);
+                if (le != hipSuccess)
+                    fail(UM_ERR_HIP, "launch %d of kernel %d (range [%d, %d), %d lanes per "
+                         "workgroup, dtype %d) failed: %s", which, p.kernel, b, e, la.block_size,
+                         la.dtype, hipGetErrorString(le));
                 if (p.timing) {
                     UM_HIP(hipEventRecord(e1, la.stream));
                     ++p.pending_pairs;
@@ -845,12 +856,17 @@ um_status um_plan_autotune(um_ctx ctx, int32_t kernel, const um_arg *args, int32
                 um_plan p = nullptr;
                 const um_status st =
                     um_plan_build(ctx, kernel, args, nargs, iter_set, &candidates[i], &p);
+                if (st != UM_OK && st != UM_ERR_LDS && st != UM_ERR_COLOURS &&
+                    st != UM_ERR_UNSUPPORTED && st != UM_ERR_ARG)
+                    g_err = "candidate " + std::to_string(i) + ": " + g_err;
                 if (st == UM_ERR_LDS || st == UM_ERR_COLOURS || st == UM_ERR_UNSUPPORTED ||
                     st == UM_ERR_ARG)
                     continue;
                 check(st);
                 try {
-                    check(um_loop_exec(p, params, nparams, stream));
+                    const um_status st0 = um_loop_exec(p, params, nparams, stream);
+                    if (st0 != UM_OK) g_err = "candidate " + std::to_string(i) + ": " + g_err;
+                    check(st0);
                     UM_HIP(hipEventRecord(ev.e[0], s));
                     for (int32_t r = 0; r < reps; ++r) check(um_loop_exec(p, params, nparams, stream));
                     UM_HIP(hipEventRecord(ev.e[1], s));

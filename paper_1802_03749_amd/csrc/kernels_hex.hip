@@ -416,7 +416,7 @@ hipError_t hex_launch_layout(const LaunchArgs &la, int which, int32_t begin, int
         auto kern = atom ? hex_hier_kernel<LAYOUT, UM_TC_LDS_ATOMIC>
                          : hex_hier_kernel<LAYOUT, UM_TC_BARRIER>;
         clear_stale_error();
-        const hipError_t ea = allow_full_lds(reinterpret_cast<const void *>(kern), attr[atom]);
+        const hipError_t ea = allow_lds(reinterpret_cast<const void *>(kern), lds, attr[atom]);
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL(kern, dim3(end - begin), dim3(la.block_size), size_t(lds), la.stream,
                            la.binfo, la.stg_c, la.crun, reinterpret_cast<const uint4 *>(la.loc), d,
@@ -429,7 +429,7 @@ hipError_t hex_launch_layout(const LaunchArgs &la, int which, int32_t begin, int
         auto kern = atom ? hex_flow_kernel<LAYOUT, UM_TC_LDS_ATOMIC>
                          : hex_flow_kernel<LAYOUT, UM_TC_BARRIER>;
         clear_stale_error();
-        const hipError_t ea = allow_full_lds(reinterpret_cast<const void *>(kern), fattr[atom]);
+        const hipError_t ea = allow_lds(reinterpret_cast<const void *>(kern), lds, fattr[atom]);
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL(kern, dim3(end - begin), dim3(la.block_size), size_t(lds), la.stream,
                            la.binfo, la.stg_c, la.crun, reinterpret_cast<const uint4 *>(la.loc), d,

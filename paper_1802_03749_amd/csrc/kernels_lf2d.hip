@@ -336,47 +336,48 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     const uint16_t *__restrict__ loc16 = reinterpret_cast<const uint16_t *>(loc + n_slots);
     const uint32_t wa = tid < ne ? loc[bi.slot_off + tid] : 0u;
     const uint32_t wb = tid < ne ? uint32_t(loc16[bi.slot_off + tid]) : 0u;
-    // one early look at the predecessors' flags: if all of them have already
-    // published (the usual case, blocks are launched in colour order), the
-    // residuals are loaded together with the other gathers, one memory
-    // latency fewer on the block's critical path; the flag loads complete
-    // before the barrier, so every residual load is issued after them
+    // one early look at the predecessors' flags, issued with the gathers: if
+    // all of them have already published (the usual case, blocks are
+    // launched in colour order), the residuals are loaded right after the
+    // gather barrier and arrive while the fluxes are computed, instead of
+    // after a wait at the end of the compute; the flag loads complete before
+    // that barrier, so every residual load is issued after them
+    __shared__ int s_ready;
     bool mine = true;
     if (tid < np)
         mine = __hip_atomic_load(flags + preds[p0 + tid], __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT) == epoch;
-    const bool ready = __syncthreads_and(mine) != 0;
     const __amdgpu_buffer_rsrc_t rres = res_rsrc(d.res, d.C);
-    // gather q, adt, x (and, when ready, the residuals) in fused passes as in
-    // hier_kernel
+    // gather q, adt, x in fused passes as in hier_kernel
     const int npass = nc > nn ? nc : nn;
     for (int t = tid; t < npass; t += T) {
         const bool hc = t < nc, hn = t < nn;
         Real qv[4] = {Real(0), Real(0), Real(0), Real(0)}, av = Real(0);
-        double rv[4] = {0.0, 0.0, 0.0, 0.0};
         Real xa = Real(0), xb = Real(0);
         if (hc) {
             const int64_t g = cell_id(t);
             load4<LAYOUT>(d.q, d.C, g, qv);
             av = d.adt[g];
-            if (ready) load4_dev<LAYOUT>(rres, d.C, g, rv);
         }
         if (hn) load2<LAYOUT>(d.x, d.N, node_id(t), xa, xb);
         if (hc) {
 #pragma unroll
             for (int k = 0; k < 4; ++k) s_q[k * nc + t] = qv[k];
             s_adt[t] = av;
-            if (ready) {
-#pragma unroll
-                for (int k = 0; k < 4; ++k) s_inc[k * nc + t] = rv[k];
-            }
         }
         if (hn) {
             s_x[t] = xa;
             s_x[nn + t] = xb;
         }
     }
+    if (tid < 64) {  // np <= 64: the flags are all in the first wavefront
+        const bool all = __all(mine);
+        if (tid == 0) s_ready = all ? 1 : 0;
+    }
     __syncthreads();
+    const bool ready = s_ready != 0;
+    double r0[4] = {0.0, 0.0, 0.0, 0.0};
+    if (ready && tid < nc) load4_dev<LAYOUT>(rres, d.C, cell_id(tid), r0);
 
     const int lL = int(wa & 0x7FFu), lR = int((wa >> 11) & 0x7FFu);
     const int col = tid < ne ? int(wb >> 12) : -1;
@@ -394,8 +395,20 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
                   eps, f);
     }
 
-    if (!ready) {  // uniform over the block
-        // wait for the earlier-coloured neighbours (np <= 64: first wavefront)
+    if (ready) {  // uniform over the block
+        if (tid < nc) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_inc[k * nc + tid] = r0[k];
+        }
+        for (int t = tid + T; t < nc; t += T) {
+            double r[4];
+            load4_dev<LAYOUT>(rres, d.C, cell_id(t), r);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s_inc[k * nc + t] = r[k];
+        }
+        __syncthreads();
+    } else {
+        // wait for the earlier-coloured neighbours
         if (tid < np) {
             const int32_t *fl = flags + preds[p0 + tid];
             const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
@@ -528,8 +541,8 @@ hipError_t launch_hier_one(const LaunchArgs &la, int32_t nblocks, int32_t base, 
                            const Dats<Real> &d) {
     static bool attr = false;
     clear_stale_error();
-    const hipError_t ea = allow_full_lds(
-        reinterpret_cast<const void *>(hier_kernel<LAYOUT, ST, TC, EPT, Real>), attr);
+    const hipError_t ea = allow_lds(
+        reinterpret_cast<const void *>(hier_kernel<LAYOUT, ST, TC, EPT, Real>), lds, attr);
     if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, EPT, Real>), dim3(nblocks),
                        dim3(la.block_size), size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n,
@@ -566,7 +579,7 @@ hipError_t launch_flow(const LaunchArgs &la, int32_t nblocks, int64_t lds, const
     static bool attr = false;
     clear_stale_error();
     const hipError_t ea =
-        allow_full_lds(reinterpret_cast<const void *>(hier_flow_kernel<LAYOUT, TC, Real>), attr);
+        allow_lds(reinterpret_cast<const void *>(hier_flow_kernel<LAYOUT, TC, Real>), lds, attr);
     if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL((hier_flow_kernel<LAYOUT, TC, Real>), dim3(nblocks), dim3(la.block_size),
                        size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun,

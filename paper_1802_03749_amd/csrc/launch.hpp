@@ -38,12 +38,19 @@ struct LaunchArgs {
 // launch only.
 inline void clear_stale_error() { (void)hipGetLastError(); }
 
-// Raises a kernel's dynamic LDS limit to the workgroup maximum once per
-// process; returns the runtime's error if it refuses.
-inline hipError_t allow_full_lds(const void *kernel, bool &done) {
-    if (done) return hipSuccess;
-    const hipError_t e =
-        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+// Makes `lds` bytes of dynamic LDS launchable for `kernel`: up to 64 KiB
+// needs nothing; above, the kernel's dynamic limit is raised once per
+// process to the workgroup maximum (160 KiB on gfx950) minus the kernel's
+// static LDS.  Returns the runtime's error, or hipErrorInvalidValue if the
+// request cannot fit.
+inline hipError_t allow_lds(const void *kernel, int64_t lds, bool &done) {
+    if (lds <= 64 * 1024 || done) return hipSuccess;
+    hipFuncAttributes fa{};
+    hipError_t e = hipFuncGetAttributes(&fa, kernel);
+    if (e != hipSuccess) return e;
+    const int64_t room = int64_t(160 * 1024) - int64_t(fa.sharedSizeBytes);
+    if (lds > room) return hipErrorInvalidValue;
+    e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(room));
     if (e == hipSuccess) done = true;
     return e;
 }
