@@ -155,6 +155,8 @@ def main() -> int:
     ap.add_argument("--tcmode", default="barrier", choices=["barrier", "lds_atomic"])
     ap.add_argument("--schedule", default="dataflow", choices=["colour_launches", "dataflow"])
     ap.add_argument("--bcol", default="recolour", choices=["first_fit", "recolour"])
+    ap.add_argument("--ept", type=int, default=2, choices=[1, 2],
+                    help="edges per lane (the workgroup has block_size / ept lanes)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="host time spent timing the CPU oracle (0 = skip)")
     ap.add_argument("--no-baselines", action="store_true",
@@ -198,7 +200,8 @@ def main() -> int:
     hier = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0,
                         order="rcm+partition", block_size=S, layout=args.layout)
     reorder_s = time.perf_counter() - t
-    hopts = dict(staging=args.staging, tcmode=args.tcmode, block_colouring=args.bcol)
+    hopts = dict(staging=args.staging, tcmode=args.tcmode, block_colouring=args.bcol,
+                 elems_per_thread=args.ept)
     plan = hier.plan("hier", S, schedule=args.schedule, **hopts)
     st = plan.stats
     log(f"reorder {reorder_s:.1f}s, plan {st['build_seconds']:.2f}s: blocks={st['n_blocks']} "
@@ -238,7 +241,8 @@ def main() -> int:
             tr = json.load(f)
         if (tr.get("kernel_source_sha256") == kernel_hash() and tr.get("block_size") == S
                 and tr.get("layout") == args.layout and tr.get("staging") == args.staging
-                and tr.get("schedule") == args.schedule):
+                and tr.get("schedule") == args.schedule
+                and tr.get("elems_per_thread", 1) == args.ept):
             traffic = tr.get("bytes_per_launch")
 
     variants = {}
@@ -260,6 +264,14 @@ def main() -> int:
             "pct_hbm_peak": 100 * useful / s4 / 1e9 / measure.HBM_PEAK_GBPS,
             "launches": p4.stats["n_launches"]}
         log(f"hier ({args.schedule}, lds atomics): {s4 * 1e6:.1f} us/step")
+    # the other number of edges per lane (the paper's kernels use one)
+    o5 = dict(hopts); o5["elems_per_thread"] = 3 - args.ept
+    p5 = hier.plan("hier", S, schedule=args.schedule, **o5)
+    s5 = time_steps(torch, lambda: hier.run(p5), args.steps, args.warmup)
+    variants[f"fp64_{args.schedule}_{3 - args.ept}_edges_per_lane"] = {
+        "edges_per_s": E / s5, "ms_per_step": s5 * 1e3, "useful_gbps": useful / s5 / 1e9,
+        "launches": p5.stats["n_launches"]}
+    log(f"hier ({args.schedule}, {3 - args.ept} edge(s) per lane): {s5 * 1e6:.1f} us/step")
     # the headline plan's launches captured in one HIP graph and replayed
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
@@ -415,6 +427,7 @@ def main() -> int:
             "order": "rcm+partition+point-reorder",
             "block_size": S, "layout": args.layout, "staging": args.staging,
             "tcmode": args.tcmode, "schedule": args.schedule, "block_colouring": args.bcol,
+            "edges_per_lane": args.ept,
             "parallelism": "none (one GPU)",
         },
         "useful_gbps": useful / sec / 1e9,

@@ -116,8 +116,8 @@ typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1, UM_BCOL_MIN = 2 } um
  * A wait that exceeds a time limit sets the plan's error count instead of
  * hanging (um_plan_errors).  Each block's flag counts the executions it has
  * completed (all flags advance together), so the launch needs no host-side
- * counter and may be captured in a HIP graph and replayed.  Supported for STAGE_ALL with one element per lane;
- * a plan must not execute concurrently with itself. */
+ * counter and may be captured in a HIP graph and replayed.  Supported for STAGE_ALL with one or two
+ * elements per lane; a plan must not execute concurrently with itself. */
 typedef enum { UM_SCHED_COLOUR_LAUNCHES = 0, UM_SCHED_DATAFLOW = 1 } um_schedule;
 
 /* Elemental kernels compiled into the library (no run-time code generation).

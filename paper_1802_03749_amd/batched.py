@@ -31,6 +31,8 @@ DEFAULT_CANDIDATES = (
     dict(block_size=512, block_colouring="recolour"),
     dict(block_size=256, schedule="dataflow"),
     dict(block_size=512, schedule="dataflow", block_colouring="recolour"),
+    dict(block_size=256, schedule="dataflow", elems_per_thread=2),
+    dict(block_size=512, schedule="dataflow", block_colouring="recolour", elems_per_thread=2),
 )
 
 
@@ -76,7 +78,8 @@ class BatchedSteps:
                     ts.build_plans(flux_block_size=c["block_size"],
                                    schedule=c.get("schedule", "colour_launches"),
                                    block_colouring=c.get("block_colouring", "first_fit"),
-                                   staging=c.get("staging", "all"))
+                                   staging=c.get("staging", "all"),
+                                   elems_per_thread=c.get("elems_per_thread", 1))
                 self.steps.append(ts)
         torch.cuda.synchronize()
         # the trial runs changed nothing but res (zeroed again) and adt

@@ -303,7 +303,7 @@ constexpr uint64_t FLOW_WAIT_TICKS = 20000000ull;
 // when its flag equals that epoch.  Nothing global is counted (a device-
 // scope atomic per block on one shared counter serialises the whole launch)
 // and a captured graph can replay the launch.
-template <int LAYOUT, int TCMODE, typename Real>
+template <int LAYOUT, int TCMODE, int EPT, typename Real>
 __global__ __launch_bounds__(1024) void hier_flow_kernel(
     const BlockInfo *__restrict__ binfo, const int32_t *__restrict__ stg_c,
     const int32_t *__restrict__ stg_n, const Run *__restrict__ crun, const Run *__restrict__ nrun,
@@ -333,9 +333,15 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     const int tid = int(threadIdx.x), T = int(blockDim.x);
     const int p0 = pred_off[pos], np = pred_off[pos + 1] - p0;
 
+    // local index words of this lane's slots tid, tid + T, ...
     const uint16_t *__restrict__ loc16 = reinterpret_cast<const uint16_t *>(loc + n_slots);
-    const uint32_t wa = tid < ne ? loc[bi.slot_off + tid] : 0u;
-    const uint32_t wb = tid < ne ? uint32_t(loc16[bi.slot_off + tid]) : 0u;
+    uint32_t wa[EPT], wb[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int s = tid + j * T;
+        wa[j] = s < ne ? loc[bi.slot_off + s] : 0u;
+        wb[j] = s < ne ? uint32_t(loc16[bi.slot_off + s]) : 0u;
+    }
     // one early look at the predecessors' flags, issued with the gathers: if
     // all of them have already published (the usual case, blocks are
     // launched in colour order), the residuals are loaded right after the
@@ -348,26 +354,38 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
         mine = __hip_atomic_load(flags + preds[p0 + tid], __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT) == epoch;
     const __amdgpu_buffer_rsrc_t rres = res_rsrc(d.res, d.C);
-    // gather q, adt, x in fused passes as in hier_kernel
+    // gather q, adt, x: each iteration issues the loads of EPT passes (one
+    // staged cell and one staged node per lane and pass) before any LDS
+    // store, so a block with more staged points than lanes still waits on
+    // memory once per iteration
     const int npass = nc > nn ? nc : nn;
-    for (int t = tid; t < npass; t += T) {
-        const bool hc = t < nc, hn = t < nn;
-        Real qv[4] = {Real(0), Real(0), Real(0), Real(0)}, av = Real(0);
-        Real xa = Real(0), xb = Real(0);
-        if (hc) {
-            const int64_t g = cell_id(t);
-            load4<LAYOUT>(d.q, d.C, g, qv);
-            av = d.adt[g];
-        }
-        if (hn) load2<LAYOUT>(d.x, d.N, node_id(t), xa, xb);
-        if (hc) {
+    for (int t0 = tid; t0 < npass; t0 += EPT * T) {
+        Real qv[EPT][4], av[EPT], xa[EPT], xb[EPT];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) s_q[k * nc + t] = qv[k];
-            s_adt[t] = av;
+        for (int j = 0; j < EPT; ++j) {
+            const int t = t0 + j * T;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) qv[j][k] = Real(0);
+            av[j] = xa[j] = xb[j] = Real(0);
+            if (t < nc) {
+                const int64_t g = cell_id(t);
+                load4<LAYOUT>(d.q, d.C, g, qv[j]);
+                av[j] = d.adt[g];
+            }
+            if (t < nn) load2<LAYOUT>(d.x, d.N, node_id(t), xa[j], xb[j]);
         }
-        if (hn) {
-            s_x[t] = xa;
-            s_x[nn + t] = xb;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int t = t0 + j * T;
+            if (t < nc) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) s_q[k * nc + t] = qv[j][k];
+                s_adt[t] = av[j];
+            }
+            if (t < nn) {
+                s_x[t] = xa[j];
+                s_x[nn + t] = xb[j];
+            }
         }
     }
     if (tid < 64) {  // np <= 64: the flags are all in the first wavefront
@@ -376,31 +394,48 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     }
     __syncthreads();
     const bool ready = s_ready != 0;
-    double r0[4] = {0.0, 0.0, 0.0, 0.0};
-    if (ready && tid < nc) load4_dev<LAYOUT>(rres, d.C, cell_id(tid), r0);
-
-    const int lL = int(wa & 0x7FFu), lR = int((wa >> 11) & 0x7FFu);
-    const int col = tid < ne ? int(wb >> 12) : -1;
-    Real f[4] = {Real(0), Real(0), Real(0), Real(0)};
-    if (col >= 0) {
-        const int nA = int((wa >> 22) | ((wb & 1u) << 10));
-        const int nB = int((wb >> 1) & 0x7FFu);
-        Real qL[4], qR[4];
+    double r0[EPT][4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            qL[k] = s_q[k * nc + lL];
-            qR[k] = s_q[k * nc + lR];
+    for (int j = 0; j < EPT; ++j) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r0[j][k] = 0.0;
+        if (ready && tid + j * T < nc) load4_dev<LAYOUT>(rres, d.C, cell_id(tid + j * T), r0[j]);
+    }
+
+    // fluxes of this lane's edges into registers
+    int lL[EPT], lR[EPT], col[EPT];
+    Real f[EPT][4];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        lL[j] = int(wa[j] & 0x7FFu);
+        lR[j] = int((wa[j] >> 11) & 0x7FFu);
+        col[j] = (tid + j * T) < ne ? int(wb[j] >> 12) : -1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[j][k] = Real(0);
+        if (col[j] >= 0) {
+            const int nA = int((wa[j] >> 22) | ((wb[j] & 1u) << 10));
+            const int nB = int((wb[j] >> 1) & 0x7FFu);
+            Real qL[4], qR[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                qL[k] = s_q[k * nc + lL[j]];
+                qR[k] = s_q[k * nc + lR[j]];
+            }
+            lf2d_flux(s_x[nA], s_x[nn + nA], s_x[nB], s_x[nn + nB], qL, qR, s_adt[lL[j]],
+                      s_adt[lR[j]], gm1, eps, f[j]);
         }
-        lf2d_flux(s_x[nA], s_x[nn + nA], s_x[nB], s_x[nn + nB], qL, qR, s_adt[lL], s_adt[lR], gm1,
-                  eps, f);
     }
 
     if (ready) {  // uniform over the block
-        if (tid < nc) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) s_inc[k * nc + tid] = r0[k];
+        for (int j = 0; j < EPT; ++j) {
+            const int t = tid + j * T;
+            if (t < nc) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) s_inc[k * nc + t] = r0[j][k];
+            }
         }
-        for (int t = tid + T; t < nc; t += T) {
+        for (int t = tid + EPT * T; t < nc; t += T) {
             double r[4];
             load4_dev<LAYOUT>(rres, d.C, cell_id(t), r);
 #pragma unroll
@@ -435,21 +470,27 @@ __global__ __launch_bounds__(1024) void hier_flow_kernel(
     if constexpr (TCMODE == UM_TC_BARRIER) {
         const int ncol = bi.ncol;
         for (int c = 0; c < ncol; ++c) {
-            if (col == c) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    lds_add(&s_inc[k * nc + lL], double(f[k]));
-                    lds_add(&s_inc[k * nc + lR], -double(f[k]));
+            for (int j = 0; j < EPT; ++j) {
+                if (col[j] == c) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        lds_add(&s_inc[k * nc + lL[j]], double(f[j][k]));
+                        lds_add(&s_inc[k * nc + lR[j]], -double(f[j][k]));
+                    }
                 }
             }
             __syncthreads();
         }
     } else {
-        if (col >= 0) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                lds_add(&s_inc[k * nc + lL], double(f[k]));
-                lds_add(&s_inc[k * nc + lR], -double(f[k]));
+        for (int j = 0; j < EPT; ++j) {
+            if (col[j] >= 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    lds_add(&s_inc[k * nc + lL[j]], double(f[j][k]));
+                    lds_add(&s_inc[k * nc + lR[j]], -double(f[j][k]));
+                }
             }
         }
         __syncthreads();
@@ -574,18 +615,26 @@ hipError_t launch_hier(const LaunchArgs &la, int32_t nblocks, int32_t base, int6
     return hipErrorInvalidValue;
 }
 
-template <int LAYOUT, int TC, typename Real>
-hipError_t launch_flow(const LaunchArgs &la, int32_t nblocks, int64_t lds, const Dats<Real> &d) {
+template <int LAYOUT, int TC, int EPT, typename Real>
+hipError_t launch_flow_one(const LaunchArgs &la, int32_t nblocks, int64_t lds,
+                           const Dats<Real> &d) {
     static bool attr = false;
     clear_stale_error();
-    const hipError_t ea =
-        allow_lds(reinterpret_cast<const void *>(hier_flow_kernel<LAYOUT, TC, Real>), lds, attr);
+    const hipError_t ea = allow_lds(
+        reinterpret_cast<const void *>(hier_flow_kernel<LAYOUT, TC, EPT, Real>), lds, attr);
     if (ea != hipSuccess) return ea;
-    hipLaunchKernelGGL((hier_flow_kernel<LAYOUT, TC, Real>), dim3(nblocks), dim3(la.block_size),
-                       size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun,
-                       la.loc, la.n_slots, d, la.gm1, la.eps, la.pred_off,
+    hipLaunchKernelGGL((hier_flow_kernel<LAYOUT, TC, EPT, Real>), dim3(nblocks),
+                       dim3(la.block_size), size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n,
+                       la.crun, la.nrun, la.loc, la.n_slots, d, la.gm1, la.eps, la.pred_off,
                        la.preds, la.flags, la.err);
     return hipGetLastError();
+}
+
+template <int LAYOUT, int TC, typename Real>
+hipError_t launch_flow(const LaunchArgs &la, int32_t nblocks, int64_t lds, const Dats<Real> &d) {
+    if (la.ept == 1) return launch_flow_one<LAYOUT, TC, 1>(la, nblocks, lds, d);
+    if (la.ept == 2) return launch_flow_one<LAYOUT, TC, 2>(la, nblocks, lds, d);
+    return hipErrorInvalidValue;
 }
 
 template <int LAYOUT, typename Real>
@@ -594,7 +643,7 @@ hipError_t launch_typed(const LaunchArgs &la, int which, int32_t begin, int32_t 
                        static_cast<const Real *>(la.adt), la.res, la.N, la.C};
     if (which == LAUNCH_HIER) return launch_hier<LAYOUT>(la, end - begin, begin, lds, d);
     if (which == LAUNCH_HIER_FLOW) {
-        if (la.staging != UM_STAGE_ALL || la.ept != 1 || end - begin <= 0)
+        if (la.staging != UM_STAGE_ALL || (la.ept != 1 && la.ept != 2) || end - begin <= 0)
             return hipErrorInvalidValue;
         return la.tcmode == UM_TC_BARRIER
                    ? launch_flow<LAYOUT, UM_TC_BARRIER>(la, end - begin, lds, d)

@@ -513,8 +513,8 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
                  (long long)need_all, (long long)limit);
         hp.staging = UM_STAGE_INC_ONLY;
     }
-    if (hp.schedule == UM_SCHED_DATAFLOW && (hp.staging != UM_STAGE_ALL || hp.ept != 1))
-        fail(UM_ERR_UNSUPPORTED, "dataflow schedule needs STAGE_ALL staging and one element per lane");
+    if (hp.schedule == UM_SCHED_DATAFLOW && hp.staging != UM_STAGE_ALL)
+        fail(UM_ERR_UNSUPPORTED, "dataflow schedule needs STAGE_ALL staging");
     if (hp.schedule == UM_SCHED_DATAFLOW && 32 * C > int64_t(INT32_MAX))
         fail(UM_ERR_UNSUPPORTED, "dataflow schedule addresses res with 32-bit byte offsets: "
              "at most %lld cells", (long long)(int64_t(INT32_MAX) / 32));

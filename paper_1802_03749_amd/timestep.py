@@ -151,7 +151,7 @@ class TimeStep2D:
         o.tcmode = TCMODES[kw.get("tcmode", "barrier")]
         o.max_block_colours = kw.get("max_block_colours", 256)
         o.allow_fallback = 1
-        o.elems_per_thread = 1
+        o.elems_per_thread = kw.get("elems_per_thread", 1)
         o.block_colouring = BCOLOURING[kw.get("block_colouring", "first_fit")]
         o.schedule = SCHEDULES[kw.get("schedule", "colour_launches")]
         return o
@@ -168,7 +168,8 @@ class TimeStep2D:
     def build_plans(self, *, flux_strategy: str = "hier", flux_block_size: int = 512,
                     staging: str = "all", tcmode: str = "barrier",
                     block_colouring: str = "first_fit", schedule: str = "colour_launches",
-                    bres_strategy: str = "global", cell_block_size: int = 256) -> dict:
+                    bres_strategy: str = "global", cell_block_size: int = 256,
+                    elems_per_thread: int = 1) -> dict:
         a = U.um_arg
         self._build("adt", U.UM_K_CELL_ADT_2D,
                     [a(self.d_x, self.m_c2n, U.UM_ALL_SLOTS, U.UM_READ),
@@ -176,7 +177,8 @@ class TimeStep2D:
                     self.s_cells, self._opts("atomic", cell_block_size), "direct")
         self._build("flux", U.UM_K_EDGE_FLUX_LF2D, self.flux_args(), self.s_edges,
                     self._opts(flux_strategy, flux_block_size, staging=staging, tcmode=tcmode,
-                               block_colouring=block_colouring, schedule=schedule),
+                               block_colouring=block_colouring, schedule=schedule,
+                               elems_per_thread=elems_per_thread),
                     flux_strategy)
         self._build("bres", U.UM_K_BOUNDARY_FLUX_2D,
                     [a(self.d_x, self.m_b2n, 0, U.UM_READ), a(self.d_x, self.m_b2n, 1, U.UM_READ),

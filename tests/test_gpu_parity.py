@@ -142,22 +142,50 @@ def test_dataflow_schedule_parity(layout, tcmode):
         assert np.array_equal(outs[0].view(np.uint64), outs[2].view(np.uint64))
 
 
+@pytest.mark.parametrize("tcmode", ["barrier", "lds_atomic"])
+@pytest.mark.parametrize("S", [128, 512])
+def test_dataflow_two_edges_per_lane(S, tcmode):
+    """Two edges per lane under the dataflow schedule (gather passes issued
+    in pairs; a block with more staged cells than lanes needs the loop past
+    the prefetched residuals): the oracle's result, and bitwise equal to
+    one edge per lane to rounding (same per-cell order of additions; the
+    compiler may contract multiply-adds differently per instantiation)."""
+    m, ref = mesh(200, 100)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
+                     block_size=S)
+    p2 = L.plan("hier", S, tcmode=tcmode, schedule="dataflow", elems_per_thread=2)
+    p1 = L.plan("hier", S, tcmode=tcmode, schedule="dataflow")
+    outs = []
+    for p in (p2, p1):
+        L.zero_res()
+        for _ in range(2):
+            L.run(p)
+        torch.cuda.synchronize()
+        outs.append(L.res_user())
+    assert U.um_plan_errors(p2.handle) == 0
+    assert rel_l2(outs[0], 2 * ref) <= TOL
+    assert rel_l2(outs[0], outs[1]) <= 1e-14
+
+
 def test_dataflow_schedule_full_size():
     m, ref = mesh(2400, 1200)
     L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
                      block_size=512)
     pf = L.plan("hier", 512, schedule="dataflow", block_colouring="recolour")
     pc = L.plan("hier", 512, block_colouring="recolour")
+    p2 = L.plan("hier", 512, schedule="dataflow", block_colouring="recolour",
+                elems_per_thread=2)
     res = []
-    for p in (pc, pf):
+    for p in (pc, pf, p2):
         L.zero_res()
         for _ in range(5):
             L.run(p)
         torch.cuda.synchronize()
         res.append(L.res_user())
-    assert U.um_plan_errors(pf.handle) == 0
+    assert U.um_plan_errors(pf.handle) == 0 and U.um_plan_errors(p2.handle) == 0
     assert rel_l2(res[0], res[1]) <= 1e-14
     assert rel_l2(res[1], 5 * ref) <= TOL
+    assert rel_l2(res[1], res[2]) <= 1e-14
 
 
 def test_lds_fallback_runs():
