@@ -22,6 +22,7 @@ struct Set {
     std::vector<int32_t> new2orig;   // cumulative renumbering
     int32_t part_block_size = 0;     // blocks from the last PARTITION reorder
     std::vector<int32_t> part_off;   // [n_blocks + 1]
+    std::vector<int32_t> part_code;  // [n_blocks] bisection parity code (empty if none)
 };
 
 struct Map {
@@ -61,9 +62,14 @@ std::vector<int32_t> lexicographic_elements(const Map &m);
 std::vector<int32_t> first_touch(const Map &m, int64_t n_points);
 // Partition the from-set of `drv` into blocks of <= block_size elements;
 // returns the element order (block by block) and fills block offsets.
+// Recursive coordinate bisection into blocks of at most block_size
+// elements; block_off gets the block offsets and block_code, per block, the
+// side (0 or 1) of the last cut along each axis as bit `axis` (the parity of
+// the block's index along that axis when the blocks form a regular grid).
 std::vector<int32_t> partition_elements(const Ctx &ctx, int32_t drv, int32_t block_size,
                                         int32_t coord_map, int32_t coord_dim,
-                                        const double *coords, std::vector<int32_t> &block_off);
+                                        const double *coords, std::vector<int32_t> &block_off,
+                                        std::vector<int32_t> &block_code);
 // Points of to-set `set` sorted by (number of accessing blocks, list of
 // accessing blocks), stable; elements of `from` are in block order.
 std::vector<int32_t> signature_order(const Ctx &ctx, int32_t from, int32_t set,

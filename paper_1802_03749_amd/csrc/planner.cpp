@@ -201,8 +201,10 @@ int32_t plan_blocks(const Ctx &ctx, int32_t iter_set, const int32_t *wt, int ari
     // order keeps consecutive blocks adjacent in space); else chunks
     const Set &is = ctx.sets[iter_set];
     const int32_t pbs = is.part_block_size;
+    bool partition_blocks = false;  // plan blocks are the partition's own blocks
     if (pbs > 0 && !is.part_off.empty() && o.block_size % pbs == 0) {
         const int32_t k = o.block_size / pbs;
+        partition_blocks = k == 1;
         const int32_t npb = int32_t(is.part_off.size()) - 1;
         hp.blk_off.clear();
         for (int32_t b = 0; b < npb; b += k) hp.blk_off.push_back(is.part_off[b]);
@@ -301,7 +303,40 @@ int32_t plan_blocks(const Ctx &ctx, int32_t iter_set, const int32_t *wt, int ari
                 hp.blk_colour = ds;
                 nbcol = nds;
             }
-            std::vector<int32_t> cur = nds > 0 ? ds : hp.blk_colour;
+            // the bisection's parity code (2^dim colours when the blocks form
+            // a regular grid: neighbours differ by one along some axis), its
+            // conflicts repaired first-fit in block order
+            bool code_won = false;
+            if (partition_blocks && is.part_code.size() == size_t(nb)) {
+                std::vector<int32_t> pc(is.part_code);
+                int32_t npc = 0;
+                std::fill(stamp.begin(), stamp.end(), -1);
+                for (int32_t b = 0; b < nb; ++b) {
+                    bool clash = false;
+                    for (int64_t i = adj_off[b]; i < adj_off[b + 1]; ++i)
+                        if (adj[i] < b && pc[adj[i]] == pc[b]) clash = true;
+                    if (clash) {
+                        // every neighbour's colour (repaired or still the code)
+                        for (int64_t i = adj_off[b]; i < adj_off[b + 1]; ++i)
+                            if (pc[adj[i]] < maxcol) stamp[pc[adj[i]]] = b;
+                        int32_t c = 0;
+                        while (c < maxcol && stamp[c] == b) ++c;
+                        if (c >= maxcol) {
+                            npc = maxcol + 1;
+                            break;
+                        }
+                        pc[b] = c;
+                    }
+                    npc = std::max(npc, pc[b] + 1);
+                }
+                std::fill(stamp.begin(), stamp.end(), -1);
+                if (npc < nbcol) {
+                    hp.blk_colour = pc;
+                    nbcol = npc;
+                    code_won = true;
+                }
+            }
+            std::vector<int32_t> cur = code_won || nds <= 0 ? hp.blk_colour : ds;
             while (nbcol > 1 &&
                    tabu_colouring(adj_off, adj, nbcol - 1, 100 * int64_t(nb) + 100000, cur)) {
                 hp.blk_colour = cur;

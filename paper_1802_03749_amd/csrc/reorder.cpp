@@ -198,6 +198,7 @@ void apply_set_perm(Ctx &ctx, int32_t set, const std::vector<int32_t> &perm) {
     s.new2orig.swap(n2o);
     s.part_block_size = 0;
     s.part_off.clear();
+    s.part_code.clear();
 }
 
 // ------------------------------------------------------------ partitioning
@@ -209,15 +210,21 @@ struct Bisector {
     int32_t max_block;
     std::vector<int32_t> out;          // element order, block by block
     std::vector<int32_t> off;          // block offsets
+    std::vector<int32_t> code;         // per block: last cut side along each axis
 
-    void run(int32_t *first, int64_t n, int64_t nb) {
+    void run(int32_t *first, int64_t n, int64_t nb, int32_t sides) {
         if (nb <= 1 || n <= max_block) {
             // one block (nb >= 1 and n <= nb*max_block guarantee n <= max_block)
             std::sort(first, first + n);
             out.insert(out.end(), first, first + n);
             off.push_back(int32_t(out.size()));
+            code.push_back(sides);
             return;
         }
+        // cut across the longest extent; extents within 5 % of each other
+        // count as equal and the lowest axis wins, so that equal subtrees of
+        // a perturbed structured mesh are cut alike and their blocks stay on
+        // a regular grid
         const std::vector<double> &c = *coord;
         int axis = 0;
         double best = -1.0;
@@ -228,7 +235,7 @@ struct Bisector {
                 lo = std::min(lo, v);
                 hi = std::max(hi, v);
             }
-            if (hi - lo > best) {
+            if (hi - lo > 1.05 * best) {
                 best = hi - lo;
                 axis = a;
             }
@@ -239,8 +246,8 @@ struct Bisector {
             double vx = c[int64_t(x) * dim + axis], vy = c[int64_t(y) * dim + axis];
             return vx != vy ? vx < vy : x < y;
         });
-        run(first, n1, nl);
-        run(first + n1, n - n1, nb - nl);
+        run(first, n1, nl, sides & ~(1 << axis));
+        run(first + n1, n - n1, nb - nl, sides | (1 << axis));
     }
 };
 
@@ -298,10 +305,12 @@ std::vector<double> landmark_coords(const Map &m, int64_t n) {
 
 std::vector<int32_t> partition_elements(const Ctx &ctx, int32_t drv, int32_t block_size,
                                         int32_t coord_map, int32_t coord_dim,
-                                        const double *coords, std::vector<int32_t> &block_off) {
+                                        const double *coords, std::vector<int32_t> &block_off,
+                                        std::vector<int32_t> &block_code) {
     const Map &m = ctx.maps[drv];
     const int64_t ne = ctx.sets[m.from].size;
     block_off.assign(1, 0);
+    block_code.clear();
     if (ne == 0) return {};
     // element coordinates: mean of their points' coordinates
     std::vector<double> pc;
@@ -324,11 +333,12 @@ std::vector<int32_t> partition_elements(const Ctx &ctx, int32_t drv, int32_t blo
     for (double &v : ec) v /= k;
     std::vector<int32_t> ids(ne);
     std::iota(ids.begin(), ids.end(), 0);
-    Bisector b{&ec, dim, block_size, {}, {0}};
+    Bisector b{&ec, dim, block_size, {}, {0}, {}};
     b.out.reserve(ne);
     int64_t nb = (ne + block_size - 1) / block_size;
-    b.run(ids.data(), ne, nb);
+    b.run(ids.data(), ne, nb, 0);
     block_off.swap(b.off);
+    block_code.swap(b.code);
     return b.out;
 }
 
@@ -400,7 +410,7 @@ void reorder_mesh(Ctx &ctx, const um_reorder_opts &o) {
         fail(UM_ERR_ARG, "reorder: unknown mode %d", o.mode);
     if (o.block_size < 1 || o.block_size > 1024)
         fail(UM_ERR_ARG, "reorder: block_size %d outside 1..1024", o.block_size);
-    std::vector<int32_t> off;
+    std::vector<int32_t> off, code;
     std::vector<int32_t> perm;
     if (o.mode == UM_REORDER_USER_BLOCKS) {
         if (!o.block_of) fail(UM_ERR_ARG, "reorder: USER_BLOCKS needs block_of");
@@ -432,10 +442,11 @@ void reorder_mesh(Ctx &ctx, const um_reorder_opts &o) {
     }
     if (o.mode == UM_REORDER_PARTITION)
         perm = partition_elements(ctx, o.driving_map, o.block_size, o.coord_map, o.coord_dim,
-                                  o.coords, off);
+                                  o.coords, off, code);
     apply_set_perm(ctx, F, perm);
     ctx.sets[F].part_block_size = o.block_size;
     ctx.sets[F].part_off = off;
+    ctx.sets[F].part_code = code;
     if (o.point_reorder) {
         std::vector<int32_t> blk(ctx.sets[F].size);
         for (size_t b = 0; b + 1 < off.size(); ++b)

@@ -387,6 +387,37 @@ def test_hex_args_checked():
     assert ei.value.status == U.UM_ERR_ARITY
 
 
+@pytest.mark.parametrize("n,S,edge", [(16, 64, 4), (16, 128, None), (12, 216, 6)])
+def test_hex_bisection_gives_lattice_and_eight_colours(n, S, edge):
+    """On a perturbed structured hex mesh, recursive bisection cuts equal
+    subtrees alike, so the blocks are congruent bricks on a regular grid
+    (every block stages the same number of nodes), and MIN block colouring
+    reaches 8 colours, the clique bound of a 3D brick grid (the 8 bricks
+    around a grid vertex are pairwise adjacent)."""
+    m = hex_mesh(n, seed=3)
+    L = HexLoop(m.x, m.v, m.e2n, device=-1, order="rcm+partition", block_size=S)
+    p = L.plan("hier", S, block_colouring="min")
+    off = L.export(p, U.UM_EXP_BLOCK_OFFSETS)
+    e2n = L.current_map()
+    bcol = L.export(p, U.UM_EXP_BLOCK_COLOURS)
+    assert P.check_block_colouring(off, bcol, e2n)
+    staged = [len(r) for r in P.staged_points(off, e2n)]
+    assert len(set(staged)) == 1
+    if edge is not None:
+        assert staged[0] == (edge + 1) ** 3
+    assert p.stats["n_block_colours"] == 8
+
+
+def test_quad_bisection_gives_four_colours():
+    """2D analogue: 8 x 8 tiles of a perturbed 64 x 64 quad mesh, 4 colours
+    (the 4 tiles around a grid vertex are pairwise adjacent)."""
+    m, L = make(nx=64, ny=64, order="rcm+partition", block_size=64)
+    p = L.plan("hier", 64, block_colouring="min")
+    off = L.export(p, U.UM_EXP_BLOCK_OFFSETS)
+    assert P.check_block_colouring(off, L.export(p, U.UM_EXP_BLOCK_COLOURS), L.current_map("e2c"))
+    assert p.stats["n_block_colours"] == 4
+
+
 @pytest.mark.parametrize("S,k", [(256, 2), (256, 4), (128, 3)])
 def test_hier_plan_merges_partition_blocks_for_multiples(S, k):
     """A plan for k * S on a mesh partitioned for S uses groups of k
