@@ -329,14 +329,15 @@ def main() -> int:
         hm = hex_mesh(128, seed=1)
         hb = 96 * hm.n_nodes + 32 * hm.n_elems   # x, v once, force twice, int32 map
         hx = {"elements": hm.n_elems, "nodes": hm.n_nodes, "useful_bytes_per_step": hb}
-        for order, strat, hS in (("rcm+partition", "hier", 256), ("rcm", "global", 256),
+        for order, strat, hS in (("rcm+partition", "hier", 512), ("rcm", "global", 256),
                                  ("rcm", "atomic", 256)):
             H = HexLoop(hm.x, hm.v, hm.e2n, device=0, order=order, block_size=hS,
                         layout=args.layout)
             p = H.plan(strat, hS, block_colouring="min" if strat == "hier" else "first_fit")
             s = time_steps(torch, lambda: H.run(p), max(args.steps // 2, 1), args.warmup)
-            hx[strat] = {"order": order, "elements_per_s": hm.n_elems / s, "ms_per_step": s * 1e3,
-                         "useful_gbps": hb / s / 1e9, "launches": p.stats["n_launches"]}
+            hx[strat] = {"order": order, "block_size": hS, "elements_per_s": hm.n_elems / s,
+                         "ms_per_step": s * 1e3, "useful_gbps": hb / s / 1e9,
+                         "launches": p.stats["n_launches"]}
             log(f"hex {strat}: {s * 1e6:.1f} us/step ({hb / s / 1e9:.0f} GB/s)")
             if strat == "hier":
                 p2 = H.plan(strat, hS, block_colouring="min", tcmode="lds_atomic")
