@@ -164,8 +164,22 @@ __global__ __launch_bounds__(1024) void update_kernel(Real *__restrict__ q,
 
 __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__ partials,
                                                       int32_t n, double *__restrict__ gbl) {
+    // lane t adds partials t, t + T, t + 2T, ... in that order; the loads of
+    // eight terms are issued before their additions (a zero past the end
+    // leaves the non-negative sum unchanged)
+    constexpr int U = 8;
+    const int32_t T = int32_t(blockDim.x);
     double acc = 0.0;
-    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) acc += partials[i];
+    for (int32_t i0 = threadIdx.x; i0 < n; i0 += U * T) {
+        double v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int32_t i = i0 + j * T;
+            v[j] = i < n ? partials[i] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) acc += v[j];
+    }
     const double t = block_sum(acc);
     if (threadIdx.x == 0) gbl[0] += t;
 }
