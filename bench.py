@@ -348,6 +348,26 @@ def main() -> int:
                 log(f"hex hier lds atomics: {s2 * 1e6:.1f} us/step")
             H.close()
         extras["hex_hourglass_128cubed"] = hx
+        # one full explicit time step on the benchmark mesh: cell adt, edge
+        # flux (the headline plan's options), far-field boundary flux, update
+        # with the sum of squares
+        from paper_1802_03749_amd.timestep import TimeStep2D
+        qinf = np.array([1.0, 0.35, 0.05, 2.7])
+        tsx = {}
+        for dt, rb in (("f64", 8), ("f32", 4)):
+            ts = TimeStep2D(mesh.x, mesh.q, mesh.e2n, mesh.e2c, mesh.b2n, mesh.b2c, mesh.c2n,
+                            qinf, device=0, block_size=S, layout=args.layout, dtype=dt)
+            ts.build_plans(flux_block_size=S, staging=args.staging, tcmode=args.tcmode,
+                           block_colouring=args.bcol, schedule=args.schedule,
+                           elems_per_thread=args.ept)
+            s = time_steps(torch, ts.step, max(args.steps // 4, 1), args.warmup)
+            sb = measure.step_useful_bytes(N, C, E, ts.B, rb)
+            tsx[dt] = {"ms_per_step": s * 1e3, "cells_per_s": C / s, "useful_bytes_per_step": sb,
+                       "useful_gbps": sb / s / 1e9,
+                       "launches": sum(p.stats["n_launches"] for p in ts.plans.values())}
+            log(f"time step {dt}: {s * 1e6:.1f} us/step ({sb / s / 1e9:.0f} GB/s useful)")
+            ts.close()
+        extras["time_step_2400x1200"] = tsx
 
     if not args.no_extras and not args.no_batched:
         # 64 meshes of log-uniform size 5k-500k cells, one full time step

@@ -27,6 +27,22 @@ def useful_bytes(n_nodes: int, n_cells: int, n_edges: int, real_bytes: int = 8,
     return x + q + adt + res + maps
 
 
+def step_useful_bytes(n_nodes: int, n_cells: int, n_edges: int, n_bedges: int,
+                      real_bytes: int = 8) -> int:
+    """Algorithmic bytes of one explicit time step of the 2D solver, counted
+    the same way per loop: cell time-step scalar (x once, the cell->node map,
+    q read, adt written), the edge flux (useful_bytes), the far-field
+    boundary flux (q, adt, both nodes' x, res read and written, the edge's
+    three map entries) and the update (q and res read and written, adt
+    read).  res and the sum of squares are FP64 whatever the storage type."""
+    rb = real_bytes
+    adt = 2 * rb * n_nodes + (16 + 4 * rb + rb) * n_cells
+    flux = useful_bytes(n_nodes, n_cells, n_edges, real_bytes=rb)
+    bres = (4 * rb + rb + 2 * 2 * rb + 2 * 4 * 8 + 12) * n_bedges
+    upd = (2 * 4 * rb + 2 * 4 * 8 + rb) * n_cells
+    return adt + flux + bres + upd
+
+
 def quad_counts(nx: int, ny: int):
     """(cells, nodes, interior edges) of an nx x ny quad mesh."""
     return nx * ny, (nx + 1) * (ny + 1), 2 * nx * ny - nx - ny

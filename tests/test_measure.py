@@ -64,3 +64,20 @@ def test_bytes_per_edge():
 def test_roofline_fraction():
     a, f = measure.roofline(8e12 * 1e-6, 1e-6)   # 8 MB in one microsecond
     assert a == pytest.approx(8000.0) and f == pytest.approx(1.0)
+
+
+def test_step_bytes_by_dataset():
+    """One time step counts every loop's datasets once (res twice where it
+    is read and written): on a 2 x 1 mesh, counted by hand per loop."""
+    C, N, E, B = 2, 6, 1, 6
+    adt = 6 * 2 * 8 + 2 * (16 + 32 + 8)           # x; c2n, q, adt per cell
+    flux = 6 * 16 + 2 * 104 + 1 * 16              # the edge-flux formula
+    bres = 6 * (32 + 8 + 32 + 64 + 12)            # q, adt, two nodes' x, res r+w, maps
+    upd = 2 * (64 + 64 + 8)                       # q r+w, res r+w, adt
+    assert measure.step_useful_bytes(N, C, E, B) == adt + flux + bres + upd
+    # binary32 storage: x, q, adt halve, res and the maps do not
+    adt32 = 6 * 2 * 4 + 2 * (16 + 16 + 4)
+    flux32 = measure.useful_bytes(N, C, E, real_bytes=4)
+    bres32 = 6 * (16 + 4 + 16 + 64 + 12)
+    upd32 = 2 * (32 + 64 + 4)
+    assert measure.step_useful_bytes(N, C, E, B, 4) == adt32 + flux32 + bres32 + upd32
