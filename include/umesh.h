@@ -97,7 +97,10 @@ typedef enum { UM_TC_BARRIER = 0, UM_TC_LDS_ATOMIC = 1 } um_tcmode;
  * neighbours holds when that class is smaller by two or more); fewer and
  * more even launches.
  * MIN: as RECOLOUR, but before the balancing pass also a DSatur colouring
- * (Brelaz) and then a tabu search (Hertz and de Werra's TabuCol,
+ * (Brelaz) and, when the plan's blocks are those of the last PARTITION
+ * reorder, the bisection's parity code (per axis, the side of the block's
+ * last cut along it: 2^dim colours on a regular grid of blocks; clashes
+ * recoloured first-fit), then a tabu search (Hertz and de Werra's TabuCol,
  * deterministic, bounded to 100 moves per block) for one colour fewer at a
  * time; the plan keeps the fewest colours found.  Slower to build. */
 typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1, UM_BCOL_MIN = 2 } um_bcolouring;
@@ -374,10 +377,12 @@ um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr);
  *     first-touch order over the sorted elements.
  *   PARTITION: the from-set of driving_map is split into contiguous blocks
  *     of at most block_size elements that share as little data as possible
- *     (recursive bisection along the longest extent of element coordinates:
- *     the mean of the element's points' `coords` through coord_map, or, if
- *     no coordinates are given, graph-distance coordinates from BFS
- *     landmarks on the driving map's point graph); every split keeps each
+ *     (recursive bisection along the longest extent of element coordinates,
+ *     extents within 5 % of each other counting as equal with the lowest
+ *     axis first: the mean of the element's points' `coords` through
+ *     coord_map, or, if no coordinates are given, graph-distance
+ *     coordinates from BFS landmarks on the driving map's point graph);
+ *     every split keeps each
  *     side at most (its share of blocks) * block_size elements, so all
  *     blocks end up at most block_size.  Elements are renumbered block by
  *     block, keeping their previous relative order inside a block.  With point_reorder, every to-set of a map from the from-set

@@ -10,6 +10,10 @@
 //                colour, and the accumulators are stored back once.  Blocks
 //                of one block colour write disjoint cells, so a launch per
 //                block colour needs no atomics.
+//  hier_flow_kernel  the same per-block work as one launch over all blocks
+//                in colour order (dataflow schedule): a block's residual
+//                read-modify-write waits for its earlier-coloured neighbours'
+//                completion flags instead of a kernel boundary.
 //  gcol_kernel   global colouring baseline (Section 2.1): one launch per
 //                colour, gather through the int32 maps, plain read-modify-
 //                write of res.
@@ -138,8 +142,8 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
 
     // gather: per pass every lane fetches at most one staged cell and one
     // staged node, issuing all their loads before any LDS store (one memory
-    // wait per pass; a block of S edges has fewer than S staged cells and
-    // nodes, so with one edge per lane a single pass covers it)
+    // wait per pass; a block of S edges usually has fewer than S staged
+    // cells and nodes, so with one edge per lane a single pass covers it)
     const int npass = STAGING == UM_STAGE_ALL ? (nc > nn ? nc : nn) : nc;
     for (int t = tid; t < npass; t += T) {
         const bool hc = t < nc;
@@ -285,9 +289,12 @@ __device__ __forceinline__ void store4_dev(__amdgpu_buffer_rsrc_t r, int64_t C, 
 constexpr uint64_t FLOW_WAIT_TICKS = 20000000ull;
 
 // DATAFLOW schedule: one launch over all blocks in colour order (position =
-// blockIdx.x).  Same per-block work as hier_kernel with STAGE_ALL and one
-// edge per lane, except that the residuals are loaded only after every
-// neighbouring block of an earlier colour has published its write-back.
+// blockIdx.x).  Same per-block work as hier_kernel with STAGE_ALL and EPT
+// edges per lane, except that the residuals are loaded only after every
+// neighbouring block of an earlier colour has published its write-back (a
+// first look at the flags goes out with the gathers; when all have already
+// published, the residual loads overlap the flux evaluation, otherwise the
+// block polls after it).
 // Publication: all lanes finish their device-scope residual stores
 // (s_waitcnt), the workgroup meets at a barrier, then one lane stores the
 // execution's epoch into the block's flag (device-scope atomic store).
