@@ -266,7 +266,7 @@ typedef struct {
                                   ceil(block_size / elems_per_thread) lanes
                                   rounded up to a multiple of 64             */
     int32_t explicit_lists;    /* HIER: 0 = a block whose staged points form
-                                  at most 32 runs of consecutive ids finds
+                                  at most 8 runs of consecutive ids finds
                                   them from the runs (no index loads); 1 =
                                   every block reads its explicit id list     */
     int32_t block_colouring;   /* HIER: um_bcolouring                        */

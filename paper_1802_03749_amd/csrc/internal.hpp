@@ -124,7 +124,7 @@ struct Run {
 
 // Blocks whose staged list splits into more runs than this read the
 // explicit list.
-constexpr int32_t MAX_RUNS = 32;
+constexpr int32_t MAX_RUNS = 8;
 
 struct HostPlan {
     int32_t strategy = 0, staging = 0, tcmode = 0, block_size = 0;
