@@ -107,7 +107,7 @@ def run_ablations(torch, mesh, S, args, useful, E):
                 "reuse_factor": st["reuse_factor"]}
 
     base = dict(staging=args.staging, tcmode=args.tcmode, block_colouring=args.bcol,
-                schedule=args.schedule)
+                schedule=args.schedule, elems_per_thread=args.ept)
     tx = 16
     ty = max(S // (2 * tx), 1)
     parts = (("chunks_of_rcm", "rcm", {}),
@@ -121,7 +121,8 @@ def run_ablations(torch, mesh, S, args, useful, E):
             if name == "recursive_bisection" and layout == args.layout:
                 for knob, val in (("staging", "inc"), ("tcmode", "lds_atomic"),
                                   ("block_colouring", "first_fit"), ("block_colouring", "recolour"),
-                                  ("schedule", "colour_launches"), ("schedule", "dataflow")):
+                                  ("schedule", "colour_launches"), ("schedule", "dataflow"),
+                                  ("elems_per_thread", 1), ("elems_per_thread", 2)):
                     if base[knob] == val:
                         continue
                     o = dict(base); o[knob] = val
