@@ -331,12 +331,49 @@ std::vector<int32_t> partition_elements(const Ctx &ctx, int32_t drv, int32_t blo
             for (int a = 0; a < dim; ++a) ec[e * dim + a] += pc[int64_t(p) * dim + a];
         }
     for (double &v : ec) v /= k;
+    // connected components of the elements (elements sharing a point of the
+    // driving map): each is bisected on its own into ceil(n_c / block_size)
+    // blocks, so no block mixes components (a count-based cut through a
+    // union of separate meshes would otherwise leave slivers and blocks
+    // straddling two meshes, whose staged sets are several times larger)
+    const int64_t np = ctx.sets[m.to].size;
+    std::vector<int32_t> parent(np);
+    std::iota(parent.begin(), parent.end(), 0);
+    auto find = [&](int32_t x) {
+        while (parent[x] != x) {
+            parent[x] = parent[parent[x]];
+            x = parent[x];
+        }
+        return x;
+    };
+    for (int64_t e = 0; e < ne; ++e)
+        for (int i = 1; i < m.arity; ++i) {
+            const int32_t a = find(m.table[e * m.arity]), c = find(m.table[e * m.arity + i]);
+            if (a != c) parent[std::max(a, c)] = std::min(a, c);
+        }
+    // components numbered by their first element; elements listed per
+    // component in increasing order
+    std::vector<int32_t> comp_of_root(np, -1), comp(ne);
+    int32_t ncomp = 0;
+    for (int64_t e = 0; e < ne; ++e) {
+        const int32_t r = find(m.table[e * m.arity]);
+        if (comp_of_root[r] < 0) comp_of_root[r] = ncomp++;
+        comp[e] = comp_of_root[r];
+    }
+    std::vector<int64_t> coff(int64_t(ncomp) + 1, 0);
+    for (int64_t e = 0; e < ne; ++e) coff[comp[e] + 1]++;
+    for (int32_t c = 0; c < ncomp; ++c) coff[c + 1] += coff[c];
     std::vector<int32_t> ids(ne);
-    std::iota(ids.begin(), ids.end(), 0);
+    {
+        std::vector<int64_t> fill(coff.begin(), coff.end() - 1);
+        for (int64_t e = 0; e < ne; ++e) ids[fill[comp[e]]++] = int32_t(e);
+    }
     Bisector b{&ec, dim, block_size, {}, {0}, {}};
     b.out.reserve(ne);
-    int64_t nb = (ne + block_size - 1) / block_size;
-    b.run(ids.data(), ne, nb, 0);
+    for (int32_t c = 0; c < ncomp; ++c) {
+        const int64_t n = coff[c + 1] - coff[c];
+        b.run(ids.data() + coff[c], n, (n + block_size - 1) / block_size, 0);
+    }
     block_off.swap(b.off);
     block_code.swap(b.code);
     return b.out;

@@ -60,6 +60,26 @@ def test_rcm_gps_match_oracle(order):
     assert np.array_equal(L.perm(L.s_nodes), nord)
 
 
+@pytest.mark.parametrize("geometric", [True, False])
+def test_partition_keeps_separate_meshes_apart(geometric):
+    """Bisection runs per connected component: on a union of separate meshes
+    (here placed on top of each other, so coordinates cannot separate
+    them) no block mixes meshes and mesh k gets ceil(E_k / S) blocks."""
+    from meshgen import union
+    S = 128
+    ms = [quad_mesh(30, 20, seed=1), quad_mesh(7, 5, seed=2), quad_mesh(41, 13, seed=3)]
+    u = union(ms, spacing=0.0)
+    L = EdgeFluxLoop(u.x, u.q, u.adt, u.e2n, u.e2c, device=-1, order="rcm+partition",
+                     block_size=S, geometric_partition=geometric)
+    off = L.part_blocks()
+    assert P.check_block_offsets(off, L.E, S) is None
+    mesh_of_edge = np.searchsorted(u.edge_off, L.perm(L.s_edges), side="right") - 1
+    for b in range(len(off) - 1):
+        assert np.unique(mesh_of_edge[off[b]:off[b + 1]]).size == 1
+    per_mesh = np.bincount(mesh_of_edge[off[:-1]], minlength=len(ms))
+    assert list(per_mesh) == [-(-m.e2n.shape[0] // S) for m in ms]
+
+
 @pytest.mark.parametrize("S", [64, 100, 512])
 @pytest.mark.parametrize("geometric", [True, False])
 def test_partition_is_valid_and_point_order_matches_oracle(S, geometric):
