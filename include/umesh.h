@@ -382,10 +382,12 @@ um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr);
  *     axis first: the mean of the element's points' `coords` through
  *     coord_map, or, if no coordinates are given, graph-distance
  *     coordinates from BFS landmarks on the driving map's point graph);
- *     every split keeps each
- *     side at most (its share of blocks) * block_size elements, so all
- *     blocks end up at most block_size.  Elements are renumbered block by
- *     block, keeping their previous relative order inside a block.  With point_reorder, every to-set of a map from the from-set
+ *     each connected component of the elements is bisected on its own into
+ *     ceil(size / block_size) blocks; every split keeps each side at most
+ *     (its share of blocks) * block_size elements, so all blocks end up at
+ *     most block_size.  Elements are renumbered block by block, keeping
+ *     their previous relative order inside a block.  With point_reorder,
+ *     every to-set of a map from the from-set
  *     is renumbered by (number of accessing blocks, list of accessing
  *     blocks), ties keeping the previous order.  The blocks are remembered
  *     and used by HIER plans with the same block_size, or with a multiple
