@@ -369,15 +369,21 @@ def main() -> int:
         for dt, rb in (("f64", 8), ("f32", 4)):
             ts = TimeStep2D(mesh.x, mesh.q, mesh.e2n, mesh.e2c, mesh.b2n, mesh.b2c, mesh.c2n,
                             qinf, device=0, block_size=S, layout=args.layout, dtype=dt)
-            ts.build_plans(flux_block_size=S, staging=args.staging, tcmode=args.tcmode,
-                           block_colouring=args.bcol, schedule=args.schedule,
-                           elems_per_thread=args.ept)
-            s = time_steps(torch, ts.step, max(args.steps // 4, 1), args.warmup)
-            sb = measure.step_useful_bytes(N, C, E, ts.B, rb)
-            tsx[dt] = {"ms_per_step": s * 1e3, "cells_per_s": C / s, "useful_bytes_per_step": sb,
-                       "useful_gbps": sb / s / 1e9,
-                       "launches": sum(p.stats["n_launches"] for p in ts.plans.values())}
-            log(f"time step {dt}: {s * 1e6:.1f} us/step ({sb / s / 1e9:.0f} GB/s useful)")
+            # the four loops as such, then the update fused with the next
+            # step's adt (one pass over q fewer; the step's algorithmic
+            # bytes are counted for the four loops in both cases)
+            for fused in (False, True):
+                ts.build_plans(flux_block_size=S, staging=args.staging, tcmode=args.tcmode,
+                               block_colouring=args.bcol, schedule=args.schedule,
+                               elems_per_thread=args.ept, fuse_adt=fused)
+                s = time_steps(torch, ts.step, max(args.steps // 4, 1), args.warmup)
+                sb = measure.step_useful_bytes(N, C, E, ts.B, rb)
+                name = dt + ("_fused_update_adt" if fused else "")
+                loops = ("flux", "bres", "upa") if fused else ("adt", "flux", "bres", "upd")
+                tsx[name] = {"ms_per_step": s * 1e3, "cells_per_s": C / s,
+                             "useful_bytes_per_step": sb, "useful_gbps": sb / s / 1e9,
+                             "launches": sum(ts.plans[k].stats["n_launches"] for k in loops)}
+                log(f"time step {name}: {s * 1e6:.1f} us/step ({sb / s / 1e9:.0f} GB/s useful)")
             ts.close()
         extras["time_step_2400x1200"] = tsx
 

@@ -205,13 +205,28 @@ typedef enum { UM_SCHED_COLOUR_LAUNCHES = 0, UM_SCHED_DATAFLOW = 1 } um_schedule
  * workgroup partials are summed by a second launch in a fixed order and
  * added to rms, so the result is bitwise reproducible for a given
  * block_size.  Two launches; the plan owns the partials buffer.
+ *
+ * UM_K_UPDATE_ADT_2D -- UM_K_UPDATE_2D followed, in the same cell loop, by
+ * UM_K_CELL_ADT_2D on the updated state: the time-step scalar the next step
+ * needs, without reading q again.  Args:
+ *   0: q   dim 4 direct, UM_RW
+ *   1: res dim 4 direct, UM_RW
+ *   2: adt dim 1 direct, UM_RW (read for the update, then overwritten)
+ *   3: rms dim 1 global, UM_INC
+ *   4: x   dim 2 via a cell->node map of arity 4, idx UM_ALL_SLOTS, UM_READ
+ * Types and layouts as for the two loops.  params = {gm1}.  Per cell the
+ * results equal bit for bit those of UM_K_UPDATE_2D then UM_K_CELL_ADT_2D
+ * (same arithmetic in the same order; the sum of squares is reduced the
+ * same way).  A time step then reads: edge flux, boundary flux, update +
+ * adt, with adt computed once before the first step.  Two launches.
  */
 typedef enum {
     UM_K_EDGE_FLUX_LF2D = 0,
     UM_K_HEX_HOURGLASS_3D = 1,
     UM_K_CELL_ADT_2D = 2,
     UM_K_BOUNDARY_FLUX_2D = 3,
-    UM_K_UPDATE_2D = 4
+    UM_K_UPDATE_2D = 4,
+    UM_K_UPDATE_ADT_2D = 5
 } um_kernel;
 
 /* Map slot value meaning "every slot of the map" (a vector argument). */

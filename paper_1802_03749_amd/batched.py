@@ -1,7 +1,8 @@
 """Batched time steps over many independent 2D meshes.
 
 Two executors of the same work, one explicit time step (cell adt, edge flux,
-boundary flux, update with sum of squares) on every mesh of a batch:
+boundary flux, update with sum of squares; by default the update and the
+next step's adt as one fused cell loop) on every mesh of a batch:
 
 * "union": the meshes are joined into one disjoint union (meshgen.union)
   and run as one mesh, so every loop is one set of launches over the whole
@@ -43,7 +44,7 @@ def size_bucket(n_edges: int) -> int:
 class BatchedSteps:
     def __init__(self, meshes, qinf, *, mode: str = "union", device: int = 0,
                  partition_block: int = 256, candidates=DEFAULT_CANDIDATES, tune_reps: int = 5,
-                 union_spacing: float = 8192.0, dtype: str = "f64"):
+                 union_spacing: float = 8192.0, dtype: str = "f64", fuse_adt: bool = True):
         if mode not in ("union", "sequential"):
             raise ValueError(mode)
         self.mode = mode
@@ -57,7 +58,7 @@ class BatchedSteps:
             self.union = u
             ts = TimeStep2D(u.x, u.q, u.e2n, u.e2c, u.b2n, u.b2c, u.c2n, qinf, device=device,
                             block_size=partition_block, dtype=dtype, partition_coords=u.x_layout)
-            ts.build_plans(flux_block_size=partition_block)
+            ts.build_plans(flux_block_size=partition_block, fuse_adt=fuse_adt)
             ts.run_loop("adt")
             best, ms = ts.autotune_flux(self.candidates, tune_reps)
             self.tuned["union"] = (self.candidates[best], ms)
@@ -69,7 +70,7 @@ class BatchedSteps:
                                 device=device, block_size=partition_block, dtype=dtype)
                 b = size_bucket(ts.E)
                 if b not in self.tuned:
-                    ts.build_plans(flux_block_size=partition_block)
+                    ts.build_plans(flux_block_size=partition_block, fuse_adt=fuse_adt)
                     ts.run_loop("adt")
                     best, ms = ts.autotune_flux(self.candidates, tune_reps)
                     self.tuned[b] = (self.candidates[best], ms)
@@ -79,7 +80,8 @@ class BatchedSteps:
                                    schedule=c.get("schedule", "colour_launches"),
                                    block_colouring=c.get("block_colouring", "first_fit"),
                                    staging=c.get("staging", "all"),
-                                   elems_per_thread=c.get("elems_per_thread", 1))
+                                   elems_per_thread=c.get("elems_per_thread", 1),
+                                   fuse_adt=fuse_adt)
                 self.steps.append(ts)
         torch.cuda.synchronize()
         # the trial runs changed nothing but res (zeroed again) and adt

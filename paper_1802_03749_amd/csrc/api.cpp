@@ -201,13 +201,16 @@ LaunchArgs launch_args_hex(Plan &p, const double *params, int32_t nparams, void 
 }
 
 bool is_step_kernel(int32_t k) {
-    return k == UM_K_CELL_ADT_2D || k == UM_K_BOUNDARY_FLUX_2D || k == UM_K_UPDATE_2D;
+    return k == UM_K_CELL_ADT_2D || k == UM_K_BOUNDARY_FLUX_2D || k == UM_K_UPDATE_2D ||
+           k == UM_K_UPDATE_ADT_2D;
 }
 
 LaunchArgs launch_args_step(Plan &p, const double *params, int32_t nparams, void *stream) {
     const Ctx &ctx = *p.ctx;
     if (ctx.device < 0) fail(UM_ERR_STATE, "host-only context cannot execute");
-    const int want = p.kernel == UM_K_CELL_ADT_2D ? 1 : p.kernel == UM_K_BOUNDARY_FLUX_2D ? 6 : 0;
+    const int want = (p.kernel == UM_K_CELL_ADT_2D || p.kernel == UM_K_UPDATE_ADT_2D) ? 1
+                     : p.kernel == UM_K_BOUNDARY_FLUX_2D                              ? 6
+                                                                                      : 0;
     if (nparams != want || (want && !params))
         fail(UM_ERR_ARG, "kernel %d takes %d params, got %d", p.kernel, want, nparams);
     LaunchArgs la{};
@@ -592,7 +595,8 @@ um_status um_plan_stats_get(um_plan plan, um_plan_stats *out) {
                 out->n_global_colours = int32_t(hp.colour_off.size()) - 1;
                 out->n_launches = out->n_global_colours;
             } else {
-                out->n_launches = hp.n_elem > 0 ? (p.kernel == UM_K_UPDATE_2D ? 2 : 1) : 0;
+                const bool two = p.kernel == UM_K_UPDATE_2D || p.kernel == UM_K_UPDATE_ADT_2D;
+                out->n_launches = hp.n_elem > 0 ? (two ? 2 : 1) : 0;
             }
         } else if (hp.strategy == UM_STRAT_HIER) {
             out->n_blocks = int32_t(hp.blk_colour.size());
@@ -795,7 +799,7 @@ um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void
             const int32_t n = int32_t(hp.n_elem);
             if (p.kernel == UM_K_CELL_ADT_2D) {
                 step(LAUNCH_DIRECT, 0, n);
-            } else if (p.kernel == UM_K_UPDATE_2D) {
+            } else if (p.kernel == UM_K_UPDATE_2D || p.kernel == UM_K_UPDATE_ADT_2D) {
                 step(LAUNCH_DIRECT, 0, n);
                 step(LAUNCH_REDUCE, 0, 1);
             } else if (hp.strategy == UM_STRAT_GLOBAL_COLOUR) {

@@ -11,6 +11,8 @@
 //                 hardware FP64 atomics.
 //  update_kernel  cell loop; q -= res/adt, res = 0, and a per-workgroup sum
 //                 of the squared changes in a fixed reduction tree.
+//  update_adt_kernel  the update, then the cell's time-step scalar from the
+//                 updated state (adt_kernel's evaluation, so the same bits).
 //  reduce_kernel  one workgroup adds the per-workgroup sums, in a fixed
 //                 order, to the global target.
 #include <hip/hip_runtime.h>
@@ -42,24 +44,17 @@ __device__ __forceinline__ void store4r(Real *__restrict__ a, int64_t n, int64_t
     }
 }
 
-// Cell time-step scalar, evaluated in the storage type Real.
+// Time-step scalar of the cell with nodes nd and state qc, in the storage
+// type Real (the one evaluation both adt kernels use).
 template <int LAYOUT, typename Real>
-__global__ __launch_bounds__(1024) void adt_kernel(const Real *__restrict__ x,
-                                                   const Real *__restrict__ q,
-                                                   Real *__restrict__ adt,
-                                                   const int4 *__restrict__ c2n, int64_t N,
-                                                   int64_t C, double gm1d) {
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+__device__ __forceinline__ Real cell_adt(const Real *__restrict__ x, int64_t N, int4 nd,
+                                         const Real qc[4], double gm1d) {
     const Real gm1 = Real(gm1d), half = Real(0.5), one = Real(1);
-    const int4 nd = c2n[c];
     Real px[4], py[4];
     load2<LAYOUT>(x, N, nd.x, px[0], py[0]);
     load2<LAYOUT>(x, N, nd.y, px[1], py[1]);
     load2<LAYOUT>(x, N, nd.z, px[2], py[2]);
     load2<LAYOUT>(x, N, nd.w, px[3], py[3]);
-    Real qc[4];
-    load4<LAYOUT>(q, C, c, qc);
     const Real ri = one / qc[0];
     const Real u = qc[1] * ri;
     const Real v = qc[2] * ri;
@@ -73,7 +68,21 @@ __global__ __launch_bounds__(1024) void adt_kernel(const Real *__restrict__ x,
         const Real my = px[k] - px[k1];
         s = s + (fabs(u * mx + v * my) + cs * sqrt(mx * mx + my * my));
     }
-    adt[c] = s;
+    return s;
+}
+
+// Cell time-step scalar, evaluated in the storage type Real.
+template <int LAYOUT, typename Real>
+__global__ __launch_bounds__(1024) void adt_kernel(const Real *__restrict__ x,
+                                                   const Real *__restrict__ q,
+                                                   Real *__restrict__ adt,
+                                                   const int4 *__restrict__ c2n, int64_t N,
+                                                   int64_t C, double gm1d) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    Real qc[4];
+    load4<LAYOUT>(q, C, c, qc);
+    adt[c] = cell_adt<LAYOUT, Real>(x, N, c2n[c], qc, gm1d);
 }
 
 // Far-field boundary flux, evaluated in Real; increments in double.
@@ -162,6 +171,40 @@ __global__ __launch_bounds__(1024) void update_kernel(Real *__restrict__ q,
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// Update, then the next step's time-step scalar from the updated (rounded)
+// state: per cell the values update_kernel and adt_kernel give in turn.
+template <int LAYOUT, typename Real>
+__global__ __launch_bounds__(1024) void update_adt_kernel(Real *__restrict__ q,
+                                                          double *__restrict__ res,
+                                                          Real *__restrict__ adt,
+                                                          const Real *__restrict__ x,
+                                                          const int4 *__restrict__ c2n,
+                                                          double *__restrict__ partials,
+                                                          int64_t N, int64_t C, double gm1d) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (c < C) {
+        const int4 nd = c2n[c];
+        Real qc[4];
+        double r[4];
+        load4<LAYOUT>(q, C, c, qc);
+        load4<LAYOUT>(res, C, c, r);
+        const double a = double(adt[c]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double d = r[k] / a;
+            qc[k] = Real(double(qc[k]) - d);
+            acc = acc + d * d;
+            r[k] = 0.0;
+        }
+        store4r<LAYOUT>(q, C, c, qc);
+        store4<LAYOUT>(res, C, c, r);
+        adt[c] = cell_adt<LAYOUT, Real>(x, N, nd, qc, gm1d);
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 __global__ __launch_bounds__(1024) void reduce_kernel(const double *__restrict__ partials,
                                                       int32_t n, double *__restrict__ gbl) {
     // lane t adds partials t, t + T, t + 2T, ... in that order; the loads of
@@ -212,7 +255,13 @@ hipError_t launch_typed(const LaunchArgs &la, int32_t kernel, int which, int32_t
         if (grid_for(n, bs) != la.n_partials) return hipErrorInvalidValue;
         update_kernel<LAYOUT, Real><<<la.n_partials, bs, 0, la.stream>>>(
             const_cast<Real *>(q), la.res, adt, la.partials, la.C);
-    } else if (kernel == UM_K_UPDATE_2D && which == LAUNCH_REDUCE) {
+    } else if (kernel == UM_K_UPDATE_ADT_2D && which == LAUNCH_DIRECT) {
+        if (grid_for(n, bs) != la.n_partials) return hipErrorInvalidValue;
+        update_adt_kernel<LAYOUT, Real><<<la.n_partials, bs, 0, la.stream>>>(
+            const_cast<Real *>(q), la.res, const_cast<Real *>(adt), x,
+            reinterpret_cast<const int4 *>(la.emap), la.partials, la.N, la.C, la.gm1);
+    } else if ((kernel == UM_K_UPDATE_2D || kernel == UM_K_UPDATE_ADT_2D) &&
+               which == LAUNCH_REDUCE) {
         reduce_kernel<<<1, 1024, 0, la.stream>>>(la.partials, la.n_partials, la.gbl);
     } else {
         return hipErrorInvalidValue;

@@ -123,6 +123,22 @@ StepArgs check_step_args(const Ctx &ctx, int32_t kernel, const um_arg *args, int
         if (sa.dat_q == sa.dat_res) fail(UM_ERR_ARITY, "update kernel: q and res must differ");
         check_layouts(ctx, {sa.dat_q, sa.dat_res, sa.dat_adt}, "update");
         sa.dtype = check_real(ctx, {sa.dat_q, sa.dat_adt}, "update");
+    } else if (kernel == UM_K_UPDATE_ADT_2D) {
+        const Want w[5] = {{4, 0, 0, UM_RW, "q", true},
+                           {4, 0, 0, UM_RW, "res", false},
+                           {1, 0, 0, UM_RW, "adt", true},
+                           {1, UM_GLOBAL, 0, UM_INC, "rms", false},
+                           {2, 4, UM_ALL_SLOTS, UM_READ, "x", true}};
+        check_pattern(ctx, args, nargs, iter, w, 5, "update + adt");
+        sa.dat_q = args[0].dat;
+        sa.dat_res = args[1].dat;
+        sa.dat_adt = args[2].dat;
+        sa.dat_rms = args[3].dat;
+        sa.map_n = args[4].map;
+        sa.dat_x = args[4].dat;
+        if (sa.dat_q == sa.dat_res) fail(UM_ERR_ARITY, "update + adt kernel: q and res must differ");
+        check_layouts(ctx, {sa.dat_x, sa.dat_q, sa.dat_res, sa.dat_adt}, "update + adt");
+        sa.dtype = check_real(ctx, {sa.dat_x, sa.dat_q, sa.dat_adt}, "update + adt");
     } else {
         fail(UM_ERR_UNSUPPORTED, "unknown kernel %d", kernel);
     }
@@ -142,9 +158,10 @@ void build_host_plan_step(const Ctx &ctx, int32_t kernel, const StepArgs &sa, in
         hp.emap = ctx.maps[sa.map_n].table;  // [C][4] node ids
         return;
     }
-    if (kernel == UM_K_UPDATE_2D) {
+    if (kernel == UM_K_UPDATE_2D || kernel == UM_K_UPDATE_ADT_2D) {
         if (o.block_size % 64) fail(UM_ERR_ARG, "update kernel: block_size must be a multiple of 64");
         hp.n_partials = int32_t((n + o.block_size - 1) / o.block_size);
+        if (kernel == UM_K_UPDATE_ADT_2D) hp.emap = ctx.maps[sa.map_n].table;  // [C][4] node ids
         return;
     }
     // boundary flux: (cell, a, b, 0) per slot

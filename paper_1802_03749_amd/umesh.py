@@ -34,7 +34,7 @@ UM_TC_BARRIER, UM_TC_LDS_ATOMIC = 0, 1
 UM_BCOL_FIRST_FIT, UM_BCOL_RECOLOUR, UM_BCOL_MIN = 0, 1, 2
 UM_SCHED_COLOUR_LAUNCHES, UM_SCHED_DATAFLOW = 0, 1
 UM_K_EDGE_FLUX_LF2D, UM_K_HEX_HOURGLASS_3D = 0, 1
-UM_K_CELL_ADT_2D, UM_K_BOUNDARY_FLUX_2D, UM_K_UPDATE_2D = 2, 3, 4
+UM_K_CELL_ADT_2D, UM_K_BOUNDARY_FLUX_2D, UM_K_UPDATE_2D, UM_K_UPDATE_ADT_2D = 2, 3, 4, 5
 UM_ALL_SLOTS = -1
 UM_GLOBAL = -2
 (UM_EXP_BLOCK_OFFSETS, UM_EXP_BLOCK_COLOURS, UM_EXP_THREAD_COLOURS, UM_EXP_SLOT_ELEMENTS,

@@ -95,6 +95,37 @@ def test_time_steps_parity(schedule, layout):
     assert U.um_plan_errors(ts.plans["flux"].handle) == 0
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+def test_fused_update_adt_steps(dtype, layout):
+    """Update and the next step's adt as one cell loop: after every step q,
+    res and the sum of squares equal the unfused step's bit for bit, and
+    adt equals, bit for bit, the adt loop run on the updated state (the
+    next unfused step's first loop) and the oracle's to the bar."""
+    m = quad_mesh(150, 70, seed=21)
+    tu = make(m, layout=layout, block_size=256, dtype=dtype)
+    tf = make(m, layout=layout, block_size=256, dtype=dtype)
+    kw = dict(flux_block_size=256, schedule="dataflow", block_colouring="recolour")
+    tu.build_plans(**kw)
+    st = tf.build_plans(fuse_adt=True, **kw)
+    assert "upa" in st and "upd" not in st and st["upa"]["n_launches"] == 2
+    for k in range(3):
+        for t in (tu, tf):
+            t.rms.zero_()
+            t.step()
+        tu.run_loop("adt")          # the next unfused step starts with this
+        torch.cuda.synchronize()
+        for a, b in ((tu.q_user(), tf.q_user()), (tu.res_user(), tf.res_user()),
+                     (tu.adt_user(), tf.adt_user())):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), k
+        assert tu.rms.item() == tf.rms.item(), k
+        if dtype == "f64":
+            assert rel_l2(tf.adt_user(), native.adt_loop(m.c2n, m.x, tf.q_user())) <= TOL, k
+    # setting up the plans again starts from a fresh adt loop
+    tf.build_plans(fuse_adt=True, **kw)
+    assert not tf.adt_valid
+
+
 def test_step_reproducible_bitwise():
     m = quad_mesh(120, 90, seed=5)
     outs = []

@@ -117,6 +117,19 @@ def test_argument_patterns_are_checked():
     with pytest.raises(U.UmeshError) as e:   # workgroup not a multiple of 64
         _plan(ts, U.UM_K_UPDATE_2D, upd, ts.s_cells, block_size=96)
     assert e.value.status == U.UM_ERR_ARG
+    upa = upd[:2] + [a(ts.d_adt, -1, 0, U.UM_RW), upd[3],
+                     a(ts.d_x, ts.m_c2n, U.UM_ALL_SLOTS, U.UM_READ)]
+    p = _plan(ts, U.UM_K_UPDATE_ADT_2D, upa, ts.s_cells)
+    assert U.um_plan_stats_get(p).n_launches == 2
+    for i, wrong in ((2, a(ts.d_adt, -1, 0, U.UM_READ)),          # adt is rewritten
+                     (4, a(ts.d_x, ts.m_c2n, 0, U.UM_READ)),       # all four nodes
+                     (1, a(ts.d_q, -1, 0, U.UM_RW))):              # q and res differ
+        bad = list(upa); bad[i] = wrong
+        with pytest.raises(U.UmeshError) as e:
+            _plan(ts, U.UM_K_UPDATE_ADT_2D, bad, ts.s_cells)
+        assert e.value.status == U.UM_ERR_ARITY
+    with pytest.raises(U.UmeshError):
+        _plan(ts, U.UM_K_UPDATE_ADT_2D, upa[:4], ts.s_cells)
     bres = [a(ts.d_x, ts.m_b2n, 0, U.UM_READ), a(ts.d_x, ts.m_b2n, 1, U.UM_READ),
             a(ts.d_q, ts.m_b2c, 0, U.UM_READ), a(ts.d_adt, ts.m_b2c, 0, U.UM_READ),
             a(ts.d_res, ts.m_b2c, 0, U.UM_INC)]
