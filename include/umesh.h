@@ -397,8 +397,10 @@ um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr);
  *     axis first: the mean of the element's points' `coords` through
  *     coord_map, or, if no coordinates are given, graph-distance
  *     coordinates from BFS landmarks on the driving map's point graph);
- *     each connected component of the elements is bisected on its own into
- *     ceil(size / block_size) blocks; every split keeps each side at most
+ *     each connected component of the elements with at least block_size
+ *     elements is bisected on its own into ceil(size / block_size) blocks,
+ *     smaller ones are packed whole into shared blocks; every split keeps
+ *     each side at most
  *     (its share of blocks) * block_size elements, so all blocks end up at
  *     most block_size.  Elements are renumbered block by block, keeping
  *     their previous relative order inside a block.  With point_reorder,

@@ -332,10 +332,12 @@ std::vector<int32_t> partition_elements(const Ctx &ctx, int32_t drv, int32_t blo
         }
     for (double &v : ec) v /= k;
     // connected components of the elements (elements sharing a point of the
-    // driving map): each is bisected on its own into ceil(n_c / block_size)
-    // blocks, so no block mixes components (a count-based cut through a
-    // union of separate meshes would otherwise leave slivers and blocks
-    // straddling two meshes, whose staged sets are several times larger)
+    // driving map): each with at least block_size elements is bisected on
+    // its own into ceil(n_c / block_size) blocks, so such a component never
+    // shares a block (a count-based cut through a union of separate meshes
+    // would otherwise leave slivers and blocks straddling two meshes, whose
+    // staged sets are several times larger); smaller components are packed
+    // whole, in order, into blocks of at most block_size elements
     const int64_t np = ctx.sets[m.to].size;
     std::vector<int32_t> parent(np);
     std::iota(parent.begin(), parent.end(), 0);
@@ -370,10 +372,27 @@ std::vector<int32_t> partition_elements(const Ctx &ctx, int32_t drv, int32_t blo
     }
     Bisector b{&ec, dim, block_size, {}, {0}, {}};
     b.out.reserve(ne);
+    int64_t pack = 0;  // elements of small components in the open block
+    auto close_pack = [&]() {
+        if (pack == 0) return;
+        // previous relative order inside the block, as for bisected blocks
+        std::sort(b.out.end() - pack, b.out.end());
+        b.off.push_back(int32_t(b.out.size()));
+        b.code.push_back(0);
+        pack = 0;
+    };
     for (int32_t c = 0; c < ncomp; ++c) {
         const int64_t n = coff[c + 1] - coff[c];
-        b.run(ids.data() + coff[c], n, (n + block_size - 1) / block_size, 0);
+        if (n >= block_size) {
+            close_pack();
+            b.run(ids.data() + coff[c], n, (n + block_size - 1) / block_size, 0);
+            continue;
+        }
+        if (pack + n > block_size) close_pack();
+        b.out.insert(b.out.end(), ids.data() + coff[c], ids.data() + coff[c + 1]);
+        pack += n;
     }
+    close_pack();
     block_off.swap(b.off);
     block_code.swap(b.code);
     return b.out;

@@ -80,6 +80,43 @@ def test_partition_keeps_separate_meshes_apart(geometric):
     assert list(per_mesh) == [-(-m.e2n.shape[0] // S) for m in ms]
 
 
+def test_partition_packs_small_components():
+    """Components smaller than a block are packed whole into shared blocks:
+    partitioning the boundary edges through their arity-1 edge->cell map
+    (nearly every edge its own component) still gives about ceil(B/S)
+    blocks, each in increasing previous order, and no component is split."""
+    m = quad_mesh(60, 40, seed=4)
+    b2c = np.ascontiguousarray(np.asarray(m.b2c, np.int32).reshape(-1, 1))
+    B, C = b2c.shape[0], m.q.shape[0]
+    ctx = U.um_create(-1)
+    try:
+        s_cells = U.um_decl_set(ctx, C, "cells")
+        s_b = U.um_decl_set(ctx, B, "bedges")
+        m_b2c = U.um_decl_map(ctx, s_b, s_cells, 1, b2c)
+        S = 64
+        o = U.um_reorder_opts()
+        o.mode = U.UM_REORDER_PARTITION
+        o.driving_map = m_b2c
+        o.block_size = S
+        o.coord_map = -1
+        U.um_reorder_mesh(ctx, o)
+        _, nb = U.um_get_blocks(ctx, s_b)
+        off = np.empty(nb + 1, np.int32)
+        U.um_get_blocks(ctx, s_b, off, nb + 1)
+        perm = np.empty(B, np.int32)
+        U.um_get_perm(ctx, s_b, perm)
+    finally:
+        U.um_destroy(ctx)
+    assert P.check_block_offsets(off, B, S) is None
+    assert nb <= -(-B // S) + 1
+    for b in range(nb):
+        assert np.all(np.diff(perm[off[b]:off[b + 1]]) > 0)
+    cell = b2c[perm, 0]
+    blk = np.repeat(np.arange(nb), np.diff(off))
+    for c in np.unique(cell):               # a corner cell's two edges stay together
+        assert np.unique(blk[cell == c]).size == 1
+
+
 @pytest.mark.parametrize("S", [64, 100, 512])
 @pytest.mark.parametrize("geometric", [True, False])
 def test_partition_is_valid_and_point_order_matches_oracle(S, geometric):
