@@ -376,7 +376,10 @@ um_status um_decl_map(um_ctx ctx, int32_t from_set, int32_t to_set, int32_t arit
 um_status um_decl_dat(um_ctx ctx, int32_t set, int32_t dim, int32_t dtype, int32_t layout,
                       void *device_ptr, int32_t *dat_id);
 
-/* Point an existing dat at another device buffer of the same shape. */
+/* Point an existing dat at another device buffer of the same shape
+ * (size(set) * dim values of the dat's dtype in its layout: the caller's
+ * guarantee, not checked).  Plans built earlier use the new buffer from
+ * their next execution on.  Errors: UM_ERR_ARG for a bad dat id. */
 um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr);
 
 /* ------------------------------------------------------------- reordering */
@@ -400,13 +403,12 @@ um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr);
  *     each connected component of the elements with at least block_size
  *     elements is bisected on its own into ceil(size / block_size) blocks,
  *     smaller ones are packed whole into shared blocks; every split keeps
- *     each side at most
- *     (its share of blocks) * block_size elements, so all blocks end up at
- *     most block_size.  Elements are renumbered block by block, keeping
- *     their previous relative order inside a block.  With point_reorder,
- *     every to-set of a map from the from-set
- *     is renumbered by (number of accessing blocks, list of accessing
- *     blocks), ties keeping the previous order.  The blocks are remembered
+ *     each side at most (its share of blocks) * block_size elements, so all
+ *     blocks end up at most block_size.  Elements are renumbered block by
+ *     block, keeping their previous relative order inside a block.  With
+ *     point_reorder, every to-set of a map from the from-set is renumbered
+ *     by (number of accessing blocks, list of accessing blocks), ties
+ *     keeping the previous order.  The blocks are remembered
  *     and used by HIER plans with the same block_size, or with a multiple
  *     k * block_size (k consecutive blocks form one plan block).
  *   USER_BLOCKS: as PARTITION, but the blocks are the caller's: elements
@@ -456,6 +458,8 @@ um_status um_permute_dat(um_ctx ctx, int32_t set, int32_t direction, const void 
 um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t nargs,
                         int32_t iter_set, const um_plan_opts *opts, um_plan *out);
 
+/* Copy the plan's statistics (um_plan_stats, fields listed there) to *out.
+ * Errors: UM_ERR_ARG for a null out. */
 um_status um_plan_stats_get(um_plan plan, um_plan_stats *out);
 
 /* Copy plan contents to host memory for verification.  *n_out receives the
@@ -464,6 +468,8 @@ um_status um_plan_stats_get(um_plan plan, um_plan_stats *out);
 um_status um_plan_export(um_plan plan, int32_t field, int32_t *host_out, int64_t capacity,
                          int64_t *n_out);
 
+/* Release the plan and its device memory after a device synchronisation
+ * (so work already enqueued with it completes first).  NULL is accepted. */
 um_status um_plan_destroy(um_plan plan);
 
 /* Execute the loop once on `stream` (hipStream_t, NULL = default stream),
@@ -501,6 +507,8 @@ um_status um_plan_set_timing(um_plan plan, int32_t enable);
  * waits of a DATAFLOW plan that gave up on a neighbour (any non-zero count
  * makes every later result of the plan invalid); 0 for other plans. */
 um_status um_plan_errors(um_plan plan, int32_t *n_errors);
+/* See um_plan_set_timing: waits for the recorded event pairs, returns their
+ * summed time and count, and resets.  Errors: UM_ERR_ARG for null outputs. */
 um_status um_plan_timing(um_plan plan, double *ms_total, int64_t *n_launches);
 
 /* Verification entry point: evaluate the elemental flux of every element of
