@@ -26,14 +26,14 @@ import torch
 
 from .timestep import TimeStep2D
 
+# block sizes are multiples of the default partition block (512), so every
+# candidate uses whole partition blocks
 DEFAULT_CANDIDATES = (
-    dict(block_size=256),
     dict(block_size=512),
     dict(block_size=512, block_colouring="recolour"),
-    dict(block_size=256, schedule="dataflow"),
     dict(block_size=512, schedule="dataflow", block_colouring="recolour"),
-    dict(block_size=256, schedule="dataflow", elems_per_thread=2),
     dict(block_size=512, schedule="dataflow", block_colouring="recolour", elems_per_thread=2),
+    dict(block_size=1024, schedule="dataflow", block_colouring="recolour", elems_per_thread=2),
 )
 
 
@@ -43,7 +43,7 @@ def size_bucket(n_edges: int) -> int:
 
 class BatchedSteps:
     def __init__(self, meshes, qinf, *, mode: str = "union", device: int = 0,
-                 partition_block: int = 256, candidates=DEFAULT_CANDIDATES, tune_reps: int = 5,
+                 partition_block: int = 512, candidates=DEFAULT_CANDIDATES, tune_reps: int = 5,
                  union_spacing: float = 8192.0, dtype: str = "f64", fuse_adt: bool = True):
         if mode not in ("union", "sequential"):
             raise ValueError(mode)
