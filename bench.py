@@ -330,25 +330,39 @@ def main() -> int:
         hm = hex_mesh(128, seed=1)
         hb = 96 * hm.n_nodes + 32 * hm.n_elems   # x, v once, force twice, int32 map
         hx = {"elements": hm.n_elems, "nodes": hm.n_nodes, "useful_bytes_per_step": hb}
-        # hierarchical in the headline layout; the baselines in their best
-        # layout (atomics run far faster on SoA data)
-        for order, strat, hS, layouts in (("rcm+partition", "hier", 512, (args.layout,)),
+        # hierarchical in the headline layout (dataflow schedule at 256
+        # elements per block; one launch per block colour at 512 as a
+        # variant); the baselines in their best layout (atomics run far
+        # faster on SoA data)
+        for order, strat, hS, layouts in (("rcm+partition", "hier", 256, (args.layout,)),
+                                          ("rcm+partition", "hier_colour_launches", 512,
+                                           (args.layout,)),
                                           ("rcm", "global", 256, ("aos", "soa")),
                                           ("rcm", "atomic", 256, ("aos", "soa"))):
             runs = {}
             for lay in layouts:
                 H = HexLoop(hm.x, hm.v, hm.e2n, device=0, order=order, block_size=hS,
                             layout=lay)
-                p = H.plan(strat, hS, block_colouring="min" if strat == "hier" else "first_fit")
+                if strat == "hier":
+                    p = H.plan("hier", hS, block_colouring="min", schedule="dataflow")
+                elif strat == "hier_colour_launches":
+                    p = H.plan("hier", hS, block_colouring="min")
+                else:
+                    p = H.plan(strat, hS)
                 s = time_steps(torch, lambda: H.run(p), max(args.steps // 2, 1), args.warmup)
+                if U.um_plan_errors(p.handle) != 0:
+                    log("a hex dataflow wait timed out: the timed results are invalid")
+                    return 3
                 runs[lay] = {"order": order, "layout": lay, "block_size": hS,
                              "elements_per_s": hm.n_elems / s, "ms_per_step": s * 1e3,
-                             "useful_gbps": hb / s / 1e9, "launches": p.stats["n_launches"]}
+                             "useful_gbps": hb / s / 1e9, "launches": p.stats["n_launches"],
+                             "block_colours": p.stats["n_block_colours"]}
                 if strat == "hier":
-                    p2 = H.plan(strat, hS, block_colouring="min", tcmode="lds_atomic")
+                    p2 = H.plan("hier", hS, block_colouring="min", tcmode="lds_atomic",
+                                schedule="dataflow")
                     s2 = time_steps(torch, lambda: H.run(p2), max(args.steps // 2, 1),
                                     args.warmup)
-                    hx["hier_lds_atomic"] = {"order": order, "layout": lay,
+                    hx["hier_lds_atomic"] = {"order": order, "layout": lay, "block_size": hS,
                                              "elements_per_s": hm.n_elems / s2,
                                              "ms_per_step": s2 * 1e3,
                                              "useful_gbps": hb / s2 / 1e9,
