@@ -411,12 +411,11 @@ hipError_t hex_launch_layout(const LaunchArgs &la, int which, int32_t begin, int
                     la.N};
     const double kappa = la.gm1;
     if (which == LAUNCH_HIER) {
-        static bool attr[2] = {false, false};
         const bool atom = la.tcmode == UM_TC_LDS_ATOMIC;
         auto kern = atom ? hex_hier_kernel<LAYOUT, UM_TC_LDS_ATOMIC>
                          : hex_hier_kernel<LAYOUT, UM_TC_BARRIER>;
         clear_stale_error();
-        const hipError_t ea = allow_lds(reinterpret_cast<const void *>(kern), lds, attr[atom]);
+        const hipError_t ea = allow_lds(reinterpret_cast<const void *>(kern), lds);
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL(kern, dim3(end - begin), dim3(la.block_size), size_t(lds), la.stream,
                            la.binfo, la.stg_c, la.crun, reinterpret_cast<const uint4 *>(la.loc), d,
@@ -424,12 +423,11 @@ hipError_t hex_launch_layout(const LaunchArgs &la, int which, int32_t begin, int
         return hipGetLastError();
     }
     if (which == LAUNCH_HIER_FLOW) {
-        static bool fattr[2] = {false, false};
         const bool atom = la.tcmode == UM_TC_LDS_ATOMIC;
         auto kern = atom ? hex_flow_kernel<LAYOUT, UM_TC_LDS_ATOMIC>
                          : hex_flow_kernel<LAYOUT, UM_TC_BARRIER>;
         clear_stale_error();
-        const hipError_t ea = allow_lds(reinterpret_cast<const void *>(kern), lds, fattr[atom]);
+        const hipError_t ea = allow_lds(reinterpret_cast<const void *>(kern), lds);
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL(kern, dim3(end - begin), dim3(la.block_size), size_t(lds), la.stream,
                            la.binfo, la.stg_c, la.crun, reinterpret_cast<const uint4 *>(la.loc), d,

@@ -592,10 +592,9 @@ __global__ __launch_bounds__(1024) void debug_kernel(const int4 *__restrict__ em
 template <int LAYOUT, int ST, int TC, int EPT, typename Real>
 hipError_t launch_hier_one(const LaunchArgs &la, int32_t nblocks, int32_t base, int64_t lds,
                            const Dats<Real> &d) {
-    static bool attr = false;
     clear_stale_error();
-    const hipError_t ea = allow_lds(
-        reinterpret_cast<const void *>(hier_kernel<LAYOUT, ST, TC, EPT, Real>), lds, attr);
+    const hipError_t ea =
+        allow_lds(reinterpret_cast<const void *>(hier_kernel<LAYOUT, ST, TC, EPT, Real>), lds);
     if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL((hier_kernel<LAYOUT, ST, TC, EPT, Real>), dim3(nblocks),
                        dim3(la.block_size), size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n,
@@ -630,10 +629,9 @@ hipError_t launch_hier(const LaunchArgs &la, int32_t nblocks, int32_t base, int6
 template <int LAYOUT, int TC, int EPT, typename Real>
 hipError_t launch_flow_one(const LaunchArgs &la, int32_t nblocks, int64_t lds,
                            const Dats<Real> &d) {
-    static bool attr = false;
     clear_stale_error();
-    const hipError_t ea = allow_lds(
-        reinterpret_cast<const void *>(hier_flow_kernel<LAYOUT, TC, EPT, Real>), lds, attr);
+    const hipError_t ea =
+        allow_lds(reinterpret_cast<const void *>(hier_flow_kernel<LAYOUT, TC, EPT, Real>), lds);
     if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL((hier_flow_kernel<LAYOUT, TC, EPT, Real>), dim3(nblocks),
                        dim3(la.block_size), size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n,

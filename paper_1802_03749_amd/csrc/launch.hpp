@@ -3,6 +3,10 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "internal.hpp"
 
 namespace um {
@@ -38,20 +42,27 @@ struct LaunchArgs {
 // launch only.
 inline void clear_stale_error() { (void)hipGetLastError(); }
 
-// Makes `lds` bytes of dynamic LDS launchable for `kernel`: up to 64 KiB
-// needs nothing; above, the kernel's dynamic limit is raised once per
-// process to the workgroup maximum (160 KiB on gfx950) minus the kernel's
-// static LDS.  Returns the runtime's error, or hipErrorInvalidValue if the
-// request cannot fit.
-inline hipError_t allow_lds(const void *kernel, int64_t lds, bool &done) {
-    if (lds <= 64 * 1024 || done) return hipSuccess;
+// Makes `lds` bytes of dynamic LDS launchable for `kernel` on the current
+// device: up to 64 KiB needs nothing; above, the kernel's dynamic limit is
+// raised, once per kernel and device, to the workgroup maximum (160 KiB on
+// gfx950) minus the kernel's static LDS.  Returns the runtime's error, or
+// hipErrorInvalidValue if the request cannot fit.
+inline hipError_t allow_lds(const void *kernel, int64_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static std::mutex mu;
+    static std::set<std::pair<const void *, int>> done;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count({kernel, dev})) return hipSuccess;
     hipFuncAttributes fa{};
-    hipError_t e = hipFuncGetAttributes(&fa, kernel);
+    e = hipFuncGetAttributes(&fa, kernel);
     if (e != hipSuccess) return e;
     const int64_t room = int64_t(160 * 1024) - int64_t(fa.sharedSizeBytes);
     if (lds > room) return hipErrorInvalidValue;
     e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(room));
-    if (e == hipSuccess) done = true;
+    if (e == hipSuccess) done.insert({kernel, dev});
     return e;
 }
 
