@@ -406,6 +406,20 @@ def test_hex_parity(layout, strategy, order, S):
     assert rel_l2(L.force_user(), ref) <= TOL
 
 
+@pytest.mark.parametrize("schedule", ["colour_launches", "dataflow"])
+def test_hex_blocks_above_64k_lds(schedule):
+    """1024-element hex blocks stage about 1,400 nodes (72 B each in LDS),
+    so the launches need the raised dynamic-LDS limit."""
+    m, ref = hexmesh(24)
+    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=1024)
+    p = L.plan("hier", 1024, block_colouring="min", schedule=schedule)
+    assert p.stats["lds_bytes_max"] > 64 * 1024
+    L.run(p)
+    torch.cuda.synchronize()
+    assert U.um_plan_errors(p.handle) == 0
+    assert rel_l2(L.force_user(), ref) <= TOL
+
+
 @pytest.mark.parametrize("layout", ["aos", "soa"])
 def test_hex_lds_atomic_rounds(layout):
     """LDS atomics instead of thread-colour rounds: same result to rounding."""
