@@ -250,10 +250,15 @@ class TimeStep2D:
         U.um_loop_exec(self.plans[name].handle, self.params(name),
                        self.stream if stream is None else stream)
 
+    def invalidate_adt(self) -> None:
+        """Declare adt stale (call after writing q outside step()): with fused
+        plans the next step then starts with the adt loop again."""
+        self.adt_valid = False
+
     def step(self, stream=None) -> None:
         """Enqueue one time step: adt, edge flux, boundary flux, update; with
         fused plans the adt of a step comes from the previous step's upa
-        (computed here only before the first step, or after q was set)."""
+        (computed here only before the first step, or after invalidate_adt)."""
         if not self.fused:
             for name in ("adt", "flux", "bres", "upd"):
                 self.run_loop(name, stream)

@@ -121,6 +121,17 @@ def test_fused_update_adt_steps(dtype, layout):
         assert tu.rms.item() == tf.rms.item(), k
         if dtype == "f64":
             assert rel_l2(tf.adt_user(), native.adt_loop(m.c2n, m.x, tf.q_user())) <= TOL, k
+    # a state written from outside: after invalidate_adt the next fused step
+    # starts with the adt loop again and still matches the unfused step
+    qn = (tf.q.flip(0) if layout == "aos" else tf.q.flip(1)).clone()
+    for t in (tu, tf):
+        t.q.copy_(qn)
+    tf.invalidate_adt()
+    for t in (tu, tf):
+        t.rms.zero_()
+        t.step()
+    torch.cuda.synchronize()
+    assert np.array_equal(tu.q_user().view(np.uint8), tf.q_user().view(np.uint8))
     # setting up the plans again starts from a fresh adt loop
     tf.build_plans(fuse_adt=True, **kw)
     assert not tf.adt_valid
