@@ -274,7 +274,8 @@ def test_timing_counts_launches():
 
 
 @pytest.mark.parametrize("strategy,order", [("hier", "rcm+partition"), ("global", "rcm"),
-                                            ("atomic", "rcm"), ("hier", "rcm")])
+                                            ("atomic", "rcm"), ("hier", "rcm"),
+                                            ("global", "none"), ("atomic", "none")])
 @pytest.mark.parametrize("layout", ["aos", "soa"])
 def test_parity_medium(strategy, order, layout):
     """1200x600 cells (~1.44M edges)."""
@@ -282,6 +283,21 @@ def test_parity_medium(strategy, order, layout):
     print(f"parity 1200x600 {strategy} {order} {layout}", flush=True)
     L, p, (r,) = gpu_res(m, order, strategy, 512, layout)
     assert rel_l2(r, ref) <= TOL
+
+
+@pytest.mark.parametrize("S", [128, 256, 512, 1024])
+def test_medium_benchmark_options_block_sizes(S):
+    """1200x600 cells with the benchmark's plan options (dataflow schedule,
+    two edges per lane, RECOLOUR) at block sizes 128 to 1024."""
+    m, ref = mesh(1200, 600)
+    print(f"parity 1200x600 dataflow S={S}", flush=True)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
+                     block_size=S)
+    p = L.plan("hier", S, schedule="dataflow", elems_per_thread=2, block_colouring="recolour")
+    L.run(p)
+    torch.cuda.synchronize()
+    assert U.um_plan_errors(p.handle) == 0
+    assert rel_l2(L.res_user(), ref) <= TOL
 
 
 def test_parity_full_size_headline_config():
