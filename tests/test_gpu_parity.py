@@ -382,16 +382,24 @@ def test_fp32_contract_off_fluxes_bit_exact():
 
 
 def test_fp32_full_size():
+    """Both the colour-launch plan and the benchmark's FP32 plan (dataflow,
+    two edges per lane, RECOLOUR) on the 2400x1200 mesh."""
     m, ref64, ref_rn, r32, _ = mesh32(2400, 1200)
     L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
                      block_size=512, dtype="f32")
-    p = L.plan("hier", 512)
-    L.run(p)
-    torch.cuda.synchronize()
-    r = L.res_user()
-    print(f"fp32 2400x1200: vs FP64(rn32) {rel_l2(r, ref_rn):.2e} max {max_rel(r, ref_rn):.2e}; "
-          f"vs FP64 oracle {rel_l2(r, ref64):.2e} max {max_rel(r, ref64):.2e}")
-    assert rel_l2(r, ref_rn) <= FP32_TOL
+    plans = {"colour_launches": L.plan("hier", 512),
+             "dataflow": L.plan("hier", 512, schedule="dataflow", elems_per_thread=2,
+                                block_colouring="recolour")}
+    for name, p in plans.items():
+        L.zero_res()
+        L.run(p)
+        torch.cuda.synchronize()
+        assert U.um_plan_errors(p.handle) == 0
+        r = L.res_user()
+        print(f"fp32 2400x1200 {name}: vs FP64(rn32) {rel_l2(r, ref_rn):.2e} "
+              f"max {max_rel(r, ref_rn):.2e}; vs FP64 oracle {rel_l2(r, ref64):.2e} "
+              f"max {max_rel(r, ref64):.2e}")
+        assert rel_l2(r, ref_rn) <= FP32_TOL
 
 
 # ---------------------------------------------------------- hex element loop
