@@ -83,6 +83,102 @@ def copy_probe(torch, nbytes: int = 512 << 20, reps: int = 20):
     return 2 * nbytes / sec / 1e9, sec
 
 
+def cold_sweep_seconds(torch, run, steps: int) -> float:
+    """Seconds per sweep with the caches evicted: before every sweep a 1 GiB
+    fill (four times the 256 MB last-level cache) runs on the same stream,
+    and only the sweep's launches sit between the two events."""
+    flush = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    run()
+    torch.cuda.synchronize()
+    for e0, e1 in evs:
+        flush.fill_(1.0)
+        e0.record()
+        run()
+        e1.record()
+    torch.cuda.synchronize()
+    ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    del flush
+    return sum(ms) / len(ms) * 1e-3
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_sweep(torch, args, U):
+    """The 1200 x 600 sweep (720k cells, 1.44M edges, FP64): order x strategy
+    x block size.  Random-order hierarchical plans need more block colours
+    than the limit of 256 and are reported as not run, as the paper did for
+    such meshes (Section 3.1.5)."""
+    from meshgen import quad_mesh
+    from paper_1802_03749_amd.edgeloop import EdgeFluxLoop
+    nx, ny = 1200, 600
+    C, N, E = measure.quad_counts(nx, ny)
+    useful = measure.useful_bytes(N, C, E)
+    mesh = quad_mesh(nx, ny, seed=1)
+    steps, warm = max(args.steps // 2, 10), 2
+    sizes = (128, 256, 384, 512, 640, 768, 896, 1024)
+    out = {"mesh": f"{nx}x{ny}", "edges": E, "useful_bytes_per_step": useful,
+           "steps_per_entry": steps, "entries": {}}
+    ent = out["entries"]
+
+    def timed(L, p):
+        s = time_steps(torch, lambda: L.run(p), steps, warm)
+        if U.um_plan_errors(p.handle) != 0:
+            raise RuntimeError("a dataflow wait timed out in the sweep")
+        return {"us_per_sweep": s * 1e6, "edges_per_s": E / s, "useful_gbps": useful / s / 1e9,
+                "launches": p.stats["n_launches"], "block_colours": p.stats["n_block_colours"],
+                "global_colours": p.stats["n_global_colours"]}
+
+    def hier_entries(L, order, S, plans):
+        for name, kw in plans:
+            try:
+                ent[f"{order}/hier_{name}/S{S}"] = timed(L, L.plan("hier", S, **kw))
+            except U.UmeshError as e:
+                why = "colours" if e.status == U.UM_ERR_COLOURS else U.STATUS_NAMES.get(e.status)
+                ent[f"{order}/hier_{name}/S{S}"] = {"not_run": why}
+
+    cl = ("colour_launches", dict(schedule="colour_launches", block_colouring="recolour"))
+    df = ("dataflow", dict(schedule="dataflow", elems_per_thread=2, block_colouring="recolour",
+                           gather=args.gather))
+    for order, lorder in (("random", "none"), ("rcm", "rcm")):
+        L = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0, order=lorder,
+                         block_size=512)
+        for S in sizes:
+            for strat in ("atomic", "global"):
+                ent[f"{order}/{strat}/S{S}"] = timed(L, L.plan(strat, S))
+            hier_entries(L, order, S, (cl,))
+        L.close()
+        log(f"sweep {order} done")
+    for S in sizes:
+        L = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0,
+                         order="rcm+partition", block_size=S)
+        for strat in ("atomic", "global"):
+            ent[f"rcm+partition/{strat}/S{S}"] = timed(L, L.plan(strat, S))
+        hier_entries(L, "rcm+partition", S, (cl, df))
+        L.close()
+    log("sweep rcm+partition done")
+    best = {}
+    for k, v in ent.items():
+        if "us_per_sweep" not in v:
+            continue
+        order, strat = k.split("/")[0], k.split("/")[1]
+        key = f"{order}/{strat}"
+        if key not in best or v["us_per_sweep"] < best[key]["us_per_sweep"]:
+            best[key] = dict(v, block_size=int(k.rsplit("/S", 1)[1]))
+    out["best"] = best
+    return out
+
+
 def tile_blocks(mesh, tx: int, ty: int) -> np.ndarray:
     """Hand-made geometric edge blocks (the paper's reuse upper bound): tiles
     of tx x ty cells of the natural grid; an interior edge belongs to the
@@ -108,6 +204,8 @@ def run_ablations(torch, mesh, S, args, useful, E):
 
     base = dict(staging=args.staging, tcmode=args.tcmode, block_colouring=args.bcol,
                 schedule=args.schedule, elems_per_thread=args.ept)
+    if args.schedule == "dataflow":
+        base["gather"] = args.gather
     tx = 16
     ty = max(S // (2 * tx), 1)
     parts = (("chunks_of_rcm", "rcm", {}),
@@ -117,15 +215,24 @@ def run_ablations(torch, mesh, S, args, useful, E):
         for layout in ("aos", "soa"):
             L = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0, order=order,
                              block_size=S, layout=layout, **kw)
-            out[f"hier_{name}_{layout}"] = entry(L, L.plan("hier", S, **base))
+            kw0 = dict(base)
+            if layout == "soa" and "gather" in kw0:
+                kw0["gather"] = "registers"   # the LDS-DMA gather reads AoS records
+            out[f"hier_{name}_{layout}"] = entry(L, L.plan("hier", S, **kw0))
             if name == "recursive_bisection" and layout == args.layout:
                 for knob, val in (("staging", "inc"), ("tcmode", "lds_atomic"),
                                   ("block_colouring", "first_fit"), ("block_colouring", "recolour"),
                                   ("schedule", "colour_launches"), ("schedule", "dataflow"),
-                                  ("elems_per_thread", 1), ("elems_per_thread", 2)):
-                    if base[knob] == val:
+                                  ("elems_per_thread", 1), ("elems_per_thread", 2),
+                                  ("gather", "registers"), ("gather", "lds_dma"),
+                                  ("wave_colour_groups", True)):
+                    if base.get(knob) == val:
                         continue
                     o = dict(base); o[knob] = val
+                    if o["schedule"] != "dataflow":
+                        o.pop("gather", None)
+                    elif "gather" not in o:
+                        o["gather"] = args.gather
                     try:
                         out[f"hier_partition_{knob}_{val}"] = entry(L, L.plan("hier", S, **o))
                     except Exception as e:  # an unsupported combination
@@ -158,6 +265,8 @@ def main() -> int:
     ap.add_argument("--bcol", default="recolour", choices=["first_fit", "recolour"])
     ap.add_argument("--ept", type=int, default=2, choices=[1, 2],
                     help="edges per lane (the workgroup has block_size / ept lanes)")
+    ap.add_argument("--gather", default="registers", choices=["registers", "lds_dma"],
+                    help="dataflow gather: through registers, or loads that write LDS directly")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="host time spent timing the CPU oracle (0 = skip)")
     ap.add_argument("--no-baselines", action="store_true",
@@ -166,9 +275,11 @@ def main() -> int:
                     help="skip the FP32 variant, the 3D hex workload and the batch")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batch of 64 meshes")
-    ap.add_argument("--ablations", action="store_true",
-                    help="also run the ablation matrix (partitioner, order, layout, staging, "
-                         "colour rounds, block colouring, schedule)")
+    ap.add_argument("--no-ablations", action="store_true",
+                    help="skip the ablation matrix (partitioner, order, layout, staging, colour "
+                         "rounds, block colouring, schedule, gather, wave-pure colour groups)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the 1200x600 order x strategy x block-size sweep")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -203,6 +314,8 @@ def main() -> int:
     reorder_s = time.perf_counter() - t
     hopts = dict(staging=args.staging, tcmode=args.tcmode, block_colouring=args.bcol,
                  elems_per_thread=args.ept)
+    if args.schedule == "dataflow":
+        hopts["gather"] = args.gather
     plan = hier.plan("hier", S, schedule=args.schedule, **hopts)
     st = plan.stats
     log(f"reorder {reorder_s:.1f}s, plan {st['build_seconds']:.2f}s: blocks={st['n_blocks']} "
@@ -236,6 +349,14 @@ def main() -> int:
         f"{achieved:.0f} GB/s ({100 * frac:.1f}% of peak); per-launch events: "
         f"{kern_ms / n_launch * 1e3:.1f} us")
 
+    # the same plan with cold caches: a 1 GiB fill before every sweep, only
+    # the sweep between the events
+    cold_s = cold_sweep_seconds(torch, run, args.steps)
+    cold_achieved, cold_frac = measure.roofline(useful / launches_per_step,
+                                                cold_s / launches_per_step)
+    log(f"cold caches: {cold_s * 1e6:.1f} us/step, {cold_achieved:.0f} GB/s "
+        f"({100 * cold_frac:.1f}% of peak)")
+
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
@@ -243,12 +364,19 @@ def main() -> int:
         if (tr.get("kernel_source_sha256") == kernel_hash() and tr.get("block_size") == S
                 and tr.get("layout") == args.layout and tr.get("staging") == args.staging
                 and tr.get("schedule") == args.schedule
-                and tr.get("elems_per_thread", 1) == args.ept):
+                and tr.get("elems_per_thread", 1) == args.ept
+                and tr.get("gather", "registers") == (args.gather if args.schedule == "dataflow"
+                                                      else "registers")):
             traffic = tr.get("bytes_per_launch")
 
     variants = {}
     other = "colour_launches" if args.schedule == "dataflow" else "dataflow"
-    p2 = hier.plan("hier", S, schedule=other, **hopts)
+    o2 = dict(hopts)
+    if other == "dataflow":
+        o2["gather"] = args.gather
+    else:
+        o2.pop("gather", None)
+    p2 = hier.plan("hier", S, schedule=other, **o2)
     s2 = time_steps(torch, lambda: hier.run(p2), args.steps, args.warmup)
     variants[f"fp64_{other}"] = {"edges_per_s": E / s2, "ms_per_step": s2 * 1e3,
                                  "useful_gbps": useful / s2 / 1e9,
@@ -273,18 +401,25 @@ def main() -> int:
         "edges_per_s": E / s5, "ms_per_step": s5 * 1e3, "useful_gbps": useful / s5 / 1e9,
         "launches": p5.stats["n_launches"]}
     log(f"hier ({args.schedule}, {3 - args.ept} edge(s) per lane): {s5 * 1e6:.1f} us/step")
-    # the headline plan's launches captured in one HIP graph and replayed
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        hier.run(plan, stream=torch.cuda.current_stream().cuda_stream)
-    torch.cuda.synchronize()
+    # the other gather of the dataflow schedule
+    if args.schedule == "dataflow":
+        og = "registers" if args.gather == "lds_dma" else "lds_dma"
+        o6 = dict(hopts); o6["gather"] = og
+        p6 = hier.plan("hier", S, schedule=args.schedule, **o6)
+        s6 = time_steps(torch, lambda: hier.run(p6), args.steps, args.warmup)
+        variants[f"fp64_{args.schedule}_gather_{og}"] = {
+            "edges_per_s": E / s6, "ms_per_step": s6 * 1e3, "useful_gbps": useful / s6 / 1e9,
+            "pct_hbm_peak": 100 * useful / s6 / 1e9 / measure.HBM_PEAK_GBPS,
+            "launches": p6.stats["n_launches"]}
+        log(f"hier ({args.schedule}, gather {og}): {s6 * 1e6:.1f} us/step")
+        # the headline plan's launches captured in one HIP graph and replayed
+    graph = U.HipGraph(lambda stream: hier.run(plan, stream=stream))
     s3 = time_steps(torch, graph.replay, args.steps, args.warmup)
     variants[f"fp64_{args.schedule}_graph"] = {"edges_per_s": E / s3, "ms_per_step": s3 * 1e3,
                                                "useful_gbps": useful / s3 / 1e9,
                                                "launches": st["n_launches"]}
     log(f"hier ({args.schedule}, graph replay): {s3 * 1e6:.1f} us/step")
-    del graph
+    graph.close()
     hier.close()
 
     # ---- baselines on the same GPU and mesh, each in its best order and
@@ -389,7 +524,8 @@ def main() -> int:
             for fused in (False, True):
                 ts.build_plans(flux_block_size=S, staging=args.staging, tcmode=args.tcmode,
                                block_colouring=args.bcol, schedule=args.schedule,
-                               elems_per_thread=args.ept, fuse_adt=fused)
+                               elems_per_thread=args.ept, fuse_adt=fused,
+                               gather=args.gather if args.schedule == "dataflow" else "registers")
                 s = time_steps(torch, ts.step, max(args.steps // 4, 1), args.warmup)
                 sb = measure.step_useful_bytes(N, C, E, ts.B, rb)
                 name = dt + ("_fused_update_adt" if fused else "")
@@ -438,26 +574,43 @@ def main() -> int:
                 bx[f"sequential_{dt}"]["ms_per_step_graph"] / bx[f"union_{dt}"]["ms_per_step_graph"])
         extras["batched_64_meshes"] = bx
 
-    ablations = run_ablations(torch, mesh, S, args, useful, E) if args.ablations else None
+    ablations = None if args.no_ablations else run_ablations(torch, mesh, S, args, useful, E)
+    sweep = None if args.no_sweep else run_sweep(torch, args, U)
 
     # ---- CPU baseline: the oracle's sequential loop on the host
     cpu = None
     if args.cpu_seconds > 0:
         from oracle import native
         native.lib()
-        t0 = time.perf_counter()
-        sweeps = 0
-        while True:
-            native.edge_loop(mesh.e2n, mesh.e2c, mesh.x, mesh.q, mesh.adt)
-            sweeps += 1
-            el = time.perf_counter() - t0
-            if el >= args.cpu_seconds and sweeps >= 2:
-                break
+        budget = args.cpu_seconds / 2
+
+        def timed_sweeps(fn):
+            t0, n = time.perf_counter(), 0
+            while True:
+                fn()
+                n += 1
+                el = time.perf_counter() - t0
+                if el >= budget and n >= 2:
+                    return n, el
+        sweeps, el = timed_sweeps(lambda: native.edge_loop(mesh.e2n, mesh.e2c, mesh.x, mesh.q,
+                                                            mesh.adt))
+        nproc = os.cpu_count()
+        model = cpu_model()
         cpu = {"value": E * sweeps / el, "unit": "edges/s", "cores": 1, "kind": "oracle",
                "sample": f"{sweeps} full sequential sweeps of the same {nx}x{ny} mesh "
-                         f"({E} edges) in user numbering, {el:.1f}s on 1 host core "
-                         f"(host has {os.cpu_count()} logical CPUs)"}
-        log(f"cpu oracle: {cpu['value']:.3g} edges/s")
+                         f"({E} edges) in user numbering, {el:.1f}s on 1 host core",
+               "nproc": nproc, "cpu_model": model}
+        log(f"cpu oracle (1 core): {cpu['value']:.3g} edges/s")
+        groups = native.colour_groups(mesh.e2c)
+        threads = native.omp_threads()
+        sweeps2, el2 = timed_sweeps(lambda: native.edge_loop_coloured(
+            groups, mesh.e2n, mesh.e2c, mesh.x, mesh.q, mesh.adt))
+        cpu["all_cores"] = {
+            "value": E * sweeps2 / el2, "unit": "edges/s", "cores": threads,
+            "kind": "oracle, colour-parallel",
+            "sample": f"{sweeps2} full sweeps of the same mesh, {groups[0]} global edge colours, "
+                      f"one OpenMP parallel loop per colour on {threads} threads, {el2:.1f}s"}
+        log(f"cpu oracle ({threads} threads): {cpu['all_cores']['value']:.3g} edges/s")
 
     out = {
         "metric": METRIC,
@@ -481,6 +634,7 @@ def main() -> int:
             "block_size": S, "layout": args.layout, "staging": args.staging,
             "tcmode": args.tcmode, "schedule": args.schedule, "block_colouring": args.bcol,
             "edges_per_lane": args.ept,
+            "gather": args.gather if args.schedule == "dataflow" else "registers",
             "parallelism": "none (one GPU)",
         },
         "useful_gbps": useful / sec / 1e9,
@@ -493,11 +647,16 @@ def main() -> int:
                      "avg_launch_us": avg_launch_s * 1e6,
                      "avg_launch_us_event_pairs": kern_ms / n_launch * 1e3,
                      "bytes_per_launch": bytes_per_launch},
+        "roofline_cold": {"bound": "hbm", "achieved": cold_achieved,
+                          "peak": measure.HBM_PEAK_GBPS, "unit": "GB/s", "frac": cold_frac,
+                          "us_per_step": cold_s * 1e6,
+                          "how": "1 GiB fill before every sweep, events around the sweep only"},
         "cpu_baseline": cpu,
         "baselines": baselines,
         "variants": variants,
         "extras": extras,
         "ablations": ablations,
+        "sweep_1200x600": sweep,
         "plan": {k: st[k] for k in ("n_blocks", "n_block_colours", "max_thread_colours",
                                      "avg_thread_colours", "reuse_factor", "lds_bytes_max",
                                      "staged_points", "plan_device_bytes", "build_seconds")},

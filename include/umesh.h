@@ -45,10 +45,11 @@
 extern "C" {
 #endif
 
-#define UMESH_ABI_VERSION 1
+#define UMESH_ABI_VERSION 2
 
 typedef struct um_ctx_s *um_ctx;
 typedef struct um_plan_s *um_plan;
+typedef struct um_graph_s *um_graph;
 
 typedef enum {
     UM_OK = 0,
@@ -116,12 +117,21 @@ typedef enum { UM_BCOL_FIRST_FIT = 0, UM_BCOL_RECOLOUR = 1, UM_BCOL_MIN = 2 } um
  * with colour launches; results agree to rounding (the two kernels may pair
  * multiply-adds into FMAs differently) and each schedule is bitwise
  * reproducible from run to run.
- * A wait that exceeds a time limit sets the plan's error count instead of
- * hanging (um_plan_errors).  Each block's flag counts the executions it has
+ * A wait that exceeds a time limit counts an error of the plan instead of
+ * hanging (um_plan_errors, um_plan_set_wait_limit).  Each block's flag counts the executions it has
  * completed (all flags advance together), so the launch needs no host-side
  * counter and may be captured in a HIP graph and replayed.  Supported for STAGE_ALL with one or two
  * elements per lane; a plan must not execute concurrently with itself. */
 typedef enum { UM_SCHED_COLOUR_LAUNCHES = 0, UM_SCHED_DATAFLOW = 1 } um_schedule;
+/* How a DATAFLOW block of the edge loop moves its staged data from HBM to
+ * LDS (Section 2.2's gather step).  REGISTERS: each lane loads a staged
+ * point's values into registers and stores them to LDS.  LDS_DMA: the loads
+ * write LDS directly (gfx950 buffer/global loads with the LDS bit, 4- and
+ * 16-byte per lane), no registers hold staged data, and the residuals are
+ * fetched in the same round trip as q, adt and x whenever the block's
+ * earlier-coloured neighbours have already published (their flags are read
+ * at the block's start); AoS data only. */
+typedef enum { UM_GATHER_REGISTERS = 0, UM_GATHER_LDS_DMA = 1 } um_gather;
 
 /* Elemental kernels compiled into the library (no run-time code generation).
  *
@@ -286,7 +296,14 @@ typedef struct {
                                   every block reads its explicit id list     */
     int32_t block_colouring;   /* HIER: um_bcolouring                        */
     int32_t schedule;          /* HIER: um_schedule                          */
-    int32_t reserved[1];
+    int32_t gather;            /* HIER, DATAFLOW: um_gather                  */
+    int32_t wave_colour_groups;/* HIER: 1 = pad each thread-colour group of a
+                                  block to whole 64-lane wavefronts, so that
+                                  every wavefront holds one colour and takes
+                                  part in one colour round only (more lanes
+                                  per block: UM_ERR_ARG when the padded slots
+                                  exceed 1024 * elems_per_thread)           */
+    int32_t reserved[2];
 } um_plan_opts;
 
 typedef struct {
@@ -314,8 +331,10 @@ typedef enum {
     UM_EXP_BLOCK_OFFSETS = 0,   /* int32[n_blocks+1]: element ranges, block id order */
     UM_EXP_BLOCK_COLOURS = 1,   /* int32[n_blocks]                                   */
     UM_EXP_THREAD_COLOURS = 2,  /* int32[n_elements]: thread colour per element     */
-    UM_EXP_SLOT_ELEMENTS = 3,   /* int32[n_elements]: element executed at each slot;
-                                   slots are grouped by block in launch order        */
+    UM_EXP_SLOT_ELEMENTS = 3,   /* int32[n_slots]: element executed at each slot,
+                                   -1 for an empty slot (wave-pure colour groups);
+                                   slots are grouped by block in launch order;
+                                   n_slots = n_elements without padding          */
     UM_EXP_GLOBAL_COLOURS = 4,  /* int32[n_elements]: global colour per element      */
     UM_EXP_STAGED_OFFSETS_A = 5,/* int32[n_blocks+1]: staged points of the read-only
                                    indirect map (edge->node for LF2D; none for the
@@ -324,7 +343,7 @@ typedef enum {
     UM_EXP_STAGED_OFFSETS_B = 7,/* as above for the INC map (edge->cell for LF2D,
                                    element->node for the hex loop)                   */
     UM_EXP_STAGED_POINTS_B = 8,
-    UM_EXP_LOCAL_INDEX = 9,     /* int32[n_elements][k]: per slot, local staged index;
+    UM_EXP_LOCAL_INDEX = 9,     /* int32[n_slots][k]: per slot, local staged index;
                                    LF2D k = 4: (B slot 0, B slot 1, A slot 0, A slot 1);
                                    hex k = 8: B slots 0..7                           */
     UM_EXP_BLOCK_ORDER = 10,    /* int32[n_blocks]: block id at each launch position  */
@@ -333,7 +352,10 @@ typedef enum {
                                    a block with none reads its explicit list        */
     UM_EXP_RUNS_A = 12,         /* int32[...][2]: (first point id, staged position)  */
     UM_EXP_RUN_OFFSETS_B = 13,  /* as above for the INC map                          */
-    UM_EXP_RUNS_B = 14
+    UM_EXP_RUNS_B = 14,
+    UM_EXP_PRED_OFFSETS = 15,   /* DATAFLOW: int32[n_blocks+1], launch position order:
+                                   the blocks each position waits for              */
+    UM_EXP_PREDS = 16           /* DATAFLOW: int32[...]: their launch positions      */
 } um_export_field;
 
 /* ---------------------------------------------------------------- context */
@@ -370,16 +392,23 @@ um_status um_decl_map(um_ctx ctx, int32_t from_set, int32_t to_set, int32_t arit
                       const int32_t *host_table, int32_t *map_id);
 
 /* Declare a dat of `dim` (1..16) values of type `dtype` per element of
- * `set`, stored at device address `device_ptr` with `layout`, in the sets'
- * current numbering.  The memory stays owned by the caller and must outlive
- * all work that uses it.  device_ptr may be NULL on a host-only context. */
+ * `set` (a dat of Section 1.1.1), stored at device address `device_ptr` with
+ * `layout`, in the sets' current numbering.  The memory stays owned by the
+ * caller and must outlive all work that uses it.  device_ptr may be NULL on
+ * a host-only context.  The kernels use vector accesses, so device_ptr must
+ * be aligned: AoS records of a multiple of 16 bytes to 16, of 8 bytes to 8,
+ * otherwise (and SoA) to the value size.  A dat a loop increments must not
+ * share memory with a dat the same loop reads (checked when a plan is built
+ * and at every execution).  Errors: UM_ERR_ARG (bad set, dim, dtype, layout,
+ * null dat_id, misaligned pointer). */
 um_status um_decl_dat(um_ctx ctx, int32_t set, int32_t dim, int32_t dtype, int32_t layout,
                       void *device_ptr, int32_t *dat_id);
 
 /* Point an existing dat at another device buffer of the same shape
  * (size(set) * dim values of the dat's dtype in its layout: the caller's
  * guarantee, not checked).  Plans built earlier use the new buffer from
- * their next execution on.  Errors: UM_ERR_ARG for a bad dat id. */
+ * their next execution on.  Errors: UM_ERR_ARG for a bad dat id or a
+ * misaligned pointer (as um_decl_dat). */
 um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr);
 
 /* ------------------------------------------------------------- reordering */
@@ -504,9 +533,25 @@ um_status um_plan_autotune(um_ctx ctx, int32_t kernel, const um_arg *args, int32
 um_status um_plan_set_timing(um_plan plan, int32_t enable);
 
 /* Synchronise the device and return in *n_errors the number of block
- * waits of a DATAFLOW plan that gave up on a neighbour (any non-zero count
- * makes every later result of the plan invalid); 0 for other plans. */
+ * waits of a DATAFLOW plan that gave up on a neighbour since the plan was
+ * built or um_plan_reset_errors was last called; 0 for other plans.  An
+ * execution in which a wait gave up has read and written its increment
+ * targets without ordering, so its results (and every result accumulated
+ * on them afterwards) are invalid; the waits of later executions are not
+ * affected (each execution has its own epoch).  Errors: UM_ERR_ARG for a
+ * null output, UM_ERR_HIP. */
 um_status um_plan_errors(um_plan plan, int32_t *n_errors);
+
+/* Synchronise the device and set the plan's count of given-up waits back
+ * to zero.  No-op for plans other than DATAFLOW. */
+um_status um_plan_reset_errors(um_plan plan);
+
+/* Longest time a DATAFLOW block waits for one neighbour before it gives up
+ * and counts an error, in ticks of the GPU's 100 MHz real-time counter;
+ * 0 restores the default (20,000,000 = 0.2 s).  A limit far below a
+ * block's run time makes waits give up on purpose (a test of the error
+ * path; the kernels always exit).  Errors: UM_ERR_ARG for ticks < 0. */
+um_status um_plan_set_wait_limit(um_plan plan, int64_t ticks);
 /* See um_plan_set_timing: waits for the recorded event pairs, returns their
  * summed time and count, and resets.  Errors: UM_ERR_ARG for null outputs. */
 um_status um_plan_timing(um_plan plan, double *ms_total, int64_t *n_launches);
@@ -518,6 +563,26 @@ um_status um_plan_timing(um_plan plan, double *ms_total, int64_t *n_launches);
  * sequential evaluation of the same formula.  Asynchronous on `stream`. */
 um_status um_debug_fluxes(um_plan plan, const double *params, int32_t nparams, void *f_out,
                           void *stream);
+
+/* ------------------------------------------------------------ HIP graphs */
+
+/* Capture of the library's launches into a HIP graph, so that a time step of
+ * several loops (the batched and time-step loops of Section 3.1.1's solver
+ * structure) is replayed with one graph launch.  Between um_graph_begin and
+ * um_graph_end on a capturing `stream` (a hipStream_t other than the NULL
+ * stream), um_loop_exec on that stream records its kernels instead of
+ * running them; nothing else may be enqueued on the stream meanwhile, and a
+ * DATAFLOW plan's epochs advance once per replay as with eager executions.
+ * Plan timing (um_plan_set_timing) must be off while capturing.  The graph
+ * refers to the plans and dats by address: they must outlive it.
+ * Errors: UM_ERR_ARG (NULL stream, null output), UM_ERR_HIP. */
+um_status um_graph_begin(void *stream);
+/* End the capture on `stream` and instantiate it; *out receives the graph. */
+um_status um_graph_end(void *stream, um_graph *out);
+/* Enqueue one replay of `graph` on `stream` (NULL = default stream). */
+um_status um_graph_launch(um_graph graph, void *stream);
+/* Release the graph (NULL accepted); replays already enqueued complete. */
+um_status um_graph_destroy(um_graph graph);
 
 #ifdef __cplusplus
 }

@@ -55,6 +55,11 @@ def lib():
         L.oracle_first_fit.argtypes = [ct.c_int64, P, P, ct.c_int64, ct.c_int32,
                                        P, P, P, P, P]
         L.oracle_first_fit.restype = ct.c_int32
+        L.oracle_omp_threads.argtypes = []
+        L.oracle_omp_threads.restype = ct.c_int32
+        L.oracle_edge_loop_coloured.argtypes = [ct.c_int32, P, P, P, P, P, P, P, ct.c_double,
+                                                ct.c_double, P]
+        L.oracle_edge_loop_coloured.restype = None
         _lib = L
     return _lib
 
@@ -116,6 +121,37 @@ def first_fit(off, pts, npts: int, max_colours: int = 1 << 20):
     if nc < 0:
         return None, -1
     return colour, int(nc)
+
+
+def omp_threads() -> int:
+    """Threads the colour-parallel loop uses (OMP_NUM_THREADS, else all cores)."""
+    return int(lib().oracle_omp_threads())
+
+
+def colour_groups(e2c):
+    """First-fit global colouring of the edges (conflict: a shared cell) and
+    the edges grouped by colour: (ncol, col_off[ncol+1] int64, order int32)."""
+    e2c = _c(e2c, np.int32)
+    E = e2c.shape[0]
+    off = np.arange(0, 2 * E + 1, 2, dtype=np.int64)
+    col, ncol = first_fit(off, e2c.reshape(-1), int(e2c.max()) + 1 if E else 0)
+    order = np.argsort(col, kind="stable").astype(np.int32)
+    col_off = np.zeros(ncol + 1, np.int64)
+    np.cumsum(np.bincount(col, minlength=ncol), out=col_off[1:])
+    return ncol, col_off, order
+
+
+def edge_loop_coloured(groups, e2n, e2c, x, q, adt, gm1=GM1, eps=EPS_D, res=None):
+    """The edge loop on all host cores: one OpenMP parallel loop per colour
+    of `groups` (from colour_groups)."""
+    ncol, col_off, order = groups
+    e2n = _c(e2n, np.int32); e2c = _c(e2c, np.int32)
+    x = _c(x, np.float64); q = _c(q, np.float64); adt = _c(adt, np.float64)
+    res = np.zeros((q.shape[0], 4)) if res is None else res
+    lib().oracle_edge_loop_coloured(int(ncol), _p(_c(col_off, np.int64)), _p(_c(order, np.int32)),
+                                    _p(e2n), _p(e2c), _p(x), _p(q), _p(adt), float(gm1),
+                                    float(eps), _p(res))
+    return res
 
 
 def edge_loop_f32(e2n, e2c, x, q, adt, gm1=GM1, eps=EPS_D):

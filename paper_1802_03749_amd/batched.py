@@ -13,8 +13,8 @@ next step's adt as one fused cell loop) on every mesh of a batch:
   once per size bucket (meshes whose edge counts share a power of two) on
   the bucket's first mesh and reused for the rest of the bucket.
 
-Either executor can capture its whole step in a HIP graph
-(torch.cuda.CUDAGraph) and replay it.  Marshalling and host policy only:
+Either executor can capture its whole step in a HIP graph (the library's
+capture entry points) and replay it.  Marshalling and host policy only:
 every loop runs in the library.
 """
 from __future__ import annotations
@@ -24,6 +24,7 @@ import math
 import numpy as np
 import torch
 
+from . import umesh as U
 from .timestep import TimeStep2D
 
 # block sizes are multiples of the default partition block (512), so every
@@ -104,16 +105,42 @@ class BatchedSteps:
             ts.rms.zero_()
 
     def capture(self) -> None:
-        """Capture one step of every mesh in a HIP graph."""
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self.step(torch.cuda.current_stream().cuda_stream)
-        torch.cuda.synchronize()
-        self.graph = g
+        """Capture one step of every mesh in a HIP graph (the library's own
+        capture entry points, on a side stream).  With fused plans the graph
+        holds the fused sequence (edge flux, boundary flux, update + adt):
+        a mesh whose adt is not valid yet gets its adt loop run eagerly
+        first, which leaves the state unchanged."""
+        self._drop_graph()
+        cur = torch.cuda.current_stream()
+        for ts in self.steps:
+            if ts.fused and not ts.adt_valid:
+                ts.run_loop("adt", cur.cuda_stream)
+                ts.adt_valid = True
+        self.graph = U.HipGraph(self.step)
 
     def replay(self) -> None:
         self.graph.replay()
+
+    def invalidate_adt(self) -> None:
+        """Declare adt stale after the state was written outside step() or
+        replay().  With a captured graph (which holds no adt loop) the adt
+        loops run eagerly now, before the next replay; otherwise the next
+        eager step starts with them."""
+        cur = torch.cuda.current_stream().cuda_stream
+        for ts in self.steps:
+            if self.graph is not None and ts.fused:
+                ts.run_loop("adt", cur)
+            else:
+                ts.invalidate_adt()
+
+    def check_errors(self) -> None:
+        for ts in self.steps:
+            ts.check_errors()
+
+    def _drop_graph(self) -> None:
+        if self.graph is not None:
+            self.graph.close()
+            self.graph = None
 
     def q_user(self):
         """Per mesh, the state in the caller's numbering."""
@@ -127,6 +154,6 @@ class BatchedSteps:
         return float(sum(ts.rms.item() for ts in self.steps))
 
     def close(self) -> None:
-        self.graph = None
+        self._drop_graph()
         for ts in self.steps:
             ts.close()

@@ -13,6 +13,10 @@
 
 struct um_ctx_s : um::Ctx {};
 struct um_plan_s : um::Plan {};
+struct um_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 namespace um {
 
@@ -76,13 +80,48 @@ T *upload(const std::vector<T> &v, int64_t &bytes) {
 }
 
 void free_device_plan(Plan &p) {
-    void *bufs[12] = {p.dp.emap, p.dp.binfo,    p.dp.stg_c, p.dp.stg_n, p.dp.loc,   p.dp.crun,
-                      p.dp.nrun, p.dp.pred_off, p.dp.preds, p.dp.flags, p.dp.err, p.dp.partials};
+    void *bufs[13] = {p.dp.emap,  p.dp.binfo, p.dp.stg_c,    p.dp.stg_n, p.dp.loc,
+                      p.dp.crun,  p.dp.nrun,  p.dp.pred_off, p.dp.preds, p.dp.preds8,
+                      p.dp.flags, p.dp.err,   p.dp.partials};
     for (void *b : bufs)
         if (b) hipFree(b);
     p.dp = DevicePlan{};
     for (void *e : p.events) hipEventDestroy(static_cast<hipEvent_t>(e));
     p.events.clear();
+}
+
+// The kernels move a dat's elements with vector accesses: an AoS element of
+// dim * size bytes with 16-byte (or, for 8-byte records, 8-byte) loads, an SoA
+// component one value at a time.  A pointer must be aligned to that width.
+void check_dat_alignment(const Dat &d, const void *ptr) {
+    const int64_t esize = d.dtype == UM_F64 ? 8 : 4;
+    int64_t align = esize;
+    if (d.layout == UM_AOS) {
+        const int64_t rec = esize * d.dim;
+        align = rec % 16 == 0 ? 16 : rec % 8 == 0 ? 8 : esize;
+    }
+    if (reinterpret_cast<uintptr_t>(ptr) % uintptr_t(align) != 0)
+        fail(UM_ERR_ARG, "dat pointer %p is not aligned to %lld bytes (dim %d, %s, %s)", ptr,
+             (long long)align, d.dim, d.dtype == UM_F64 ? "f64" : "f32",
+             d.layout == UM_AOS ? "AoS" : "SoA");
+}
+
+int64_t dat_bytes(const Ctx &c, const Dat &d) {
+    return c.sets[d.set].size * d.dim * (d.dtype == UM_F64 ? 8 : 4);
+}
+
+// An incremented dat must not share memory with a dat the loop reads: the
+// kernels read those through non-aliasing (restrict) pointers.
+void check_no_overlap(const Ctx &c, int32_t inc, const int32_t *reads, int n, const char *what) {
+    const Dat &w = c.dats[inc];
+    for (int i = 0; i < n; ++i) {
+        if (reads[i] == inc) fail(UM_ERR_ARG, "%s: the incremented dat is also read", what);
+        const Dat &r = c.dats[reads[i]];
+        if (!w.ptr || !r.ptr) continue;
+        const char *a = static_cast<const char *>(w.ptr), *b = static_cast<const char *>(r.ptr);
+        if (a < b + dat_bytes(c, r) && b < a + dat_bytes(c, w))
+            fail(UM_ERR_ARG, "%s: the incremented dat overlaps a dat the loop reads", what);
+    }
 }
 
 // LF2D argument pattern (umesh.h, UM_K_EDGE_FLUX_LF2D).
@@ -131,6 +170,8 @@ EdgeArgs check_lf2d_args(const Ctx &ctx, const um_arg *args, int32_t nargs, int3
         fail(UM_ERR_UNSUPPORTED, "edge flux kernel: x, q and adt must share one dtype");
     if (ctx.dats[ea.dat_res].dtype != UM_F64)
         fail(UM_ERR_UNSUPPORTED, "edge flux kernel: res must be UM_F64");
+    const int32_t reads[3] = {ea.dat_x, ea.dat_q, ea.dat_adt};
+    check_no_overlap(ctx, ea.dat_res, reads, 3, "edge flux kernel");
     return ea;
 }
 
@@ -164,6 +205,8 @@ HexArgs check_hex_args(const Ctx &ctx, const um_arg *args, int32_t nargs, int32_
     ha.dat_v = args[1].dat;
     ha.dat_f = args[2].dat;
     ha.layout = ctx.dats[ha.dat_x].layout;
+    const int32_t reads[2] = {ha.dat_x, ha.dat_v};
+    check_no_overlap(ctx, ha.dat_f, reads, 2, "hex kernel");
     return ha;
 }
 
@@ -187,6 +230,10 @@ LaunchArgs launch_args_hex(Plan &p, const double *params, int32_t nparams, void 
     const Dat &x = ctx.dats[p.ha.dat_x], &v = ctx.dats[p.ha.dat_v], &f = ctx.dats[p.ha.dat_f];
     if (ctx.sets[p.iter_set].size > 0 && (!x.ptr || !v.ptr || !f.ptr))
         fail(UM_ERR_STATE, "a dat of the loop has no device memory");
+    {
+        const int32_t reads[2] = {p.ha.dat_x, p.ha.dat_v};
+        check_no_overlap(ctx, p.ha.dat_f, reads, 2, "hex kernel");
+    }
     la.x = x.ptr;
     la.q = v.ptr;
     la.res = static_cast<double *>(f.ptr);
@@ -195,8 +242,11 @@ LaunchArgs launch_args_hex(Plan &p, const double *params, int32_t nparams, void 
     la.schedule = p.hp.schedule;
     la.pred_off = p.dp.pred_off;
     la.preds = p.dp.preds;
+    la.preds8 = p.dp.preds8;
+    la.gather = p.hp.gather;
     la.flags = p.dp.flags;
     la.err = p.dp.err;
+    la.wait_ticks = p.wait_ticks;
     return la;
 }
 
@@ -262,13 +312,17 @@ LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *str
     la.crun = p.dp.crun;
     la.nrun = p.dp.nrun;
     la.loc = p.dp.loc;
-    la.n_slots = p.hp.n_elem;
+    la.n_slots = p.hp.n_slots;
     la.emap = p.dp.emap;
     const Dat &x = ctx.dats[p.ea.dat_x], &q = ctx.dats[p.ea.dat_q];
     const Dat &adt = ctx.dats[p.ea.dat_adt], &res = ctx.dats[p.ea.dat_res];
     const int64_t E = ctx.sets[p.iter_set].size;
     if (E > 0 && (!x.ptr || !q.ptr || !adt.ptr || !res.ptr))
         fail(UM_ERR_STATE, "a dat of the loop has no device memory");
+    {
+        const int32_t reads[3] = {p.ea.dat_x, p.ea.dat_q, p.ea.dat_adt};
+        check_no_overlap(ctx, p.ea.dat_res, reads, 3, "edge flux kernel");
+    }
     la.dtype = p.ea.dtype;
     la.x = x.ptr;
     la.q = q.ptr;
@@ -281,8 +335,11 @@ LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *str
     la.schedule = p.hp.schedule;
     la.pred_off = p.dp.pred_off;
     la.preds = p.dp.preds;
+    la.preds8 = p.dp.preds8;
+    la.gather = p.hp.gather;
     la.flags = p.dp.flags;
     la.err = p.dp.err;
+    la.wait_ticks = p.wait_ticks;
     return la;
 }
 
@@ -405,6 +462,7 @@ um_status um_decl_dat(um_ctx ctx, int32_t set, int32_t dim, int32_t dtype, int32
         d.dim = dim;
         d.dtype = dtype;
         d.layout = layout;
+        check_dat_alignment(d, device_ptr);
         d.ptr = device_ptr;
         c.dats.push_back(d);
         *dat_id = int32_t(c.dats.size()) - 1;
@@ -415,6 +473,7 @@ um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr) {
     return guarded([&] {
         Ctx &c = need(ctx);
         if (dat < 0 || dat >= int32_t(c.dats.size())) fail(UM_ERR_ARG, "bad dat id %d", dat);
+        check_dat_alignment(c.dats[dat], device_ptr);
         c.dats[dat].ptr = device_ptr;
     });
 }
@@ -524,6 +583,13 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
             fail(UM_ERR_ARG, "bad block_colouring %d", o.block_colouring);
         if (o.schedule != UM_SCHED_COLOUR_LAUNCHES && o.schedule != UM_SCHED_DATAFLOW)
             fail(UM_ERR_ARG, "bad schedule %d", o.schedule);
+        if (o.gather != UM_GATHER_REGISTERS && o.gather != UM_GATHER_LDS_DMA)
+            fail(UM_ERR_ARG, "bad gather %d", o.gather);
+        if (o.wave_colour_groups != 0 && o.wave_colour_groups != 1)
+            fail(UM_ERR_ARG, "wave_colour_groups must be 0 or 1");
+        if (o.wave_colour_groups != 0 &&
+            (kernel != UM_K_EDGE_FLUX_LF2D || o.strategy != UM_STRAT_HIER))
+            fail(UM_ERR_UNSUPPORTED, "wave-pure colour groups: HIER plans of the edge loop only");
         const auto t0 = std::chrono::steady_clock::now();
         auto *p = new um_plan_s();
         p->ctx = &c;
@@ -532,11 +598,21 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
         try {
             if (kernel == UM_K_EDGE_FLUX_LF2D) {
                 p->ea = check_lf2d_args(c, args, nargs, iter_set);
+                if (o.gather == UM_GATHER_LDS_DMA &&
+                    (o.strategy != UM_STRAT_HIER || o.schedule != UM_SCHED_DATAFLOW ||
+                     p->ea.layout != UM_AOS))
+                    fail(UM_ERR_UNSUPPORTED,
+                         "LDS-DMA gather: HIER plans with the DATAFLOW schedule on AoS data only");
                 build_host_plan(c, p->ea, iter_set, o, p->hp);
+                p->hp.gather = o.gather;
             } else if (is_step_kernel(kernel)) {
+                if (o.gather != UM_GATHER_REGISTERS)
+                    fail(UM_ERR_UNSUPPORTED, "LDS-DMA gather: edge flux loop only");
                 p->sa = check_step_args(c, kernel, args, nargs, iter_set);
                 build_host_plan_step(c, kernel, p->sa, iter_set, o, p->hp);
             } else {
+                if (o.gather != UM_GATHER_REGISTERS)
+                    fail(UM_ERR_UNSUPPORTED, "LDS-DMA gather: edge flux loop only");
                 p->ha = check_hex_args(c, args, nargs, iter_set);
                 build_host_plan_hex(c, p->ha, iter_set, o, p->hp);
             }
@@ -553,6 +629,7 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
                 if (p->hp.schedule == UM_SCHED_DATAFLOW && !p->hp.binfo.empty()) {
                     p->dp.pred_off = upload(p->hp.pred_off, bytes);
                     p->dp.preds = upload(p->hp.preds, bytes);
+                    p->dp.preds8 = upload(p->hp.preds8, bytes);
                     std::vector<int32_t> zeros(p->hp.binfo.size(), 0);
                     p->dp.flags = upload(zeros, bytes);
                     std::vector<int32_t> ctl(4, 0);
@@ -680,6 +757,11 @@ um_status um_plan_export(um_plan plan, int32_t field, int32_t *host_out, int64_t
         case UM_EXP_BLOCK_COLOURS: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); v = &hp.blk_colour; break;
         case UM_EXP_THREAD_COLOURS: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); v = &hp.tcol; break;
         case UM_EXP_BLOCK_ORDER: if (!hier) fail(UM_ERR_STATE, "not a HIER plan"); v = &hp.blk_order; break;
+        case UM_EXP_PRED_OFFSETS:
+        case UM_EXP_PREDS:
+            if (!hier || hp.schedule != UM_SCHED_DATAFLOW) fail(UM_ERR_STATE, "not a DATAFLOW plan");
+            v = field == UM_EXP_PREDS ? &hp.preds : &hp.pred_off;
+            break;
         case UM_EXP_SLOT_ELEMENTS:
             if (hp.strategy == UM_STRAT_ATOMIC) fail(UM_ERR_STATE, "atomic plans run elements in order");
             v = &hp.slot_elem;
@@ -704,10 +786,10 @@ um_status um_plan_export(um_plan plan, int32_t field, int32_t *host_out, int64_t
                     }
                 break;
             }
-            tmp.resize(4 * hp.n_elem);
-            for (int64_t s = 0; s < hp.n_elem; ++s) {
+            tmp.resize(4 * hp.n_slots);
+            for (int64_t s = 0; s < hp.n_slots; ++s) {
                 const uint32_t a = hp.loc[s];
-                const uint32_t h = (hp.loc[hp.n_elem + s / 2] >> (16 * (s & 1))) & 0xFFFFu;
+                const uint32_t h = (hp.loc[hp.n_slots + s / 2] >> (16 * (s & 1))) & 0xFFFFu;
                 tmp[4 * s] = int32_t(a & 0x7FFu);
                 tmp[4 * s + 1] = int32_t((a >> 11) & 0x7FFu);
                 tmp[4 * s + 2] = int32_t(((a >> 22) & 0x3FFu) | ((h & 1u) << 10));
@@ -944,6 +1026,25 @@ um_status um_plan_errors(um_plan plan, int32_t *n_errors) {
     });
 }
 
+um_status um_plan_reset_errors(um_plan plan) {
+    return guarded([&] {
+        Plan &p = need(plan);
+        if (!p.dp.err) return;
+        DeviceGuard g(p.ctx->device);
+        UM_HIP(hipDeviceSynchronize());
+        const int32_t zero[2] = {0, 0};
+        UM_HIP(hipMemcpy(p.dp.err, zero, sizeof zero, hipMemcpyHostToDevice));
+    });
+}
+
+um_status um_plan_set_wait_limit(um_plan plan, int64_t ticks) {
+    return guarded([&] {
+        Plan &p = need(plan);
+        if (ticks < 0) fail(UM_ERR_ARG, "negative wait limit");
+        p.wait_ticks = ticks == 0 ? DEFAULT_WAIT_TICKS : uint64_t(ticks);
+    });
+}
+
 um_status um_debug_fluxes(um_plan plan, const double *params, int32_t nparams, void *f_out,
                           void *stream) {
     return guarded([&] {
@@ -981,6 +1082,49 @@ um_status um_debug_fluxes(um_plan plan, const double *params, int32_t nparams, v
         hipFree(d_em);
         if (err != hipSuccess || err2 != hipSuccess)
             fail(UM_ERR_HIP, "debug flux launch: %s", hipGetErrorString(err != hipSuccess ? err : err2));
+    });
+}
+
+um_status um_graph_begin(void *stream) {
+    return guarded([&] {
+        if (!stream) fail(UM_ERR_ARG, "the default (NULL) stream cannot be captured");
+        UM_HIP(hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeRelaxed));
+    });
+}
+
+um_status um_graph_end(void *stream, um_graph *out) {
+    return guarded([&] {
+        if (!stream || !out) fail(UM_ERR_ARG, "null stream or output");
+        *out = nullptr;
+        hipGraph_t g = nullptr;
+        UM_HIP(hipStreamEndCapture(static_cast<hipStream_t>(stream), &g));
+        if (!g) fail(UM_ERR_STATE, "capture produced no graph");
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            fail(UM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+        um_graph h = new um_graph_s;
+        h->graph = g;
+        h->exec = ex;
+        *out = h;
+    });
+}
+
+um_status um_graph_launch(um_graph graph, void *stream) {
+    return guarded([&] {
+        if (!graph) fail(UM_ERR_ARG, "null graph");
+        UM_HIP(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)));
+    });
+}
+
+um_status um_graph_destroy(um_graph graph) {
+    return guarded([&] {
+        if (!graph) return;
+        if (graph->exec) hipGraphExecDestroy(graph->exec);
+        if (graph->graph) hipGraphDestroy(graph->graph);
+        delete graph;
     });
 }
 

@@ -1,3 +1,5 @@
+// Device helpers shared by the hierarchical kernels.
+//
 // Staged point ids of a block inside the hierarchical kernels.  A block's
 // sorted staged list is stored either explicitly or, when it splits into few
 // runs of consecutive ids, as run descriptors (first id, first staged
@@ -46,6 +48,25 @@ struct StagedIds {
         return g;
     }
 };
+
+// Dataflow schedules: waits until the completion flag *fl holds `epoch`.
+// Gives up after `ticks` of s_memrealtime (100 MHz), or at once when another
+// wait of the same execution has given up (ctl[1] == epoch); a timeout adds
+// one to ctl[0] and records its epoch in ctl[1].  Each execution has its own
+// epoch, so a timeout never shortens the waits of a later execution.
+__device__ __forceinline__ void bounded_wait(const int32_t *fl, int32_t epoch, int32_t *ctl,
+                                             uint64_t ticks) {
+    const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        if (__hip_atomic_load(ctl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) break;
+        if (__builtin_amdgcn_s_memrealtime() - t_begin > ticks) {
+            __hip_atomic_fetch_add(ctl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(ctl + 1, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
 
 }  // namespace dev
 }  // namespace um

@@ -132,6 +132,7 @@ struct HostPlan {
     int32_t n_partials = 0;                    // UPDATE: workgroups of the first launch
     int32_t schedule = 0;                      // HIER: um_schedule
     int64_t n_elem = 0;
+    int64_t n_slots = 0;                       // HIER edge loop: slots incl. wave padding
     // GLOBAL_COLOUR / ATOMIC: packed (L, R, a, b) per slot, slot order
     std::vector<int32_t> emap;                 // [n_slots][4]
     std::vector<int32_t> colour_off;           // GLOBAL: [ncol + 1] slot ranges
@@ -150,6 +151,9 @@ struct HostPlan {
     std::vector<int32_t> tcol;                 // element -> thread colour
     std::vector<int64_t> lds_per_colour;       // max LDS bytes per block colour
     std::vector<int32_t> pred_off, preds;      // DATAFLOW: earlier neighbours per position
+    std::vector<int32_t> preds8;               // DATAFLOW: [nb][8] the first 8 of them
+    int32_t gather = 0;                        // HIER, DATAFLOW: um_gather
+    int32_t wave_groups = 0;                   // HIER: colour groups padded to waves
     int32_t max_tcol = 0;
     double avg_tcol = 0.0, reuse = 0.0;
     int64_t lds_max = 0, staged_total = 0;
@@ -185,11 +189,17 @@ struct DevicePlan {
     Run *crun = nullptr, *nrun = nullptr;
     uint32_t *loc = nullptr;
     int32_t *pred_off = nullptr, *preds = nullptr;  // DATAFLOW
+    int32_t *preds8 = nullptr;                      // DATAFLOW: [nb][8]
     int32_t *flags = nullptr;                       // DATAFLOW: completion epochs per block
-    int32_t *err = nullptr;                         // DATAFLOW: [timeouts, unused x3]
+    int32_t *err = nullptr;                         // DATAFLOW: [timeouts, epoch of the
+                                                    //  last timeout, unused x2]
     double *partials = nullptr;                     // UPDATE: one sum per workgroup
     int64_t bytes = 0;
 };
+
+// Longest a dataflow block waits for one neighbour: 0.2 s of the 100 MHz
+// s_memrealtime counter.
+constexpr uint64_t DEFAULT_WAIT_TICKS = 20000000ull;
 
 struct Plan {
     Ctx *ctx = nullptr;
@@ -201,6 +211,7 @@ struct Plan {
     HostPlan hp;
     DevicePlan dp;
     double build_seconds = 0.0;
+    uint64_t wait_ticks = DEFAULT_WAIT_TICKS;  // DATAFLOW wait limit
     bool timing = false;
     std::vector<void *> events;                // hipEvent_t pairs
     double timed_ms = 0.0;

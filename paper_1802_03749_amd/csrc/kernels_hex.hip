@@ -209,14 +209,13 @@ __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restr
 // covers whole lines of a run of consecutive nodes.
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 constexpr int HEX_CPOL_SC1 = 16;
-constexpr uint64_t HEX_FLOW_WAIT_TICKS = 20000000ull;  // s_memrealtime at 100 MHz: 0.2 s
 
 template <int LAYOUT, int TCMODE>
 __global__ __launch_bounds__(1024) void hex_flow_kernel(
     const BlockInfo *__restrict__ binfo, const int32_t *__restrict__ stg,
     const Run *__restrict__ runs, const uint4 *__restrict__ loc, HexDats d, double kappa,
     const int32_t *__restrict__ pred_off, const int32_t *__restrict__ preds, int32_t *flags,
-    int32_t *ctl) {
+    int32_t *ctl, uint64_t wait_ticks) {
     extern __shared__ double lds[];
     const int32_t pos = int32_t(blockIdx.x);
     const int32_t epoch =
@@ -286,15 +285,7 @@ __global__ __launch_bounds__(1024) void hex_flow_kernel(
     // wait for the earlier-coloured neighbours (np <= 64: first wavefront)
     if (tid < np) {
         const int32_t *fl = flags + preds[p0 + tid];
-        const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
-        while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-            if (__hip_atomic_load(ctl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-            if (__builtin_amdgcn_s_memrealtime() - t_begin > HEX_FLOW_WAIT_TICKS) {
-                __hip_atomic_fetch_add(ctl, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-        }
+        dev::bounded_wait(fl, epoch, ctl, wait_ticks);
     }
     __syncthreads();
 
@@ -431,7 +422,7 @@ hipError_t hex_launch_layout(const LaunchArgs &la, int which, int32_t begin, int
         if (ea != hipSuccess) return ea;
         hipLaunchKernelGGL(kern, dim3(end - begin), dim3(la.block_size), size_t(lds), la.stream,
                            la.binfo, la.stg_c, la.crun, reinterpret_cast<const uint4 *>(la.loc), d,
-                           kappa, la.pred_off, la.preds, la.flags, la.err);
+                           kappa, la.pred_off, la.preds, la.flags, la.err, la.wait_ticks);
         return hipGetLastError();
     }
     const int32_t n = end - begin;

@@ -99,6 +99,9 @@ __device__ __forceinline__ void put_cell(double *s_inc, Real *s_q, Real *s_adt, 
     }
 }
 
+// Colour code of an empty slot (padding of wave-pure colour groups).
+constexpr int EMPTY_SLOT = 15;
+
 // EPT = elements (edges) per lane: the workgroup has T lanes and handles a
 // block of up to EPT*T edges; lane l computes slots l, l+T, ...
 template <int LAYOUT, int STAGING, int TCMODE, int EPT, typename Real>
@@ -168,6 +171,7 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
         lL[j] = int(wa[j] & 0x7FFu);
         lR[j] = int((wa[j] >> 11) & 0x7FFu);
         col[j] = (tid + j * T) < ne ? int(wb[j] >> 12) : -1;
+        if (col[j] == EMPTY_SLOT) col[j] = -1;
         const int nA = int((wa[j] >> 22) | ((wb[j] & 1u) << 10));
         const int nB = int((wb[j] >> 1) & 0x7FFu);
 #pragma unroll
@@ -284,9 +288,6 @@ __device__ __forceinline__ void store4_dev(__amdgpu_buffer_rsrc_t r, int64_t C, 
     }
 }
 
-// Longest a block waits for one predecessor before giving up (s_memrealtime
-// ticks at 100 MHz: 0.2 s).
-constexpr uint64_t FLOW_WAIT_TICKS = 20000000ull;
 
 // DATAFLOW schedule: one launch over all blocks in colour order (position =
 // blockIdx.x).  Same per-block work as hier_kernel with STAGE_ALL and EPT
@@ -303,7 +304,11 @@ constexpr uint64_t FLOW_WAIT_TICKS = 20000000ull;
 // the polls precedes the device-scope residual loads.  Blocks are dispatched in increasing
 // blockIdx order and a block only waits for smaller positions, so every
 // awaited block is already running or finished; the wait is bounded in time
-// anyway and a timeout is counted in ctl[0] instead of hanging.
+// anyway (wait_ticks of s_memrealtime, 100 MHz) and a timeout is counted
+// instead of hanging: ctl[0] counts timeouts, ctl[1] holds the epoch of the
+// execution in which the last one happened, and the other waits of that
+// same execution then give up at once (a later execution has a larger epoch
+// and waits normally again).
 // Execution numbers: a block's flag holds the number of executions it has
 // completed, and every execution runs every block once, so all flags move
 // in lockstep; a block's epoch is its own flag + 1 and a predecessor is done
@@ -321,9 +326,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
     const int32_t *__restrict__ stg_n, const Run *__restrict__ crun, const Run *__restrict__ nrun,
     const uint32_t *__restrict__ loc, int64_t n_slots, Dats<Real> d, double gm1d, double epsd,
     const int32_t *__restrict__ pred_off, const int32_t *__restrict__ preds, int32_t *flags,
-    int32_t *ctl) {
+    int32_t *ctl, uint64_t wait_ticks) {
     extern __shared__ double lds[];
-    int32_t *err = ctl;
     const int32_t pos = int32_t(blockIdx.x);
     const int32_t epoch =
         __hip_atomic_load(flags + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
@@ -422,6 +426,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
         lL[j] = int(wa[j] & 0x7FFu);
         lR[j] = int((wa[j] >> 11) & 0x7FFu);
         col[j] = (tid + j * T) < ne ? int(wb[j] >> 12) : -1;
+        if (col[j] == EMPTY_SLOT) col[j] = -1;
 #pragma unroll
         for (int k = 0; k < 4; ++k) f[j][k] = Real(0);
         if (col[j] >= 0) {
@@ -458,15 +463,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
         // wait for the earlier-coloured neighbours
         if (tid < np) {
             const int32_t *fl = flags + preds[p0 + tid];
-            const uint64_t t_begin = __builtin_amdgcn_s_memrealtime();
-            while (__hip_atomic_load(fl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-                if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-                if (__builtin_amdgcn_s_memrealtime() - t_begin > FLOW_WAIT_TICKS) {
-                    __hip_atomic_fetch_add(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
+            dev::bounded_wait(fl, epoch, ctl, wait_ticks);
         }
         __syncthreads();
         // residuals as accumulators
@@ -528,6 +525,246 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
         }
     }
     // publish: every lane's stores complete, then one flag store
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(flags + pos, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// DATAFLOW schedule with the gather done by LDS DMA (UM_GATHER_LDS_DMA, AoS
+// data): the loads of the staged q, adt, x and residuals write LDS directly
+// (buffer loads with the LDS bit: lane i of a wavefront lands at the
+// wavefront's LDS base + i * size), so no registers hold staged data and the
+// block waits on memory once for all of it.  The block's order of work:
+//   1. scalar loads: block descriptor, predecessor count and (up to 8)
+//      predecessor positions;
+//   2. one round trip: the block's own flag (its epoch), the predecessors'
+//      flags (every wavefront reads them itself), the run descriptors of the
+//      staged lists and this lane's local index words;
+//   3. one round trip: q, adt and x of the staged points, and the staged
+//      cells' residuals when this wavefront saw every predecessor published
+//      in step 2 (the residual loads are issued after that observation);
+//   4. fluxes from LDS; a wavefront that was not ready polls its
+//      predecessors' flags now (bounded wait) and then fetches its cells'
+//      residuals;
+//   5. thread-colour rounds into the residual accumulators, write-back with
+//      device-scope stores, completion flag (as hier_flow_kernel).
+// LDS layout (each staged record split so that every DMA lands in 16-byte
+// lanes): residual accumulators as two arrays of (res0, res1) and (res2, res3)
+// pairs, then q (binary64: two arrays of pairs; binary32: one float4 array),
+// x (binary64: one array of pairs; binary32: two arrays of words), adt
+// (binary64: low and high words; binary32: one array).
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// (the builtin takes its size and cache policy as literal constants)
+template <int SIZE, int CPOL = 0>
+__device__ __forceinline__ void dma(__amdgpu_buffer_rsrc_t r, void *lds_wave_base, int32_t voff) {
+    static_assert((SIZE == 4 || SIZE == 16) && (CPOL == 0 || CPOL == CPOL_SC1));
+    lds_void_t *l = (lds_void_t *)lds_wave_base;
+    if constexpr (SIZE == 16 && CPOL == 0)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, l, 16, voff, 0, 0, 0);
+    else if constexpr (SIZE == 16)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, l, 16, voff, 0, 0, 16);
+    else if constexpr (CPOL == 0)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, l, 4, voff, 0, 0, 0);
+    else
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, l, 4, voff, 0, 0, 16);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void *p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, int32_t(bytes), 0x00020000);
+}
+
+template <int TCMODE, int EPT, typename Real>
+__global__ __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_dma_kernel(
+    const BlockInfo *__restrict__ binfo, const int32_t *__restrict__ stg_c,
+    const int32_t *__restrict__ stg_n, const Run *__restrict__ crun, const Run *__restrict__ nrun,
+    const uint32_t *__restrict__ loc, int64_t n_slots, Dats<Real> d, double gm1d, double epsd,
+    const int32_t *__restrict__ pred_off, const int32_t *__restrict__ preds,
+    const int32_t *__restrict__ preds8, int32_t *flags, int32_t *ctl, uint64_t wait_ticks) {
+    constexpr bool F64 = sizeof(Real) == 8;
+    extern __shared__ double lds[];
+    const int32_t pos = int32_t(blockIdx.x);
+    const Real gm1 = Real(gm1d), eps = Real(epsd);
+    const BlockInfo bi = binfo[pos], bn = binfo[pos + 1];
+    const int ne = bn.slot_off - bi.slot_off;
+    const int nc = bn.cell_off - bi.cell_off;
+    const int nn = bn.node_off - bi.node_off;
+    const int ncr = bn.crun_off - bi.crun_off, nnr = bn.nrun_off - bi.nrun_off;
+    const int p0 = pred_off[pos], np = pred_off[pos + 1] - p0;
+    const int tid = int(threadIdx.x), T = int(blockDim.x), lane = tid & 63;
+
+    // ---- round trip 1: flags, run descriptors, local index words
+    const int32_t epoch =
+        __hip_atomic_load(flags + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+    int32_t pr = 0;
+    if (np <= 8) {
+        const int32_t *__restrict__ p8 = preds8 + 8 * pos;
+        pr = p8[0];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) pr = lane == k ? p8[k] : pr;
+    } else if (lane < np) {
+        pr = preds[p0 + lane];
+    }
+    const int32_t pf = lane < np ? __hip_atomic_load(flags + pr, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                 : epoch;
+    StagedIds cell_id, node_id;
+    cell_id.init(crun, bi.crun_off, ncr, stg_c + bi.cell_off);
+    node_id.init(nrun, bi.nrun_off, nnr, stg_n + bi.node_off);
+    const uint16_t *__restrict__ loc16 = reinterpret_cast<const uint16_t *>(loc + n_slots);
+    uint32_t wa[EPT], wb[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int s = tid + j * T;
+        wa[j] = s < ne ? loc[bi.slot_off + s] : 0u;
+        wb[j] = s < ne ? uint32_t(loc16[bi.slot_off + s]) : 0u;
+    }
+    const bool ready = __all(pf == epoch);  // this wavefront's view
+
+    // LDS regions
+    double *r_lo = lds;                 // [nc] x (res0, res1)
+    double *r_hi = r_lo + 2 * nc;       // [nc] x (res2, res3)
+    Real *q_a = reinterpret_cast<Real *>(r_hi + 2 * nc);  // F64: [nc] x (q0, q1); F32: [nc] x q[4]
+    Real *q_b = q_a + 2 * nc;           // F64: [nc] x (q2, q3)
+    Real *x_a = q_a + 4 * nc;           // F64: [nn] x (x, y); F32: [nn] x
+    Real *x_b = x_a + nn;               // F32: [nn] y
+    uint32_t *adt_w = reinterpret_cast<uint32_t *>(x_a + 2 * nn);  // F64: [2][nc] words; F32: [nc]
+    const __amdgpu_buffer_rsrc_t rq = rsrc_of(d.q, 4 * sizeof(Real) * d.C);
+    const __amdgpu_buffer_rsrc_t ra = rsrc_of(d.adt, sizeof(Real) * d.C);
+    const __amdgpu_buffer_rsrc_t rx = rsrc_of(d.x, 2 * sizeof(Real) * d.N);
+    const __amdgpu_buffer_rsrc_t rres = res_rsrc(d.res, d.C);
+
+    // ---- round trip 2: staged data (and residuals when ready) into LDS
+    const int npass = nc > nn ? nc : nn;
+    for (int t0 = __builtin_amdgcn_readfirstlane(tid - lane); t0 < npass; t0 += T) {
+        const int t = t0 + lane;
+        if (t < nc) {
+            const int32_t g = cell_id(t);
+            if constexpr (F64) {
+                dma<16>(rq, q_a + 2 * t0, 32 * g);
+                dma<16>(rq, q_b + 2 * t0, 32 * g + 16);
+                dma<4>(ra, adt_w + t0, 8 * g);
+                dma<4>(ra, adt_w + nc + t0, 8 * g + 4);
+            } else {
+                dma<16>(rq, q_a + 4 * t0, 16 * g);
+                dma<4>(ra, adt_w + t0, 4 * g);
+            }
+            if (ready) {
+                dma<16, CPOL_SC1>(rres, r_lo + 2 * t0, 32 * g);
+                dma<16, CPOL_SC1>(rres, r_hi + 2 * t0, 32 * g + 16);
+            }
+        }
+        if (t < nn) {
+            const int32_t g = node_id(t);
+            if constexpr (F64) {
+                dma<16>(rx, x_a + 2 * t0, 16 * g);
+            } else {
+                dma<4>(rx, x_a + t0, 8 * g);
+                dma<4>(rx, x_b + t0, 8 * g + 4);
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    // ---- fluxes of this lane's edges from LDS into registers
+    int lL[EPT], lR[EPT], col[EPT];
+    Real f[EPT][4];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        lL[j] = int(wa[j] & 0x7FFu);
+        lR[j] = int((wa[j] >> 11) & 0x7FFu);
+        col[j] = (tid + j * T) < ne ? int(wb[j] >> 12) : -1;
+        if (col[j] == EMPTY_SLOT) col[j] = -1;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) f[j][k] = Real(0);
+        if (col[j] >= 0) {
+            const int nA = int((wa[j] >> 22) | ((wb[j] & 1u) << 10));
+            const int nB = int((wb[j] >> 1) & 0x7FFu);
+            Real qL[4], qR[4], aL, aR, xa0, xa1, xb0, xb1;
+            if constexpr (F64) {
+                const f64x2 l0 = *reinterpret_cast<const f64x2 *>(q_a + 2 * lL[j]);
+                const f64x2 l1 = *reinterpret_cast<const f64x2 *>(q_b + 2 * lL[j]);
+                const f64x2 r0 = *reinterpret_cast<const f64x2 *>(q_a + 2 * lR[j]);
+                const f64x2 r1 = *reinterpret_cast<const f64x2 *>(q_b + 2 * lR[j]);
+                qL[0] = l0.x; qL[1] = l0.y; qL[2] = l1.x; qL[3] = l1.y;
+                qR[0] = r0.x; qR[1] = r0.y; qR[2] = r1.x; qR[3] = r1.y;
+                aL = __builtin_bit_cast(double, uint64_t(adt_w[lL[j]]) |
+                                                    (uint64_t(adt_w[nc + lL[j]]) << 32));
+                aR = __builtin_bit_cast(double, uint64_t(adt_w[lR[j]]) |
+                                                    (uint64_t(adt_w[nc + lR[j]]) << 32));
+                const f64x2 xa = *reinterpret_cast<const f64x2 *>(x_a + 2 * nA);
+                const f64x2 xb = *reinterpret_cast<const f64x2 *>(x_a + 2 * nB);
+                xa0 = xa.x; xa1 = xa.y; xb0 = xb.x; xb1 = xb.y;
+            } else {
+                const float4 l = *reinterpret_cast<const float4 *>(q_a + 4 * lL[j]);
+                const float4 r = *reinterpret_cast<const float4 *>(q_a + 4 * lR[j]);
+                qL[0] = l.x; qL[1] = l.y; qL[2] = l.z; qL[3] = l.w;
+                qR[0] = r.x; qR[1] = r.y; qR[2] = r.z; qR[3] = r.w;
+                aL = __builtin_bit_cast(float, adt_w[lL[j]]);
+                aR = __builtin_bit_cast(float, adt_w[lR[j]]);
+                xa0 = x_a[nA]; xa1 = x_b[nA]; xb0 = x_a[nB]; xb1 = x_b[nB];
+            }
+            lf2d_flux(xa0, xa1, xb0, xb1, qL, qR, aL, aR, gm1, eps, f[j]);
+        }
+    }
+
+    // ---- a wavefront that was not ready waits for the earlier-coloured
+    // neighbours now, then fetches its cells' residuals
+    if (!ready) {
+        if (lane < np) dev::bounded_wait(flags + pr, epoch, ctl, wait_ticks);
+        for (int t0 = __builtin_amdgcn_readfirstlane(tid - lane); t0 < nc; t0 += T) {
+            const int t = t0 + lane;
+            if (t < nc) {
+                const int32_t g = cell_id(t);
+                dma<16, CPOL_SC1>(rres, r_lo + 2 * t0, 32 * g);
+                dma<16, CPOL_SC1>(rres, r_hi + 2 * t0, 32 * g + 16);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
+
+    // ---- thread-colour rounds into the accumulators
+    auto acc = [&](int l, int k) -> double * { return (k < 2 ? r_lo : r_hi) + 2 * l + (k & 1); };
+    if constexpr (TCMODE == UM_TC_BARRIER) {
+        const int ncol = bi.ncol;
+        for (int c = 0; c < ncol; ++c) {
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+                if (col[j] == c) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        lds_add(acc(lL[j], k), double(f[j][k]));
+                        lds_add(acc(lR[j], k), -double(f[j][k]));
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (col[j] >= 0) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    lds_add(acc(lL[j], k), double(f[j][k]));
+                    lds_add(acc(lR[j], k), -double(f[j][k]));
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- write-back: lane pairs store the two 16-byte halves of a cell
+    for (int u = tid; u < 2 * nc; u += T) {
+        const int t = u >> 1, h = u & 1;
+        const f64x2 v = *reinterpret_cast<const f64x2 *>((h ? r_hi : r_lo) + 2 * t);
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rres,
+                                               int32_t(32 * int64_t(cell_id(t)) + 16 * h), 0,
+                                               CPOL_SC1);
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (tid == 0) __hip_atomic_store(flags + pos, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -636,12 +873,33 @@ hipError_t launch_flow_one(const LaunchArgs &la, int32_t nblocks, int64_t lds,
     hipLaunchKernelGGL((hier_flow_kernel<LAYOUT, TC, EPT, Real>), dim3(nblocks),
                        dim3(la.block_size), size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n,
                        la.crun, la.nrun, la.loc, la.n_slots, d, la.gm1, la.eps, la.pred_off,
-                       la.preds, la.flags, la.err);
+                       la.preds, la.flags, la.err, la.wait_ticks);
+    return hipGetLastError();
+}
+
+template <int TC, int EPT, typename Real>
+hipError_t launch_dma_one(const LaunchArgs &la, int32_t nblocks, int64_t lds,
+                          const Dats<Real> &d) {
+    clear_stale_error();
+    const hipError_t ea =
+        allow_lds(reinterpret_cast<const void *>(hier_dma_kernel<TC, EPT, Real>), lds);
+    if (ea != hipSuccess) return ea;
+    hipLaunchKernelGGL((hier_dma_kernel<TC, EPT, Real>), dim3(nblocks), dim3(la.block_size),
+                       size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun,
+                       la.loc, la.n_slots, d, la.gm1, la.eps, la.pred_off, la.preds, la.preds8,
+                       la.flags, la.err, la.wait_ticks);
     return hipGetLastError();
 }
 
 template <int LAYOUT, int TC, typename Real>
 hipError_t launch_flow(const LaunchArgs &la, int32_t nblocks, int64_t lds, const Dats<Real> &d) {
+    if (la.gather == UM_GATHER_LDS_DMA) {
+        if constexpr (LAYOUT == UM_AOS) {
+            if (la.ept == 1) return launch_dma_one<TC, 1>(la, nblocks, lds, d);
+            if (la.ept == 2) return launch_dma_one<TC, 2>(la, nblocks, lds, d);
+        }
+        return hipErrorInvalidValue;
+    }
     if (la.ept == 1) return launch_flow_one<LAYOUT, TC, 1>(la, nblocks, lds, d);
     if (la.ept == 2) return launch_flow_one<LAYOUT, TC, 2>(la, nblocks, lds, d);
     return hipErrorInvalidValue;

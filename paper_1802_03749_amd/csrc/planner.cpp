@@ -394,6 +394,12 @@ int32_t plan_blocks(const Ctx &ctx, int32_t iter_set, const int32_t *wt, int ari
             if (hp.pred_off[pos + 1] - hp.pred_off[pos] > 64)
                 fail(UM_ERR_UNSUPPORTED, "dataflow schedule: block %d waits on more than 64 blocks", b);
         }
+        // the first 8 predecessors of every position in a fixed-size table,
+        // read by the block with scalar loads before anything else
+        hp.preds8.assign(size_t(nb) * 8, 0);
+        for (int32_t pos = 0; pos < nb; ++pos)
+            for (int32_t i = hp.pred_off[pos], k = 0; i < hp.pred_off[pos + 1] && k < 8; ++i, ++k)
+                hp.preds8[size_t(pos) * 8 + k] = hp.preds[i];
     }
 
     return nbcol;
@@ -412,6 +418,7 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     hp.tcmode = o.tcmode;
     hp.ept = o.elems_per_thread > 0 ? o.elems_per_thread : 1;
     hp.threads = ((o.block_size + hp.ept - 1) / hp.ept + 63) / 64 * 64;
+    hp.n_slots = E;
     auto pack = [&](int64_t e, int32_t *dst) {
         dst[0] = mc.table[2 * e];
         dst[1] = mc.table[2 * e + 1];
@@ -440,11 +447,20 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     // ---- per block in launch order: staged lists, layer 2 colouring, slots
     std::vector<int32_t> cloc(C, -1), nloc(ctx.sets[mn.to].size, -1);
     hp.binfo.resize(nb + 1);
-    // local index words: E 32-bit words (lL | lR << 11 | nA[0:10) << 22),
-    // then E 16-bit halves (nA >> 10 | nB << 1 | colour << 12), packed two
-    // per 32-bit word: 6 bytes per edge
-    hp.loc.assign(E + (E + 1) / 2, 0u);
-    hp.slot_elem.resize(E);
+    // local index words: one 32-bit word per slot (lL | lR << 11 |
+    // nA[0:10) << 22), then one 16-bit half per slot (nA >> 10 | nB << 1 |
+    // colour << 12), packed two per 32-bit word: 6 bytes per edge.  Colour
+    // code 15 marks an empty slot (padding of wave-pure colour groups), so a
+    // block may use at most 15 thread colours.
+    std::vector<uint32_t> words;
+    std::vector<uint16_t> halves;
+    words.reserve(E);
+    halves.reserve(E);
+    hp.slot_elem.clear();
+    hp.slot_elem.reserve(E);
+    const bool wave_groups = o.wave_colour_groups != 0;
+    hp.wave_groups = wave_groups ? 1 : 0;
+    int32_t max_slots = 0;
     hp.tcol.assign(E, 0);
     hp.stg_c.clear();
     hp.stg_n.clear();
@@ -488,8 +504,8 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
             const int64_t e = e0 + i;
             const int32_t lL = cloc[mc.table[2 * e]], lR = cloc[mc.table[2 * e + 1]];
             uint32_t taken = uint32_t(mask[lL]) | uint32_t(mask[lR]);
-            if ((taken & 0xFFFFu) == 0xFFFFu)
-                fail(UM_ERR_UNSUPPORTED, "block %d needs more than 16 thread colours", b);
+            if ((taken & 0x7FFFu) == 0x7FFFu)
+                fail(UM_ERR_UNSUPPORTED, "block %d needs more than 15 thread colours", b);
             int32_t c = __builtin_ctz(~taken);
             ecol[i] = c;
             mask[lL] |= 1 << c;
@@ -514,25 +530,50 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
         encode(hp.stg_n, n0, nn, hp.nrun, bi.nrun_off);
         tcol_sum += ncol;
         hp.max_tcol = std::max(hp.max_tcol, ncol);
-        // slots: the block's edges sorted by colour, stable
+        // slots: the block's edges sorted by colour, stable; with wave-pure
+        // groups every colour's run of slots is padded with empty slots to a
+        // multiple of 64, so that each wavefront's slots hold one colour
         order = counting_order(ecol, ncol, goff);
-        for (int32_t i = 0; i < ne; ++i) {
-            const int64_t e = e0 + order[i];
-            const uint32_t lL = cloc[mc.table[2 * e]], lR = cloc[mc.table[2 * e + 1]];
-            const uint32_t nA = nloc[mn.table[2 * e]], nB = nloc[mn.table[2 * e + 1]];
-            const uint32_t c = uint32_t(ecol[order[i]]);
-            hp.loc[slot] = lL | (lR << 11) | ((nA & 0x3FFu) << 22);
-            hp.loc[E + slot / 2] |= ((nA >> 10) | (nB << 1) | (c << 12)) << (16 * (slot & 1));
-            hp.slot_elem[slot] = int32_t(e);
-            hp.tcol[e] = int32_t(c);
-            ++slot;
+        const int64_t slot0 = slot;
+        for (int32_t c = 0; c < ncol; ++c) {
+            for (int32_t i = goff[c]; i < goff[c + 1]; ++i) {
+                const int64_t e = e0 + order[i];
+                const uint32_t lL = cloc[mc.table[2 * e]], lR = cloc[mc.table[2 * e + 1]];
+                const uint32_t nA = nloc[mn.table[2 * e]], nB = nloc[mn.table[2 * e + 1]];
+                words.push_back(lL | (lR << 11) | ((nA & 0x3FFu) << 22));
+                halves.push_back(uint16_t((nA >> 10) | (nB << 1) | (uint32_t(c) << 12)));
+                hp.slot_elem.push_back(int32_t(e));
+                hp.tcol[e] = c;
+                ++slot;
+            }
+            if (wave_groups)
+                for (; (slot - slot0) % 64 != 0; ++slot) {
+                    words.push_back(0u);
+                    halves.push_back(uint16_t(15u << 12));
+                    hp.slot_elem.push_back(-1);
+                }
         }
+        max_slots = std::max(max_slots, int32_t(slot - slot0));
         for (int32_t i = 0; i < nc; ++i) cloc[hp.stg_c[c0 + i]] = -1;
         for (int32_t i = 0; i < nn; ++i) nloc[hp.stg_n[n0 + i]] = -1;
         lds_all[pos] = lf2d_lds_bytes(UM_STAGE_ALL, ea.dtype, nc, nn);
     }
     hp.binfo[nb] = BlockInfo{int32_t(slot), int32_t(hp.stg_c.size()), int32_t(hp.stg_n.size()), 0,
                              int32_t(hp.crun.size()), int32_t(hp.nrun.size()), 0, 0};
+    hp.n_slots = slot;
+    if (slot > int64_t(INT32_MAX)) fail(UM_ERR_UNSUPPORTED, "too many slots");
+    hp.loc.assign(size_t(slot) + size_t(slot + 1) / 2, 0u);
+    std::copy(words.begin(), words.end(), hp.loc.begin());
+    for (int64_t i = 0; i < slot; ++i)
+        hp.loc[size_t(slot) + size_t(i / 2)] |= uint32_t(halves[i]) << (16 * (i & 1));
+    if (wave_groups) {
+        // lanes: enough for the largest padded block
+        hp.threads = ((max_slots + hp.ept - 1) / hp.ept + 63) / 64 * 64;
+        if (hp.threads > 1024)
+            fail(UM_ERR_ARG, "wave-pure colour groups need %d slots in a block: more than "
+                 "1024 lanes at %d elements per lane", max_slots, hp.ept);
+        hp.threads = std::max(hp.threads, 64);
+    }
 
     // ---- LDS sizing, with the increments-only fallback
     const int64_t limit = o.lds_limit_bytes > 0 ? o.lds_limit_bytes : ctx.lds_limit;
@@ -553,6 +594,10 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     if (hp.schedule == UM_SCHED_DATAFLOW && 32 * C > int64_t(INT32_MAX))
         fail(UM_ERR_UNSUPPORTED, "dataflow schedule addresses res with 32-bit byte offsets: "
              "at most %lld cells", (long long)(int64_t(INT32_MAX) / 32));
+    if (o.gather == UM_GATHER_LDS_DMA && hp.staging != UM_STAGE_ALL)
+        fail(UM_ERR_UNSUPPORTED, "LDS-DMA gather needs STAGE_ALL staging");
+    if (o.gather == UM_GATHER_LDS_DMA && 16 * ctx.sets[mn.to].size > int64_t(INT32_MAX))
+        fail(UM_ERR_UNSUPPORTED, "LDS-DMA gather addresses x with 32-bit byte offsets");
     if (hp.staging == UM_STAGE_INC_ONLY && need_inc > limit)
         fail(UM_ERR_LDS, "staging increments needs %lld bytes of LDS per block, limit %lld",
              (long long)need_inc, (long long)limit);

@@ -27,6 +27,7 @@ TCMODES = {"barrier": U.UM_TC_BARRIER, "lds_atomic": U.UM_TC_LDS_ATOMIC}
 BCOLOURING = {"first_fit": U.UM_BCOL_FIRST_FIT, "recolour": U.UM_BCOL_RECOLOUR,
               "min": U.UM_BCOL_MIN}
 SCHEDULES = {"colour_launches": U.UM_SCHED_COLOUR_LAUNCHES, "dataflow": U.UM_SCHED_DATAFLOW}
+GATHERS = {"registers": U.UM_GATHER_REGISTERS, "lds_dma": U.UM_GATHER_LDS_DMA}
 
 
 def parse_order(order: str):
@@ -176,7 +177,13 @@ class EdgeFluxLoop:
         self.res.zero_()
 
     def res_user(self) -> np.ndarray:
+        """res in user numbering; raises if a dataflow plan of this loop gave
+        up a wait (the results of that execution would be invalid)."""
+        self.check_errors()
         return self.to_user(self.res, self.s_cells)
+
+    def check_errors(self) -> None:
+        U.raise_on_plan_errors([p.handle for p in self._plans], "edge loop")
 
     # ---------------------------------------------------------------- plans
     def args(self):
@@ -190,7 +197,8 @@ class EdgeFluxLoop:
              tcmode: str = "barrier", max_block_colours: int = 256, lds_limit_bytes: int = 0,
              allow_fallback: bool = True, elems_per_thread: int = 1,
              explicit_lists: bool = False, block_colouring: str = "first_fit",
-             schedule: str = "colour_launches") -> Plan:
+             schedule: str = "colour_launches", gather: str = "registers",
+             wave_colour_groups: bool = False) -> Plan:
         o = U.um_plan_opts()
         o.strategy = STRATEGIES[strategy]
         o.block_size = block_size
@@ -203,6 +211,8 @@ class EdgeFluxLoop:
         o.explicit_lists = 1 if explicit_lists else 0
         o.block_colouring = BCOLOURING[block_colouring]
         o.schedule = SCHEDULES[schedule]
+        o.gather = GATHERS[gather]
+        o.wave_colour_groups = 1 if wave_colour_groups else 0
         h = U.um_plan_build(self.ctx, U.UM_K_EDGE_FLUX_LF2D, self.args(), self.s_edges, o)
         p = Plan(h, strategy, block_size, U.um_plan_stats_get(h).as_dict())
         self._plans.append(p)

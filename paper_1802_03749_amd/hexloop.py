@@ -27,6 +27,7 @@ class HexLoop:
         e2n = np.ascontiguousarray(e2n, np.int32)
         self.N, self.E = x.shape[0], e2n.shape[0]
         self.ctx = U.um_create(device)
+        self._plans = []
         self.s_nodes = U.um_decl_set(self.ctx, self.N, "nodes")
         self.s_elems = U.um_decl_set(self.ctx, self.E, "elements")
         self.m_e2n = U.um_decl_map(self.ctx, self.s_elems, self.s_nodes, 8, e2n)
@@ -91,6 +92,9 @@ class HexLoop:
         self.force.zero_()
 
     def force_user(self) -> np.ndarray:
+        """force in user numbering; raises if a dataflow plan of this loop
+        gave up a wait (its results would be invalid)."""
+        U.raise_on_plan_errors([p.handle for p in self._plans], "hex loop")
         dst = torch.empty_like(self.force)
         U.um_permute_dat(self.ctx, self.s_nodes, 1, self.force.data_ptr(), dst.data_ptr(), 3,
                          U.UM_F64, self.layout, self.stream)
@@ -118,7 +122,9 @@ class HexLoop:
         o.block_colouring = BCOLOURING[block_colouring]
         o.schedule = SCHEDULES[schedule]
         h = U.um_plan_build(self.ctx, U.UM_K_HEX_HOURGLASS_3D, self.args(), self.s_elems, o)
-        return Plan(h, strategy, block_size, U.um_plan_stats_get(h).as_dict())
+        p = Plan(h, strategy, block_size, U.um_plan_stats_get(h).as_dict())
+        self._plans.append(p)
+        return p
 
     def export(self, plan: Plan, field: int) -> np.ndarray:
         n = U.um_plan_export(plan.handle, field)

@@ -23,7 +23,8 @@ import numpy as np
 import torch
 
 from . import umesh as U
-from .edgeloop import BCOLOURING, LAYOUTS, SCHEDULES, STAGING, STRATEGIES, TCMODES, Plan, parse_order
+from .edgeloop import (BCOLOURING, GATHERS, LAYOUTS, SCHEDULES, STAGING, STRATEGIES, TCMODES, Plan,
+                       parse_order)
 
 GM1 = 0.4
 EPS_D = 0.25
@@ -131,7 +132,13 @@ class TimeStep2D:
         torch.cuda.synchronize(self.dev)
         return dst
 
+    def check_errors(self) -> None:
+        """Raise if a dataflow plan of the step gave up a wait: the state it
+        produced is invalid."""
+        U.raise_on_plan_errors([p.handle for p in self.plans.values()], "time step")
+
     def to_user(self, t: torch.Tensor, set_id: int) -> np.ndarray:
+        self.check_errors()
         dim = t.shape[1] if self.layout == U.UM_AOS else t.shape[0]
         dst = torch.empty_like(t)
         dt = U.UM_F64 if t.dtype == torch.float64 else U.UM_F32
@@ -161,6 +168,8 @@ class TimeStep2D:
         o.elems_per_thread = kw.get("elems_per_thread", 1)
         o.block_colouring = BCOLOURING[kw.get("block_colouring", "first_fit")]
         o.schedule = SCHEDULES[kw.get("schedule", "colour_launches")]
+        o.gather = GATHERS[kw.get("gather", "registers")]
+        o.wave_colour_groups = 1 if kw.get("wave_colour_groups", False) else 0
         return o
 
     def _build(self, name, kernel, args, iter_set, o, strategy):
@@ -176,7 +185,8 @@ class TimeStep2D:
                     staging: str = "all", tcmode: str = "barrier",
                     block_colouring: str = "first_fit", schedule: str = "colour_launches",
                     bres_strategy: str = "global", cell_block_size: int = 256,
-                    elems_per_thread: int = 1, fuse_adt: bool = False) -> dict:
+                    elems_per_thread: int = 1, fuse_adt: bool = False,
+                    gather: str = "registers") -> dict:
         a = U.um_arg
         self.fused = bool(fuse_adt)
         self.adt_valid = False
@@ -187,7 +197,7 @@ class TimeStep2D:
         self._build("flux", U.UM_K_EDGE_FLUX_LF2D, self.flux_args(), self.s_edges,
                     self._opts(flux_strategy, flux_block_size, staging=staging, tcmode=tcmode,
                                block_colouring=block_colouring, schedule=schedule,
-                               elems_per_thread=elems_per_thread),
+                               elems_per_thread=elems_per_thread, gather=gather),
                     flux_strategy)
         self._build("bres", U.UM_K_BOUNDARY_FLUX_2D,
                     [a(self.d_x, self.m_b2n, 0, U.UM_READ), a(self.d_x, self.m_b2n, 1, U.UM_READ),

@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libumesh.so")
 
 # ---- constants mirrored from umesh.h
-UMESH_ABI_VERSION = 1
+UMESH_ABI_VERSION = 2
 UM_OK, UM_ERR_ARG, UM_ERR_RANGE, UM_ERR_ARITY, UM_ERR_COLOURS = 0, -1, -2, -3, -4
 UM_ERR_LDS, UM_ERR_HIP, UM_ERR_STATE, UM_ERR_NOMEM, UM_ERR_UNSUPPORTED = -5, -6, -7, -8, -9
 UM_F64, UM_F32 = 0, 1
@@ -33,6 +33,7 @@ UM_STAGE_ALL, UM_STAGE_INC_ONLY = 0, 1
 UM_TC_BARRIER, UM_TC_LDS_ATOMIC = 0, 1
 UM_BCOL_FIRST_FIT, UM_BCOL_RECOLOUR, UM_BCOL_MIN = 0, 1, 2
 UM_SCHED_COLOUR_LAUNCHES, UM_SCHED_DATAFLOW = 0, 1
+UM_GATHER_REGISTERS, UM_GATHER_LDS_DMA = 0, 1
 UM_K_EDGE_FLUX_LF2D, UM_K_HEX_HOURGLASS_3D = 0, 1
 UM_K_CELL_ADT_2D, UM_K_BOUNDARY_FLUX_2D, UM_K_UPDATE_2D, UM_K_UPDATE_ADT_2D = 2, 3, 4, 5
 UM_ALL_SLOTS = -1
@@ -41,7 +42,7 @@ UM_GLOBAL = -2
  UM_EXP_GLOBAL_COLOURS, UM_EXP_STAGED_OFFSETS_A, UM_EXP_STAGED_POINTS_A,
  UM_EXP_STAGED_OFFSETS_B, UM_EXP_STAGED_POINTS_B, UM_EXP_LOCAL_INDEX,
  UM_EXP_BLOCK_ORDER, UM_EXP_RUN_OFFSETS_A, UM_EXP_RUNS_A, UM_EXP_RUN_OFFSETS_B,
- UM_EXP_RUNS_B) = range(15)
+ UM_EXP_RUNS_B, UM_EXP_PRED_OFFSETS, UM_EXP_PREDS) = range(17)
 
 STATUS_NAMES = {0: "UM_OK", -1: "UM_ERR_ARG", -2: "UM_ERR_RANGE", -3: "UM_ERR_ARITY",
                 -4: "UM_ERR_COLOURS", -5: "UM_ERR_LDS", -6: "UM_ERR_HIP", -7: "UM_ERR_STATE",
@@ -71,7 +72,8 @@ class um_plan_opts(ct.Structure):
                 ("lds_limit_bytes", ct.c_int32), ("allow_fallback", ct.c_int32),
                 ("elems_per_thread", ct.c_int32), ("explicit_lists", ct.c_int32),
                 ("block_colouring", ct.c_int32), ("schedule", ct.c_int32),
-                ("reserved", ct.c_int32 * 1)]
+                ("gather", ct.c_int32), ("wave_colour_groups", ct.c_int32),
+                ("reserved", ct.c_int32 * 2)]
 
 
 class um_plan_stats(ct.Structure):
@@ -119,6 +121,12 @@ _SIGNATURES = {
     "um_plan_set_timing": [_P, _I32],
     "um_plan_timing": [_P, ct.POINTER(ct.c_double), _PI64],
     "um_plan_errors": [_P, _PI32],
+    "um_plan_reset_errors": [_P],
+    "um_plan_set_wait_limit": [_P, _I64],
+    "um_graph_begin": [_P],
+    "um_graph_end": [_P, ct.POINTER(_P)],
+    "um_graph_launch": [_P, _P],
+    "um_graph_destroy": [_P],
     "um_debug_fluxes": [_P, _P, _I32, _P, _P],
 }
 _RESTYPES = {"um_abi_version": ct.c_int32, "um_last_error": ct.c_char_p}
@@ -305,3 +313,70 @@ def um_plan_errors(plan: int) -> int:
     n = _I32()
     _check(lib().um_plan_errors(plan, ct.byref(n)), "um_plan_errors")
     return n.value
+
+
+def um_plan_reset_errors(plan: int) -> None:
+    _check(lib().um_plan_reset_errors(plan), "um_plan_reset_errors")
+
+
+def um_plan_set_wait_limit(plan: int, ticks: int) -> None:
+    _check(lib().um_plan_set_wait_limit(plan, int(ticks)), "um_plan_set_wait_limit")
+
+
+def um_graph_begin(stream: int) -> None:
+    _check(lib().um_graph_begin(stream), "um_graph_begin")
+
+
+def um_graph_end(stream: int) -> int:
+    g = _P()
+    _check(lib().um_graph_end(stream, ct.byref(g)), "um_graph_end")
+    return g.value
+
+
+def um_graph_launch(graph: int, stream: int) -> None:
+    _check(lib().um_graph_launch(graph, stream), "um_graph_launch")
+
+
+def um_graph_destroy(graph: int) -> None:
+    _check(lib().um_graph_destroy(graph), "um_graph_destroy")
+
+
+def raise_on_plan_errors(handles, what: str) -> None:
+    """Raise if a DATAFLOW plan among `handles` counted a given-up wait:
+    the results of the executions it happened in are invalid."""
+    for h in handles:
+        n = um_plan_errors(h)
+        if n:
+            raise RuntimeError(f"{what}: {n} dataflow wait(s) gave up; the results of "
+                               f"those executions are invalid")
+
+
+class HipGraph:
+    """Work enqueued by `enqueue(stream)` captured into a HIP graph with the
+    library's capture entry points (on a side stream of the current device)
+    and replayed with replay(); torch provides only the streams."""
+
+    def __init__(self, enqueue):
+        import torch
+        cur = torch.cuda.current_stream()
+        side = torch.cuda.Stream()
+        side.wait_stream(cur)
+        torch.cuda.synchronize()
+        um_graph_begin(side.cuda_stream)
+        try:
+            enqueue(side.cuda_stream)
+        finally:
+            self.handle = um_graph_end(side.cuda_stream)
+        torch.cuda.synchronize()
+
+    def replay(self, stream: int | None = None) -> None:
+        import torch
+        um_graph_launch(self.handle,
+                        torch.cuda.current_stream().cuda_stream if stream is None else stream)
+
+    def close(self) -> None:
+        if self.handle:
+            import torch
+            torch.cuda.synchronize()
+            um_graph_destroy(self.handle)
+            self.handle = 0

@@ -471,10 +471,7 @@ def test_hex_dataflow(layout, tcmode):
     assert rel_l2(outs[0], ref) <= TOL
     if tcmode == "barrier":
         assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        L.run(p, stream=torch.cuda.current_stream().cuda_stream)
-    torch.cuda.synchronize()
+    g = U.HipGraph(lambda stream: L.run(p, stream=stream))
     L.zero_force(); torch.cuda.synchronize()
     for k in range(1, 3):
         g.replay(); torch.cuda.synchronize()
@@ -531,8 +528,8 @@ def test_hex_full_size():
 
 @pytest.mark.parametrize("schedule", ["colour_launches", "dataflow"])
 def test_graph_capture_replay(schedule):
-    """The loop captured in a HIP graph (torch.cuda.CUDAGraph on the capture
-    stream) and replayed several times, with eager work and synchronisation
+    """The loop captured in a HIP graph (the library's capture entry points
+    on a side stream) and replayed several times, with eager work and synchronisation
     in between: every replay adds exactly one more loop's increments."""
     m, ref = mesh(200, 100)
     L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
@@ -543,10 +540,7 @@ def test_graph_capture_replay(schedule):
     torch.cuda.synchronize()
     eager = L.res_user()
     assert rel_l2(eager, ref) <= TOL
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        L.run(p, stream=torch.cuda.current_stream().cuda_stream)
-    torch.cuda.synchronize()
+    g = U.HipGraph(lambda stream: L.run(p, stream=stream))
     L.zero_res()
     torch.cuda.synchronize()
     for k in range(1, 4):

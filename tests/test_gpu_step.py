@@ -205,10 +205,7 @@ def test_graph_captured_steps(schedule):
     B = make(m, block_size=256); B.build_plans(flux_block_size=256, schedule=schedule)
     A.step(); B.step()                    # eager warm-up on both
     torch.cuda.synchronize()
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        B.step(stream=torch.cuda.current_stream().cuda_stream)
-    torch.cuda.synchronize()
+    g = U.HipGraph(lambda stream: B.step(stream=stream))
     for k in range(3):
         g.replay()
         A.step()

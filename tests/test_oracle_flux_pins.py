@@ -196,9 +196,27 @@ def test_global_conservation():
     f = native.edge_fluxes(m.e2n, m.e2c, m.x, m.q, m.adt)
     bound = 2 * m.e2n.shape[0] * U * np.abs(f).max(axis=0) * 8
     assert np.all(np.abs(res.sum(axis=0)) <= bound)
-    # the per-edge increments cancel exactly
-    inc = np.zeros_like(res)
-    assert np.array_equal(f + (-f), np.zeros_like(f))
+
+
+def test_scatter_is_antisymmetric_per_edge():
+    """The loop run over one interior edge at a time: exactly the edge's two
+    cells change, by f and -f bitwise (the per-edge increments of an
+    interior edge sum to zero), f is the edge's flux, and the sum of the
+    single-edge results is the whole loop within rounding."""
+    m = quad_mesh(9, 6, seed=29)
+    E, C = m.e2n.shape[0], m.n_cells
+    total = np.zeros((C, 4))
+    f_all = native.edge_fluxes(m.e2n, m.e2c, m.x, m.q, m.adt)
+    for e in range(E):
+        r = native.edge_loop(m.e2n[e:e + 1], m.e2c[e:e + 1], m.x, m.q, m.adt)
+        L, R = m.e2c[e]
+        touched = np.nonzero(np.any(r != 0.0, axis=1))[0]
+        assert set(touched) == {L, R}, e
+        assert np.array_equal(r[L], -r[R]), e
+        assert np.array_equal(r[L], f_all[e]), e
+        total += r
+    full = native.edge_loop(m.e2n, m.e2c, m.x, m.q, m.adt)
+    assert np.abs(total - full).max() <= 8 * U * np.abs(f_all).max()
 
 
 def test_renumbering_invariance():
@@ -226,3 +244,22 @@ def test_edge_fluxes_match_loop_scatter():
         res[m.e2c[e, 0]] += f[e]
         res[m.e2c[e, 1]] -= f[e]
     assert np.array_equal(res, native.edge_loop(m.e2n, m.e2c, m.x, m.q, m.adt))
+
+
+def test_colour_parallel_cpu_loop_matches_sequential():
+    """The all-cores CPU baseline (one OpenMP loop per global colour) equals
+    the sequential loop within rounding, and its colouring is race-free."""
+    from oracle import plans as P
+    m = quad_mesh(60, 40, seed=31)
+    g = native.colour_groups(m.e2c)
+    ncol, col_off, order = g
+    col = np.empty(m.e2c.shape[0], np.int32)
+    for c in range(ncol):
+        col[order[col_off[c]:col_off[c + 1]]] = c
+    assert P.check_global_colouring(col, m.e2c)
+    assert np.array_equal(np.sort(order), np.arange(m.e2c.shape[0]))
+    seq = native.edge_loop(m.e2n, m.e2c, m.x, m.q, m.adt)
+    par = native.edge_loop_coloured(g, m.e2n, m.e2c, m.x, m.q, m.adt)
+    f = native.edge_fluxes(m.e2n, m.e2c, m.x, m.q, m.adt)
+    assert np.abs(par - seq).max() <= 8 * U * np.abs(f).max()
+    assert native.omp_threads() >= 1

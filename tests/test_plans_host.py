@@ -298,6 +298,55 @@ def test_declaration_errors():
         U.um_destroy(ctx)
 
 
+def test_dat_alignment_and_aliasing_rejected():
+    """Pointers the kernels' vector accesses cannot use, and an incremented
+    dat sharing memory with a read one, are refused (host-only context: the
+    addresses are checked, never dereferenced)."""
+    ctx = U.um_create(-1)
+    try:
+        s_c = U.um_decl_set(ctx, 4, "cells")
+        s_n = U.um_decl_set(ctx, 3, "nodes")
+        s_e = U.um_decl_set(ctx, 2, "edges")
+        cases = [(4, U.UM_F64, U.UM_AOS, 0x1008, False), (4, U.UM_F64, U.UM_AOS, 0x1010, True),
+                 (2, U.UM_F32, U.UM_AOS, 0x1008, True), (2, U.UM_F32, U.UM_AOS, 0x1004, False),
+                 (4, U.UM_F64, U.UM_SOA, 0x1004, False), (1, U.UM_F32, U.UM_SOA, 0x1004, True),
+                 (3, U.UM_F64, U.UM_AOS, 0x1008, True)]
+        for dim, dt, lay, ptr, ok in cases:
+            if ok:
+                U.um_decl_dat(ctx, s_c, dim, dt, lay, ptr)
+            else:
+                with pytest.raises(U.UmeshError) as ei:
+                    U.um_decl_dat(ctx, s_c, dim, dt, lay, ptr)
+                assert ei.value.status == U.UM_ERR_ARG and "aligned" in U.um_last_error()
+        d = U.um_decl_dat(ctx, s_c, 4, U.UM_F64, U.UM_AOS, 0x10000)
+        with pytest.raises(U.UmeshError) as ei:
+            U.um_set_dat_ptr(ctx, d, 0x10008)
+        assert ei.value.status == U.UM_ERR_ARG and "aligned" in U.um_last_error()
+        U.um_set_dat_ptr(ctx, d, 0x10020)
+        m_n = U.um_decl_map(ctx, s_e, s_n, 2, np.array([[0, 1], [1, 2]], np.int32))
+        m_c = U.um_decl_map(ctx, s_e, s_c, 2, np.array([[0, 1], [2, 3]], np.int32))
+        x = U.um_decl_dat(ctx, s_n, 2, U.UM_F64, U.UM_AOS, 0x20000)
+        q = U.um_decl_dat(ctx, s_c, 4, U.UM_F64, U.UM_AOS, 0x30000)
+        adt = U.um_decl_dat(ctx, s_c, 1, U.UM_F64, U.UM_AOS, 0x40000)
+        res_over = U.um_decl_dat(ctx, s_c, 4, U.UM_F64, U.UM_AOS, 0x30000 + 64)
+        res_ok = U.um_decl_dat(ctx, s_c, 4, U.UM_F64, U.UM_AOS, 0x50000)
+        a = U.um_arg
+        o = U.um_plan_opts(); o.strategy = U.UM_STRAT_ATOMIC; o.block_size = 64
+
+        def args(res):
+            return [a(x, m_n, 0, U.UM_READ), a(x, m_n, 1, U.UM_READ), a(q, m_c, 0, U.UM_READ),
+                    a(q, m_c, 1, U.UM_READ), a(adt, m_c, 0, U.UM_READ), a(adt, m_c, 1, U.UM_READ),
+                    a(res, m_c, 0, U.UM_INC), a(res, m_c, 1, U.UM_INC)]
+        for res in (q, res_over):
+            with pytest.raises(U.UmeshError) as ei:
+                U.um_plan_build(ctx, U.UM_K_EDGE_FLUX_LF2D, args(res), s_e, o)
+            assert ei.value.status == U.UM_ERR_ARG, res
+        h = U.um_plan_build(ctx, U.UM_K_EDGE_FLUX_LF2D, args(res_ok), s_e, o)
+        U.um_plan_destroy(h)
+    finally:
+        U.um_destroy(ctx)
+
+
 def test_host_only_context_cannot_execute():
     _, L = make(nx=6, ny=4, order="rcm")
     p = L.plan("atomic", 64)
@@ -537,3 +586,49 @@ def test_min_block_colouring_is_valid_and_no_worse():
     # deterministic
     pm2 = L.plan("hier", 512, block_colouring="min")
     assert np.array_equal(L.export(pm2, U.UM_EXP_BLOCK_COLOURS), bcol)
+
+
+@pytest.mark.parametrize("S,ept", [(512, 1), (512, 2), (256, 2), (1024, 2)])
+def test_wave_colour_groups_padding(S, ept):
+    """Wave-pure colour groups: each block's slots are its elements sorted by
+    thread colour (the unpadded plan's order), every colour's run padded with
+    empty slots to a multiple of 64, so every 64-slot chunk of a block holds
+    one colour; the thread colouring itself is the oracle's first fit."""
+    m, L = make(nx=64, ny=40, order="rcm+partition", block_size=S)
+    base = L.plan("hier", S, elems_per_thread=ept)
+    p = L.plan("hier", S, elems_per_thread=ept, wave_colour_groups=True)
+    off = L.export(p, U.UM_EXP_BLOCK_OFFSETS)
+    e2c = L.current_map("e2c")
+    tcol = L.export(p, U.UM_EXP_THREAD_COLOURS)
+    tref, _ = P.first_fit_threads(off, e2c)
+    assert np.array_equal(tcol, tref)
+    border = L.export(p, U.UM_EXP_BLOCK_ORDER)
+    assert np.array_equal(border, L.export(base, U.UM_EXP_BLOCK_ORDER))
+    slots = L.export(p, U.UM_EXP_SLOT_ELEMENTS)
+    bslots = L.export(base, U.UM_EXP_SLOT_ELEMENTS)
+    loc = L.export(p, U.UM_EXP_LOCAL_INDEX).reshape(-1, 4)
+    bloc = L.export(base, U.UM_EXP_LOCAL_INDEX).reshape(-1, 4)
+    assert np.array_equal(slots[slots >= 0], bslots)          # same order, gaps removed
+    assert np.array_equal(loc[slots >= 0], bloc)
+    pos, max_slots = 0, 0
+    for b in border:
+        cols = tref[off[b]:off[b + 1]]
+        want = sum(-(-int((cols == c).sum()) // 64) * 64 for c in range(int(cols.max()) + 1))
+        blk = slots[pos:pos + want]
+        assert len(blk) == want
+        for c0 in range(0, want, 64):
+            chunk = blk[c0:c0 + 64]
+            real = chunk[chunk >= 0]
+            assert real.size > 0 and np.unique(tcol[real]).size == 1
+            assert np.all(chunk[:real.size] >= 0) and np.all(chunk[real.size:] < 0)
+        pos += want
+        max_slots = max(max_slots, want)
+    assert pos == len(slots)
+    assert U.um_plan_stats_get(p.handle).n_elements == L.E
+
+
+def test_wave_colour_groups_refused_where_unsupported():
+    _, L = make(order="rcm+partition", block_size=256)
+    with pytest.raises(U.UmeshError) as ei:
+        L.plan("global", 256, wave_colour_groups=True)
+    assert ei.value.status == U.UM_ERR_UNSUPPORTED
