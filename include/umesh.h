@@ -369,7 +369,9 @@ const char *um_last_error(void);
 
 /* Create a context on HIP device `device` (>= 0), or a host-only context
  * (device = -1) that can declare meshes, reorder and build plans but not
- * execute or touch device memory.  *out receives the handle.
+ * execute or touch device memory.  A context holds one mesh in the sense of
+ * Section 1.1.1 (its sets, maps and dats) and the plans built for its
+ * loops.  *out receives the handle.
  * Errors: UM_ERR_ARG (null out, device < -1), UM_ERR_HIP (device unusable). */
 um_status um_create(int32_t device, um_ctx *out);
 
@@ -379,8 +381,9 @@ um_status um_destroy(um_ctx ctx);
 
 /* ------------------------------------------------------------ declaration */
 
-/* Declare a set of `size` elements (size >= 0).  `name` (may be NULL) is
- * copied.  *set_id receives the id (0, 1, ... in declaration order). */
+/* Declare a set of `size` elements (size >= 0), a set of Section 1.1.1
+ * (cells, edges, nodes, ...).  `name` (may be NULL) is copied.  *set_id
+ * receives the id (0, 1, ... in declaration order). */
 um_status um_decl_set(um_ctx ctx, int64_t size, const char *name, int32_t *set_id);
 
 /* Declare a map from every element of `from_set` to `arity` elements of
@@ -467,7 +470,7 @@ um_status um_get_blocks(um_ctx ctx, int32_t set, int32_t *block_size, int32_t *n
                         int32_t *host_off, int64_t capacity);
 
 /* Device gather/scatter of a dat between the original numbering and the
- * current one.  direction 0: dst[k] = src[new2old[k]] (original -> current);
+ * current one (the renumbering of Section 2.3 applied to the data).  direction 0: dst[k] = src[new2old[k]] (original -> current);
  * direction 1: dst[new2old[k]] = src[k] (current -> original).  src and dst
  * are distinct device buffers of size(set)*dim values with the given dtype
  * and layout.  Asynchronous on `stream` (a hipStream_t; NULL = default). */
@@ -502,7 +505,10 @@ um_status um_plan_export(um_plan plan, int32_t field, int32_t *host_out, int64_t
 um_status um_plan_destroy(um_plan plan);
 
 /* Execute the loop once on `stream` (hipStream_t, NULL = default stream),
- * incrementing the INC dats (they are not cleared).  Asynchronous; the
+ * incrementing the INC dats (they are not cleared): the loop of Section
+ * 1.1.1 over every element of the iteration set, executed by the plan's
+ * strategy (Section 2.1; HIER: Algorithm 1 of Section 2.2 per block, block
+ * colours ordered by kernel launches or by the DATAFLOW schedule).  Asynchronous; the
  * dats bound to the plan's args must stay valid until the work completes.
  * params: kernel constants (listed with each um_kernel).  Errors: UM_ERR_STATE on a
  * host-only context or a dat without device memory, UM_ERR_HIP on launch

@@ -28,13 +28,21 @@ from . import umesh as U
 from .timestep import TimeStep2D
 
 # block sizes are multiples of the default partition block (512), so every
-# candidate uses whole partition blocks
+# candidate uses whole partition blocks; the candidates vary block size,
+# schedule, block colouring, the layout of thread colours (wave-pure
+# groups), staging (all data or increments only) and the gather
 DEFAULT_CANDIDATES = (
     dict(block_size=512),
     dict(block_size=512, block_colouring="recolour"),
+    dict(block_size=512, block_colouring="recolour", staging="inc"),
+    dict(block_size=512, block_colouring="recolour", wave_colour_groups=True),
     dict(block_size=512, schedule="dataflow", block_colouring="recolour"),
     dict(block_size=512, schedule="dataflow", block_colouring="recolour", elems_per_thread=2),
+    dict(block_size=512, schedule="dataflow", block_colouring="recolour", elems_per_thread=2,
+         gather="lds_dma"),
     dict(block_size=1024, schedule="dataflow", block_colouring="recolour", elems_per_thread=2),
+    dict(block_size=1024, schedule="dataflow", block_colouring="recolour", elems_per_thread=2,
+         gather="lds_dma"),
 )
 
 
@@ -82,6 +90,8 @@ class BatchedSteps:
                                    block_colouring=c.get("block_colouring", "first_fit"),
                                    staging=c.get("staging", "all"),
                                    elems_per_thread=c.get("elems_per_thread", 1),
+                                   gather=c.get("gather", "registers"),
+                                   wave_colour_groups=c.get("wave_colour_groups", False),
                                    fuse_adt=fuse_adt)
                 self.steps.append(ts)
         torch.cuda.synchronize()

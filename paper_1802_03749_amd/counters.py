@@ -2,6 +2,7 @@
 
     python -m paper_1802_03749_amd.counters --loop edge --out profiles/<name>_traffic.json
     python -m paper_1802_03749_amd.counters --loop hex --out profiles/<name>_traffic.json
+    python -m paper_1802_03749_amd.counters --loop batch --out profiles/<name>_gaps.json
 
 The driver runs this same module in workload mode (--workload) under
 rocprofv3 once per counter pass (FETCH_SIZE, then WRITE_SIZE: one counter
@@ -20,6 +21,9 @@ kernel are counted the same way (their ratios are reported).
 
 The workload builds the benchmark's plan (the same options as bench.py's
 headline) and runs it `--launches` times after the calibration kernels.
+With --loop batch the workload is the 64-mesh batch's union time step
+replayed from its captured graph, and the driver runs only a kernel trace:
+it reports how much of each replayed step lies between the step's kernels.
 """
 from __future__ import annotations
 
@@ -65,6 +69,23 @@ def workload(args) -> int:
         w.fill_(2.0)
     torch.cuda.synchronize()
     del a, b, r, w
+    if args.loop == "batch":
+        import numpy as np
+        from meshgen import quad_batch
+        from paper_1802_03749_amd.batched import BatchedSteps
+        ms = quad_batch(64, c_min=5e3, c_max=5e5, size_seed=5)
+        B = BatchedSteps(ms, np.array([1.0, 0.35, 0.05, 2.7]), mode="union", dtype=args.dtype)
+        B.capture()
+        for _ in range(args.launches):
+            B.replay()
+        torch.cuda.synchronize()
+        B.check_errors()
+        print(json.dumps({"tuned": {str(k): v[0] for k, v in B.tuned.items()},
+                          "launches_per_step": sum(p.stats["n_launches"]
+                                                   for ts in B.steps for p in ts.plans.values())}),
+              flush=True)
+        B.close()
+        return 0
     if args.loop == "edge":
         m = quad_mesh(args.nx, args.ny, seed=1)
         L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
@@ -115,9 +136,85 @@ def _mean_of(per, pattern: str):
     return sum(vals) / len(vals), len(vals)
 
 
+def _kernel_stats(outdir: str):
+    """Rows of rocprofv3's kernel statistics CSV (--stats)."""
+    files = glob.glob(os.path.join(outdir, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise RuntimeError(f"no kernel statistics CSV under {outdir}")
+    rows = []
+    for fn in files:
+        with open(fn, newline="") as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def trace_pass(args, passthrough, base):
+    """Kernel trace with statistics of the same workload; returns the
+    command and {kernel: (calls, avg us, min us, max us)}."""
+    outdir = os.path.join(base, "trace")
+    cmd = ["timeout", "-s", "KILL", str(args.pass_timeout), "rocprofv3", "--kernel-trace",
+           "--stats", "--output-format", "csv", "-d", outdir, "-o", "t", "--", sys.executable,
+           "-m", "paper_1802_03749_amd.counters", "--workload", *passthrough]
+    print("[counters]", " ".join(cmd), file=sys.stderr, flush=True)
+    r = subprocess.run(cmd, cwd=ROOT)
+    if r.returncode != 0:
+        raise RuntimeError(f"trace pass failed with status {r.returncode}")
+    stats = {}
+    for row in _kernel_stats(outdir):
+        name = _kernel_key(row["Name"])
+        stats[name] = (int(row["Calls"]), float(row["AverageNs"]) / 1e3,
+                       float(row["MinNs"]) / 1e3, float(row["MaxNs"]) / 1e3)
+    return " ".join(cmd[4:]), stats
+
+
+def step_gaps(outdir: str, per_step: int, n_steps: int, skip_steps: int = 2):
+    """From the kernel trace of graph-replayed steps: each step is
+    `per_step` consecutive dispatches; the step's span (first start to last
+    end) against the sum of its kernels' durations gives the share of the
+    step spent between kernels."""
+    files = glob.glob(os.path.join(outdir, "**", "*kernel_trace.csv"), recursive=True)
+    rows = []
+    for fn in files:
+        with open(fn, newline="") as f:
+            for r in csv.DictReader(f):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]),
+                             _kernel_key(r["Kernel_Name"])))
+    rows.sort()
+    # the replayed steps are the last dispatches of the run
+    names = [r[2] for r in rows]
+    tail = rows[-n_steps * per_step:]
+    steps = [tail[i:i + per_step] for i in range(0, len(tail), per_step)][skip_steps:]
+    spans = [st[-1][1] - st[0][0] for st in steps]
+    busy = [sum(e - b for b, e, _ in st) for st in steps]
+    gaps = [sp - bu for sp, bu in zip(spans, busy)]
+    n = len(steps)
+    return {"steps_analysed": n, "dispatches_per_step": per_step,
+            "kernels_of_a_step": [k for _, _, k in steps[-1]] if steps else [],
+            "mean_step_span_us": sum(spans) / n / 1e3 if n else None,
+            "mean_kernel_time_us": sum(busy) / n / 1e3 if n else None,
+            "mean_gap_us": sum(gaps) / n / 1e3 if n else None,
+            "gap_share": (sum(gaps) / sum(spans)) if n else None,
+            "all_dispatches": len(names)}
+
+
 def driver(args, passthrough) -> int:
     base = os.path.abspath(args.workdir or tempfile.mkdtemp(prefix="counters_"))
     cmds, per = [], {}
+    trace = None
+    if args.loop == "batch":
+        # the batch: kernel trace only, the gaps between the step's launches
+        tcmd, stats = trace_pass(args, passthrough, base)
+        out = {"loop": "batch", "dtype": args.dtype, "trace_command": tcmd,
+               "kernels": {k: {"calls": v[0], "avg_us": v[1], "min_us": v[2], "max_us": v[3]}
+                           for k, v in sorted(stats.items())},
+               "gaps": step_gaps(os.path.join(base, "trace"), args.per_step, args.launches)}
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        with open(args.out, "w") as f:
+            json.dump(out, f, indent=1)
+        print(json.dumps(out), flush=True)
+        return 0
+    if args.trace:
+        trace = trace_pass(args, passthrough, base)
     for counter in ("FETCH_SIZE", "WRITE_SIZE"):
         outdir = os.path.join(base, counter.lower())
         cmd = ["timeout", "-s", "KILL", str(args.pass_timeout), "rocprofv3", "--pmc", counter,
@@ -164,6 +261,17 @@ def driver(args, passthrough) -> int:
         "what_is_counted": "L2-to-fabric bytes (HBM plus last-level-cache hits), scaled",
         "commands": cmds,
     }
+    if trace is not None:
+        tcmd, stats = trace
+        mine = {k: v for k, v in stats.items() if re.search(kpat, k)}
+        out["trace"] = {"command": tcmd,
+                        "kernels": {k: {"calls": v[0], "avg_us": v[1], "min_us": v[2],
+                                        "max_us": v[3]} for k, v in sorted(mine.items())}}
+        if mine:
+            calls = sum(v[0] for v in mine.values())
+            avg = sum(v[0] * v[1] for v in mine.values()) / calls
+            out["trace"]["avg_us"] = avg
+            out["trace"]["traffic_tbps"] = out["bytes_per_launch"] / (avg * 1e-6) / 1e12
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as f:
         json.dump(out, f, indent=1)
@@ -177,7 +285,10 @@ def main() -> int:
     ap.add_argument("--out", default=None)
     ap.add_argument("--workdir", default=None, help="where rocprofv3 writes its CSV files")
     ap.add_argument("--pass-timeout", type=int, default=150)
-    ap.add_argument("--loop", default="edge", choices=["edge", "hex"])
+    ap.add_argument("--loop", default="edge", choices=["edge", "hex", "batch"])
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--per-step", type=int, default=6,
+                    help="batch: kernel launches of one replayed step")
     ap.add_argument("--nx", type=int, default=2400)
     ap.add_argument("--ny", type=int, default=1200)
     ap.add_argument("--n", type=int, default=128)
@@ -190,6 +301,8 @@ def main() -> int:
     ap.add_argument("--ept", type=int, default=2, choices=[1, 2])
     ap.add_argument("--gather", default="registers", choices=["registers", "lds_dma"])
     ap.add_argument("--launches", type=int, default=20)
+    ap.add_argument("--trace", action="store_true",
+                    help="also run a kernel-trace pass with statistics (average launch time)")
     args, _ = ap.parse_known_args()
     if args.workload:
         return workload(args)
@@ -200,6 +313,9 @@ def main() -> int:
     while i < len(argv):
         if argv[i] in skip:
             i += 2
+            continue
+        if argv[i] == "--trace":
+            i += 1
             continue
         passthrough.append(argv[i])
         i += 1

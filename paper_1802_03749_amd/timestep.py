@@ -186,7 +186,7 @@ class TimeStep2D:
                     block_colouring: str = "first_fit", schedule: str = "colour_launches",
                     bres_strategy: str = "global", cell_block_size: int = 256,
                     elems_per_thread: int = 1, fuse_adt: bool = False,
-                    gather: str = "registers") -> dict:
+                    gather: str = "registers", wave_colour_groups: bool = False) -> dict:
         a = U.um_arg
         self.fused = bool(fuse_adt)
         self.adt_valid = False
@@ -197,7 +197,8 @@ class TimeStep2D:
         self._build("flux", U.UM_K_EDGE_FLUX_LF2D, self.flux_args(), self.s_edges,
                     self._opts(flux_strategy, flux_block_size, staging=staging, tcmode=tcmode,
                                block_colouring=block_colouring, schedule=schedule,
-                               elems_per_thread=elems_per_thread, gather=gather),
+                               elems_per_thread=elems_per_thread, gather=gather,
+                               wave_colour_groups=wave_colour_groups),
                     flux_strategy)
         self._build("bres", U.UM_K_BOUNDARY_FLUX_2D,
                     [a(self.d_x, self.m_b2n, 0, U.UM_READ), a(self.d_x, self.m_b2n, 1, U.UM_READ),
