@@ -266,6 +266,9 @@ def main() -> int:
     ap.add_argument("--bcol", default="recolour", choices=["first_fit", "recolour"])
     ap.add_argument("--ept", type=int, default=2, choices=[1, 2],
                     help="edges per lane (the workgroup has block_size / ept lanes)")
+    ap.add_argument("--point-order", type=int, default=1, choices=[1, 2],
+                    help="1: the paper's block-signature order of points; 2: smallest "
+                         "accessing block first")
     ap.add_argument("--gather", default="lds_dma", choices=["registers", "lds_dma"],
                     help="dataflow gather: through registers, or loads that write LDS directly")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -311,7 +314,8 @@ def main() -> int:
     # ---- hierarchical colouring on the reordered + partitioned mesh
     t = time.perf_counter()
     hier = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0,
-                        order="rcm+partition", block_size=S, layout=args.layout)
+                        order="rcm+partition", block_size=S, layout=args.layout,
+                        point_reorder=args.point_order)
     reorder_s = time.perf_counter() - t
     hopts = dict(staging=args.staging, tcmode=args.tcmode, block_colouring=args.bcol,
                  elems_per_thread=args.ept)
@@ -639,6 +643,7 @@ def main() -> int:
             "cells": C, "nodes": N, "edges": E,
             "strategy": "hierarchical two-layer colouring",
             "order": "rcm+partition+point-reorder",
+            "point_order": "block signature" if args.point_order == 1 else "smallest block first",
             "block_size": S, "layout": args.layout, "staging": args.staging,
             "tcmode": args.tcmode, "schedule": args.schedule, "block_colouring": args.bcol,
             "edges_per_lane": args.ept,

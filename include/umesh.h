@@ -261,8 +261,14 @@ typedef struct {
     int32_t driving_map;   /* map whose to-set is renumbered (RCM/GPS) and
                               whose from-set is partitioned (PARTITION)      */
     int32_t block_size;    /* PARTITION: maximum elements per block, 1..1024 */
-    int32_t point_reorder; /* PARTITION: 1 = group points of every to-set by
-                              accessing-block signature, 0 = keep order      */
+    int32_t point_reorder; /* PARTITION / USER_BLOCKS: 0 = keep the order;
+                              1 = group points of every to-set by accessing-
+                              block signature (Section 2.3.2: number of
+                              accessing blocks, then their list); 2 = by the
+                              smallest accessing block first, then number
+                              and list (an extension: each block's own
+                              points and the halo it shares with later
+                              blocks form one run)                          */
     int32_t coord_map;     /* PARTITION, optional: map from the partitioned set
                               whose to-set carries `coords`; -1 = none, then
                               a graph-distance embedding is used instead     */
@@ -439,7 +445,8 @@ um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr);
  *     blocks end up at most block_size.  Elements are renumbered block by
  *     block, keeping their previous relative order inside a block.  With
  *     point_reorder, every to-set of a map from the from-set is renumbered
- *     by (number of accessing blocks, list of accessing blocks), ties
+ *     by (number of accessing blocks, list of accessing blocks), or with
+ *     point_reorder = 2 by (smallest accessing block, number, list), ties
  *     keeping the previous order.  The blocks are remembered
  *     and used by HIER plans with the same block_size, or with a multiple
  *     k * block_size (k consecutive blocks form one plan block).

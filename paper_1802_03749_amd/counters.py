@@ -111,7 +111,17 @@ def workload(args) -> int:
 
 # -------------------------------------------------------------- driver mode
 def _kernel_key(name: str) -> str:
-    return re.sub(r"\(.*$", "", name.strip())
+    """The kernel name without its trailing parameter list (names contain
+    parentheses of their own, e.g. "(anonymous namespace)")."""
+    name = name.strip()
+    if not name.endswith(")"):
+        return name
+    depth = 0
+    for i in range(len(name) - 1, -1, -1):
+        depth += {")": 1, "(": -1}.get(name[i], 0)
+        if depth == 0:
+            return name[:i].rstrip()
+    return name
 
 
 def _read_counters(outdir: str, counter: str):
@@ -134,6 +144,13 @@ def _mean_of(per, pattern: str):
     if not vals:
         raise RuntimeError(f"no dispatch of a kernel matching {pattern!r}")
     return sum(vals) / len(vals), len(vals)
+
+
+def _max_of(per, pattern: str):
+    vals = [v for k, vs in per.items() if re.search(pattern, k) for v in vs]
+    if not vals:
+        raise RuntimeError(f"no dispatch of a kernel matching {pattern!r}")
+    return max(vals)
 
 
 def _kernel_stats(outdir: str):
@@ -228,10 +245,12 @@ def driver(args, passthrough) -> int:
         per[counter] = _read_counters(outdir, counter)
         cmds.append(" ".join(cmd[4:]))
     fetch, write = per["FETCH_SIZE"], per["WRITE_SIZE"]
-    copy_f, _ = _mean_of(fetch, r"copyBuffer")
-    copy_w, _ = _mean_of(write, r"copyBuffer")
-    red_f, _ = _mean_of(fetch, r"reduce_kernel")
-    fill_w, _ = _mean_of(write, r"FillFunctor")
+    # the calibration dispatches are the largest of their kernels in the
+    # workload (the same kernels also copy or fill smaller buffers)
+    copy_f = _max_of(fetch, r"copyBuffer")
+    copy_w = _max_of(write, r"copyBuffer")
+    red_f = _max_of(fetch, r"reduce_kernel")
+    fill_w = _max_of(write, r"FillFunctor")
     kib = 1024.0
     fetch_scale = COPY_BYTES / kib / copy_f
     write_scale = COPY_BYTES / kib / copy_w

@@ -71,9 +71,11 @@ std::vector<int32_t> partition_elements(const Ctx &ctx, int32_t drv, int32_t blo
                                         const double *coords, std::vector<int32_t> &block_off,
                                         std::vector<int32_t> &block_code);
 // Points of to-set `set` sorted by (number of accessing blocks, list of
-// accessing blocks), stable; elements of `from` are in block order.
+// accessing blocks), stable; with by_first_block, by (smallest accessing
+// block, number, list); elements of `from` are in block order.
 std::vector<int32_t> signature_order(const Ctx &ctx, int32_t from, int32_t set,
-                                     const std::vector<int32_t> &block_of_elem);
+                                     const std::vector<int32_t> &block_of_elem,
+                                     bool by_first_block);
 // Renumber `set` by new->old `perm`: rewrites every map from or into it.
 void apply_set_perm(Ctx &ctx, int32_t set, const std::vector<int32_t> &perm);
 

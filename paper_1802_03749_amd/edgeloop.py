@@ -57,7 +57,7 @@ class EdgeFluxLoop:
     """
 
     def __init__(self, x, q, adt, e2n, e2c, *, device: int = 0, order: str = "rcm+partition",
-                 block_size: int = 512, point_reorder: bool = True, layout: str = "aos",
+                 block_size: int = 512, point_reorder: int = 1, layout: str = "aos",
                  geometric_partition: bool = True, dtype: str = "f64", edge_blocks=None):
         """dtype: "f64", or "f32" to store x, q and adt in binary32 (rounded to
         nearest from the given binary64 values); res is always binary64.
@@ -94,12 +94,12 @@ class EdgeFluxLoop:
                     np.asarray(edge_blocks, np.int32)[self.perm(self.s_edges)])
                 o.mode = U.UM_REORDER_USER_BLOCKS
                 o.block_size = block_size
-                o.point_reorder = 1 if point_reorder else 0
+                o.point_reorder = int(point_reorder)
                 o.block_of = keep.ctypes.data
             else:
                 o.mode = U.UM_REORDER_PARTITION
                 o.block_size = block_size
-                o.point_reorder = 1 if point_reorder else 0
+                o.point_reorder = int(point_reorder)
                 if geometric_partition:
                     keep = np.ascontiguousarray(x[self.perm(self.s_nodes)])
                     o.coord_map = self.m_e2n

@@ -19,7 +19,7 @@ PARAMS = (KAPPA,)
 
 class HexLoop:
     def __init__(self, x, v, e2n, *, device: int = 0, order: str = "rcm+partition",
-                 block_size: int = 256, point_reorder: bool = True, layout: str = "aos",
+                 block_size: int = 256, point_reorder: int = 1, layout: str = "aos",
                  geometric_partition: bool = True):
         self.device = device
         self.layout = LAYOUTS[layout]
@@ -40,7 +40,7 @@ class HexLoop:
             else:
                 o.mode = U.UM_REORDER_PARTITION
                 o.block_size = block_size
-                o.point_reorder = 1 if point_reorder else 0
+                o.point_reorder = int(point_reorder)
                 if geometric_partition:
                     xc = np.ascontiguousarray(x[self.perm(self.s_nodes)])
                     o.coord_map = self.m_e2n

@@ -32,7 +32,7 @@ EPS_D = 0.25
 
 class TimeStep2D:
     def __init__(self, x, q, e2n, e2c, b2n, b2c, c2n, qinf, *, device: int = 0,
-                 order: str = "rcm+partition", block_size: int = 512, point_reorder: bool = True,
+                 order: str = "rcm+partition", block_size: int = 512, point_reorder: int = 1,
                  layout: str = "aos", geometric_partition: bool = True, dtype: str = "f64",
                  partition_coords=None):
         """dtype "f32": x, q and adt stored in binary32 (q rounded to nearest
@@ -75,7 +75,7 @@ class TimeStep2D:
             else:
                 o.mode = U.UM_REORDER_PARTITION
                 o.block_size = block_size
-                o.point_reorder = 1 if point_reorder else 0
+                o.point_reorder = int(point_reorder)
                 if geometric_partition:
                     pc = x if partition_coords is None else np.asarray(partition_coords, np.float64)
                     xc = np.ascontiguousarray(pc[self.perm(self.s_nodes)])

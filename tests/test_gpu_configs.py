@@ -294,3 +294,17 @@ def test_wave_colour_groups(schedule, gather, ept, tcmode):
                    tcmode=tcmode, block_colouring="recolour", wave_colour_groups=True)
         assert rel_l2(run_once(L, p), ref) <= TOL, (nx, ny)
         L.close()
+
+
+@pytest.mark.parametrize("nx,ny,S", [(200, 100, 256), (1200, 600, 512), (2400, 1200, 512)])
+def test_point_order_smallest_block_first(nx, ny, S):
+    """Points grouped by their smallest accessing block (point_reorder 2):
+    the benchmark's plan options, against the oracle."""
+    m, ref = mesh(nx, ny)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
+                     block_size=S, point_reorder=2)
+    for gather in ("registers", "lds_dma"):
+        p = L.plan("hier", S, schedule="dataflow", elems_per_thread=2, block_colouring="recolour",
+                   gather=gather)
+        assert rel_l2(run_once(L, p), ref) <= TOL, gather
+    L.close()

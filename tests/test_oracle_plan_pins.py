@@ -178,3 +178,14 @@ def test_recolour_balances_a_star():
     col, nc = plans.recolour_blocks(off, w)
     assert nc == 2 and col.tolist() == [1, 0, 0, 0, 0]
     assert plans.check_block_colouring(off, col, w)
+
+
+def test_signature_order_hand_worked_both_keys():
+    """Six points, two blocks: p0 in {1}, p1 in {0, 1}, p2 in {0}, p3 in no
+    block, p4 in {1}, p5 in {0}.  The paper's key (number of blocks, list)
+    orders 2, 5, 0, 4, 1, 3; smallest-block-first orders 2, 5, 1, 0, 4, 3;
+    ties keep the previous order and the unaccessed point goes last."""
+    blk = [0, 0, 1, 1]
+    table = np.array([[2, 5], [1, 2], [0, 1], [4, 0]])
+    assert list(plans.signature_order(blk, [table], 6)) == [2, 5, 0, 4, 1, 3]
+    assert list(plans.signature_order(blk, [table], 6, by_first_block=True)) == [2, 5, 1, 0, 4, 3]

@@ -139,10 +139,13 @@ def test_partition_is_valid_and_point_order_matches_oracle(S, geometric):
     assert np.array_equal(P.signature_order(blk, [e2n], L.N), np.arange(L.N))
 
 
-def test_partition_signature_order_exact_from_previous_numbering():
+@pytest.mark.parametrize("point_reorder", [1, 2])
+def test_partition_signature_order_exact_from_previous_numbering(point_reorder):
     """Partition without RCM: the point permutation equals the oracle's
-    signature order computed on the pre-reorder numbering."""
-    m, L = make(order="partition", block_size=128)
+    signature order computed on the pre-reorder numbering (1: the paper's
+    key; 2: smallest accessing block first)."""
+    m, L = make(order="partition", block_size=128, point_reorder=point_reorder)
+    first = point_reorder == 2
     off = L.part_blocks()
     pe = L.perm(L.s_edges)
     blk_user = np.empty(L.E, np.int64)
@@ -150,9 +153,11 @@ def test_partition_signature_order_exact_from_previous_numbering():
     # in the original numbering the accessing-block signature of each point
     # only depends on which block each edge went to
     e_in_block_order = pe  # current edge k is user edge pe[k]
-    order_c = P.signature_order(blk_user[e_in_block_order], [m.e2c[e_in_block_order]], m.n_cells)
+    order_c = P.signature_order(blk_user[e_in_block_order], [m.e2c[e_in_block_order]], m.n_cells,
+                                by_first_block=first)
     assert np.array_equal(L.perm(L.s_cells), order_c)
-    order_n = P.signature_order(blk_user[e_in_block_order], [m.e2n[e_in_block_order]], m.n_nodes)
+    order_n = P.signature_order(blk_user[e_in_block_order], [m.e2n[e_in_block_order]], m.n_nodes,
+                                by_first_block=first)
     assert np.array_equal(L.perm(L.s_nodes), order_n)
 
 
