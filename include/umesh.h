@@ -522,6 +522,23 @@ um_status um_plan_destroy(um_plan plan);
  * failure. */
 um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void *stream);
 
+/* um_loop_exec for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * executes the plan once like um_loop_exec, but the kernels' scratch memory
+ * (the DATAFLOW completion flags and control words; the UPDATE loops'
+ * per-workgroup partial sums) is a static device array of 256 KiB that the
+ * library holds on each GPU it runs on, instead of the plan's own buffers.
+ * The call allocates nothing.  Before a DATAFLOW launch the flags and control
+ * words are cleared by a kernel (so every such call is execution 1 of its
+ * own), and a give-up count of the call is added to the plan's count
+ * (um_plan_errors).  Limits: DATAFLOW plans of at most 65,471 blocks, UPDATE
+ * plans of at most 32,768 workgroups; larger plans give UM_ERR_ARG.  All
+ * calls on one GPU share the array: calls that overlap in time on one GPU
+ * (different streams, or several host threads) race and give wrong results.
+ * Other plans use no scratch and run exactly as with um_loop_exec.  Errors
+ * as um_loop_exec, and UM_ERR_ARG over the limits. */
+um_status um_loop_exec_static(um_plan plan, const double *params, int32_t nparams, void *stream);
+
 /* Autotuning: build a plan for each of the n_candidates option sets, run
  * each once untimed and then `reps` times between two HIP events on
  * `stream`, keep the fastest plan in *out and destroy the others.  The

@@ -1,5 +1,5 @@
 // C ABI of libumesh: contexts, declarations, reordering, plans, execution.
-#include <hip/hip_runtime_api.h>
+#include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
@@ -19,6 +19,13 @@ struct um_graph_s {
 };
 
 namespace um {
+
+// Device memory of um_loop_exec_static: a file-scope array that every GPU the
+// library runs on holds until the process ends.  Host code never uses the
+// array's name as an address; it uses the device address looked up once per
+// device (scratch_address) with that device current.
+constexpr int64_t STATIC_SCRATCH_BYTES = 256 * 1024;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
 
 namespace {
 thread_local std::string g_err;
@@ -57,6 +64,24 @@ um_status guarded(F &&f) {
         g_err = e.what();
         return UM_ERR_ARG;
     }
+}
+
+// Device address of `scratch` on `device` (which must be current), looked
+// up on the first call for that device and kept.
+void *scratch_address(int device) {
+    static std::mutex mu;
+    static std::vector<void *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device >= int(addr.size())) addr.resize(size_t(device) + 1, nullptr);
+    if (!addr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            fail(UM_ERR_HIP, "hipGetSymbolAddress of the static scratch on device %d: %s", device,
+                 hipGetErrorString(e));
+        addr[device] = ptr;
+    }
+    return addr[device];
 }
 
 Ctx &need(um_ctx c) {
@@ -383,6 +408,13 @@ um_status um_create(int32_t device, um_ctx *out) {
                 fail(UM_ERR_HIP, "cannot query HIP device %d", device);
             }
             c->lds_limit = int32_t(prop.sharedMemPerBlock);
+            try {
+                DeviceGuard g(device);
+                (void)scratch_address(device);
+            } catch (...) {
+                delete c;
+                throw;
+            }
         }
         *out = c;
     });
@@ -820,13 +852,49 @@ um_status um_plan_destroy(um_plan plan) {
     });
 }
 
-um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void *stream) {
-    return guarded([&] {
-        Plan &p = need(plan);
+}  // extern "C"
+
+namespace um {
+namespace {
+
+// Executes the plan once.  With use_static, the plan's scratch buffers (the
+// DATAFLOW completion flags and control words, the UPDATE partial sums) are
+// replaced by the static scratch array of the plan's device: the flags and
+// control words are cleared by a kernel first (every execution then has
+// epoch 1) and a give-up count is added to the plan's own count afterwards.
+void exec_plan(Plan &p, const double *params, int32_t nparams, void *stream, bool use_static) {
         LaunchArgs la = launch_args(p, params, nparams, stream);
         const HostPlan &hp = p.hp;
         if (hp.n_elem == 0) return;
         DeviceGuard g(p.ctx->device);
+        const bool flow = hp.strategy == UM_STRAT_HIER && hp.schedule == UM_SCHED_DATAFLOW &&
+                          !is_step_kernel(p.kernel);
+        int32_t *static_ctl = nullptr;
+        if (use_static) {
+            char *base = static_cast<char *>(scratch_address(p.ctx->device));
+            if (flow) {
+                // [control words: 256 bytes][flags: one word per launch position]
+                const int64_t words = int64_t(hp.binfo.size());
+                if (256 + 4 * words > STATIC_SCRATCH_BYTES)
+                    fail(UM_ERR_ARG, "static scratch: %lld dataflow blocks need %lld bytes, "
+                         "limit %lld", (long long)(words - 1), (long long)(256 + 4 * words),
+                         (long long)STATIC_SCRATCH_BYTES);
+                static_ctl = reinterpret_cast<int32_t *>(base);
+                la.err = static_ctl;
+                la.flags = reinterpret_cast<int32_t *>(base + 256);
+                const hipError_t e1 = zero_words(static_ctl, 4, la.stream);
+                const hipError_t e2 = zero_words(la.flags, words, la.stream);
+                if (e1 != hipSuccess || e2 != hipSuccess)
+                    fail(UM_ERR_HIP, "clearing the static scratch: %s",
+                         hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+            } else if (la.n_partials > 0) {
+                if (8 * int64_t(la.n_partials) > STATIC_SCRATCH_BYTES)
+                    fail(UM_ERR_ARG, "static scratch: %d partial sums need %lld bytes, limit %lld",
+                         la.n_partials, (long long)(8 * int64_t(la.n_partials)),
+                         (long long)STATIC_SCRATCH_BYTES);
+                la.partials = reinterpret_cast<double *>(base);
+            }
+        }
         auto one = [&](int which, int32_t b, int32_t e, int64_t lds) {
             hipEvent_t e0 = nullptr, e1 = nullptr;
             if (p.timing) {
@@ -905,7 +973,25 @@ um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void
         } else {
             one(LAUNCH_ATOMIC, 0, int32_t(hp.n_elem), 0);
         }
-    });
+        if (static_ctl) {
+            const hipError_t e = add_count(p.dp.err, static_ctl, la.stream);
+            if (e != hipSuccess)
+                fail(UM_ERR_HIP, "adding the give-up count: %s", hipGetErrorString(e));
+        }
+}
+
+}  // namespace
+}  // namespace um
+
+extern "C" {
+
+um_status um_loop_exec(um_plan plan, const double *params, int32_t nparams, void *stream) {
+    return guarded([&] { exec_plan(need(plan), params, nparams, stream, false); });
+}
+
+um_status um_loop_exec_static(um_plan plan, const double *params, int32_t nparams,
+                              void *stream) {
+    return guarded([&] { exec_plan(need(plan), params, nparams, stream, true); });
 }
 
 um_status um_plan_autotune(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t nargs,

@@ -89,6 +89,11 @@ hipError_t hex_launch_one(const LaunchArgs &la, int which, int32_t begin, int32_
 hipError_t step_launch_one(const LaunchArgs &la, int32_t kernel, int which, int32_t begin,
                            int32_t end);
 
+// p[0..n) = 0 with a kernel on `stream`.
+hipError_t zero_words(int32_t *p, int64_t n, hipStream_t stream);
+// *dst += *src (device-scope atomic) with a one-lane kernel on `stream`.
+hipError_t add_count(int32_t *dst, const int32_t *src, hipStream_t stream);
+
 // dst[k] = src[idx[k]] for k < n over dim components (gather).
 hipError_t permute_gather(const void *src, void *dst, const int32_t *idx, int64_t n, int32_t dim,
                           int32_t dtype, int32_t layout, hipStream_t stream);

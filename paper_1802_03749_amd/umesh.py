@@ -118,6 +118,7 @@ _SIGNATURES = {
     "um_plan_export": [_P, _I32, _P, _I64, _PI64],
     "um_plan_destroy": [_P],
     "um_loop_exec": [_P, _P, _I32, _P],
+    "um_loop_exec_static": [_P, _P, _I32, _P],
     "um_plan_set_timing": [_P, _I32],
     "um_plan_timing": [_P, ct.POINTER(ct.c_double), _PI64],
     "um_plan_errors": [_P, _PI32],
@@ -292,6 +293,11 @@ def um_plan_destroy(plan: int) -> None:
 def um_loop_exec(plan: int, params, stream: int) -> None:
     p = (ct.c_double * len(params))(*params)
     _check(lib().um_loop_exec(plan, p, len(params), stream), "um_loop_exec")
+
+
+def um_loop_exec_static(plan: int, params, stream: int) -> None:
+    p = (ct.c_double * len(params))(*params)
+    _check(lib().um_loop_exec_static(plan, p, len(params), stream), "um_loop_exec_static")
 
 
 def um_plan_set_timing(plan: int, enable: bool) -> None:
