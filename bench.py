@@ -36,7 +36,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "edges/s and achieved HBM GB/s (% peak) vs atomics/global-colour, FP64 and FP32"
 KERNEL_SRC = os.path.join(ROOT, "paper_1802_03749_amd", "csrc", "kernels_lf2d.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hier_kernel_2400x1200_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "edge_flux_2400x1200_traffic.json")
 
 
 def log(*a):
@@ -266,7 +266,7 @@ def main() -> int:
     ap.add_argument("--bcol", default="recolour", choices=["first_fit", "recolour"])
     ap.add_argument("--ept", type=int, default=2, choices=[1, 2],
                     help="edges per lane (the workgroup has block_size / ept lanes)")
-    ap.add_argument("--point-order", type=int, default=1, choices=[1, 2],
+    ap.add_argument("--point-order", type=int, default=2, choices=[1, 2],
                     help="1: the paper's block-signature order of points; 2: smallest "
                          "accessing block first")
     ap.add_argument("--gather", default="lds_dma", choices=["registers", "lds_dma"],
@@ -378,7 +378,8 @@ def main() -> int:
                 and tr.get("schedule") == args.schedule
                 and tr.get("elems_per_thread", 1) == args.ept
                 and tr.get("gather", "registers") == (args.gather if args.schedule == "dataflow"
-                                                      else "registers")):
+                                                      else "registers")
+                and tr.get("point_order", 1) == args.point_order):
             traffic = tr.get("bytes_per_launch")
 
     variants = {}
@@ -571,8 +572,7 @@ def main() -> int:
                 eager = time_steps(torch, B.step, bsteps, 2)
                 B.capture()
                 graph = time_steps(torch, B.replay, bsteps, 2)
-                launches = sum(sum(p.stats["n_launches"] for p in ts.plans.values())
-                               for ts in B.steps)
+                launches = B.launches_per_step()
                 bx[f"{mode}_{dt}"] = {
                     "ms_per_step_eager": eager * 1e3, "ms_per_step_graph": graph * 1e3,
                     "edges_per_s_graph": bx["interior_edges"] / graph,

@@ -110,6 +110,15 @@ class BatchedSteps:
         for ts in self.steps:
             ts.step(stream)
 
+    def launches_per_step(self) -> int:
+        """Kernel launches of one step (what step() enqueues; the adt loop
+        only before the first fused step)."""
+        n = 0
+        for ts in self.steps:
+            names = ("flux", "bres", "upa") if ts.fused else ("adt", "flux", "bres", "upd")
+            n += sum(ts.plans[k].stats["n_launches"] for k in names)
+        return n
+
     def zero_rms(self) -> None:
         for ts in self.steps:
             ts.rms.zero_()

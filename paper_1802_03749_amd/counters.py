@@ -81,15 +81,14 @@ def workload(args) -> int:
         torch.cuda.synchronize()
         B.check_errors()
         print(json.dumps({"tuned": {str(k): v[0] for k, v in B.tuned.items()},
-                          "launches_per_step": sum(p.stats["n_launches"]
-                                                   for ts in B.steps for p in ts.plans.values())}),
-              flush=True)
+                          "launches_per_step": B.launches_per_step()}), flush=True)
         B.close()
         return 0
     if args.loop == "edge":
         m = quad_mesh(args.nx, args.ny, seed=1)
         L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
-                         block_size=args.block_size, layout=args.layout)
+                         block_size=args.block_size, layout=args.layout,
+                         point_reorder=args.point_order)
         kw = dict(schedule=args.schedule, elems_per_thread=args.ept, staging=args.staging,
                   tcmode=args.tcmode, block_colouring=args.bcol)
         if args.schedule == "dataflow":
@@ -173,22 +172,26 @@ def trace_pass(args, passthrough, base):
            "--stats", "--output-format", "csv", "-d", outdir, "-o", "t", "--", sys.executable,
            "-m", "paper_1802_03749_amd.counters", "--workload", *passthrough]
     print("[counters]", " ".join(cmd), file=sys.stderr, flush=True)
-    r = subprocess.run(cmd, cwd=ROOT)
+    r = subprocess.run(cmd, cwd=ROOT, stdout=subprocess.PIPE, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"trace pass failed with status {r.returncode}")
+    wl = {}
+    for line in r.stdout.splitlines():   # the workload's one JSON line
+        if line.startswith("{"):
+            wl = json.loads(line)
     stats = {}
     for row in _kernel_stats(outdir):
         name = _kernel_key(row["Name"])
         stats[name] = (int(row["Calls"]), float(row["AverageNs"]) / 1e3,
                        float(row["MinNs"]) / 1e3, float(row["MaxNs"]) / 1e3)
-    return " ".join(cmd[4:]), stats
+    return " ".join(cmd[4:]), stats, wl
 
 
 def step_gaps(outdir: str, per_step: int, n_steps: int, skip_steps: int = 2):
-    """From the kernel trace of graph-replayed steps: each step is
-    `per_step` consecutive dispatches; the step's span (first start to last
-    end) against the sum of its kernels' durations gives the share of the
-    step spent between kernels."""
+    """From the kernel trace of graph-replayed steps: a step is the edge-flux
+    dispatch that opens it and the per_step - 1 dispatches after it; the
+    step's span (first start to last end) against the sum of its kernels'
+    durations gives the share of the step spent between kernels."""
     files = glob.glob(os.path.join(outdir, "**", "*kernel_trace.csv"), recursive=True)
     rows = []
     for fn in files:
@@ -197,15 +200,26 @@ def step_gaps(outdir: str, per_step: int, n_steps: int, skip_steps: int = 2):
                 rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]),
                              _kernel_key(r["Kernel_Name"])))
     rows.sort()
-    # the replayed steps are the last dispatches of the run
     names = [r[2] for r in rows]
-    tail = rows[-n_steps * per_step:]
-    steps = [tail[i:i + per_step] for i in range(0, len(tail), per_step)][skip_steps:]
+    fpat = r"hier_dma_kernel|hier_flow_kernel|hier_kernel|gcol_kernel|atomic_kernel"
+    flux = [i for i, k in enumerate(names) if re.search(fpat, k)]
+    # a step may hold several flux launches (colour launches): a step opens
+    # with a flux launch that follows a dispatch of another kernel; the
+    # last n_steps such openings are the replays
+    starts = [i for i in flux if i == 0 or not re.search(fpat, names[i - 1])]
+    starts = starts[-n_steps:][skip_steps:]
+    steps = [rows[i:i + per_step] for i in starts if i + per_step <= len(rows)]
     spans = [st[-1][1] - st[0][0] for st in steps]
     busy = [sum(e - b for b, e, _ in st) for st in steps]
     gaps = [sp - bu for sp, bu in zip(spans, busy)]
+    # start to start of consecutive steps: includes the time between two
+    # graph replays
+    periods = [b[0][0] - a[0][0] for a, b in zip(steps, steps[1:])]
     n = len(steps)
+    pbusy = busy[:len(periods)]
     return {"steps_analysed": n, "dispatches_per_step": per_step,
+            "mean_period_us": sum(periods) / len(periods) / 1e3 if periods else None,
+            "period_gap_share": (1 - sum(pbusy) / sum(periods)) if periods else None,
             "kernels_of_a_step": [k for _, _, k in steps[-1]] if steps else [],
             "mean_step_span_us": sum(spans) / n / 1e3 if n else None,
             "mean_kernel_time_us": sum(busy) / n / 1e3 if n else None,
@@ -220,18 +234,20 @@ def driver(args, passthrough) -> int:
     trace = None
     if args.loop == "batch":
         # the batch: kernel trace only, the gaps between the step's launches
-        tcmd, stats = trace_pass(args, passthrough, base)
+        tcmd, stats, wl = trace_pass(args, passthrough, base)
+        per_step = wl.get("launches_per_step", args.per_step)
         out = {"loop": "batch", "dtype": args.dtype, "trace_command": tcmd,
+               "tuned": wl.get("tuned"), "launches_per_step": per_step,
                "kernels": {k: {"calls": v[0], "avg_us": v[1], "min_us": v[2], "max_us": v[3]}
                            for k, v in sorted(stats.items())},
-               "gaps": step_gaps(os.path.join(base, "trace"), args.per_step, args.launches)}
+               "gaps": step_gaps(os.path.join(base, "trace"), per_step, args.launches)}
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         with open(args.out, "w") as f:
             json.dump(out, f, indent=1)
         print(json.dumps(out), flush=True)
         return 0
     if args.trace:
-        trace = trace_pass(args, passthrough, base)
+        trace = trace_pass(args, passthrough, base)[:2]
     for counter in ("FETCH_SIZE", "WRITE_SIZE"):
         outdir = os.path.join(base, counter.lower())
         cmd = ["timeout", "-s", "KILL", str(args.pass_timeout), "rocprofv3", "--pmc", counter,
@@ -267,6 +283,7 @@ def driver(args, passthrough) -> int:
         "schedule": args.schedule, "elems_per_thread": args.ept, "tcmode": args.tcmode,
         "gather": args.gather if args.loop == "edge" and args.schedule == "dataflow" else "registers",
         "mesh": f"{args.nx}x{args.ny}" if args.loop == "edge" else f"{args.n}^3",
+        "point_order": args.point_order,
         "fetch_kib_per_launch": lf, "write_kib_per_launch": lw, "launches_counted": nl,
         "fetch_scale": fetch_scale, "write_scale": write_scale,
         "bytes_per_launch": (lf * fetch_scale + lw * write_scale) * kib,
@@ -318,7 +335,8 @@ def main() -> int:
     ap.add_argument("--schedule", default="dataflow", choices=["colour_launches", "dataflow"])
     ap.add_argument("--bcol", default="recolour", choices=["first_fit", "recolour", "min"])
     ap.add_argument("--ept", type=int, default=2, choices=[1, 2])
-    ap.add_argument("--gather", default="registers", choices=["registers", "lds_dma"])
+    ap.add_argument("--gather", default="lds_dma", choices=["registers", "lds_dma"])
+    ap.add_argument("--point-order", type=int, default=2, choices=[1, 2])
     ap.add_argument("--launches", type=int, default=20)
     ap.add_argument("--trace", action="store_true",
                     help="also run a kernel-trace pass with statistics (average launch time)")
