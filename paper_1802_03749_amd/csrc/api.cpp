@@ -106,7 +106,7 @@ T *upload(const std::vector<T> &v, int64_t &bytes) {
 
 void free_device_plan(Plan &p) {
     void *bufs[13] = {p.dp.emap,  p.dp.binfo, p.dp.stg_c,    p.dp.stg_n, p.dp.loc,
-                      p.dp.crun,  p.dp.nrun,  p.dp.pred_off, p.dp.preds, p.dp.preds8,
+                      p.dp.crun,  p.dp.nrun,  p.dp.pred_off, p.dp.preds, p.dp.frec,
                       p.dp.flags, p.dp.err,   p.dp.partials};
     for (void *b : bufs)
         if (b) hipFree(b);
@@ -267,7 +267,7 @@ LaunchArgs launch_args_hex(Plan &p, const double *params, int32_t nparams, void 
     la.schedule = p.hp.schedule;
     la.pred_off = p.dp.pred_off;
     la.preds = p.dp.preds;
-    la.preds8 = p.dp.preds8;
+    la.frec = p.dp.frec;
     la.gather = p.hp.gather;
     la.flags = p.dp.flags;
     la.err = p.dp.err;
@@ -360,7 +360,7 @@ LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *str
     la.schedule = p.hp.schedule;
     la.pred_off = p.dp.pred_off;
     la.preds = p.dp.preds;
-    la.preds8 = p.dp.preds8;
+    la.frec = p.dp.frec;
     la.gather = p.hp.gather;
     la.flags = p.dp.flags;
     la.err = p.dp.err;
@@ -661,7 +661,7 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
                 if (p->hp.schedule == UM_SCHED_DATAFLOW && !p->hp.binfo.empty()) {
                     p->dp.pred_off = upload(p->hp.pred_off, bytes);
                     p->dp.preds = upload(p->hp.preds, bytes);
-                    p->dp.preds8 = upload(p->hp.preds8, bytes);
+                    p->dp.frec = upload(p->hp.frec, bytes);
                     std::vector<int32_t> zeros(p->hp.binfo.size(), 0);
                     p->dp.flags = upload(zeros, bytes);
                     std::vector<int32_t> ctl(4, 0);

@@ -128,6 +128,22 @@ struct Run {
 // explicit list.
 constexpr int32_t MAX_RUNS = 8;
 
+// Everything a DATAFLOW block of the edge loop's LDS-DMA kernel needs before
+// its first memory round trip, one record per launch position, read with
+// scalar loads: its ranges and counts, its (first 8) predecessors and the
+// run descriptors of its staged cell and node lists (ncr / nnr = 0: the
+// block reads its explicit list instead).
+struct FlowRec {
+    int32_t slot_off, cell_off, node_off, ncol;
+    int32_t ne, nc, nn, np;
+    int32_t ncr, nnr, p0, pad0;
+    int32_t preds[8];
+    Run cruns[MAX_RUNS];
+    Run nruns[MAX_RUNS];
+    int32_t pad1[12];
+};
+static_assert(sizeof(FlowRec) == 256, "FlowRec is 256 bytes");
+
 struct HostPlan {
     int32_t strategy = 0, staging = 0, tcmode = 0, block_size = 0;
     int32_t ept = 1, threads = 0;              // HIER: elements per lane, lanes per block
@@ -153,7 +169,7 @@ struct HostPlan {
     std::vector<int32_t> tcol;                 // element -> thread colour
     std::vector<int64_t> lds_per_colour;       // max LDS bytes per block colour
     std::vector<int32_t> pred_off, preds;      // DATAFLOW: earlier neighbours per position
-    std::vector<int32_t> preds8;               // DATAFLOW: [nb][8] the first 8 of them
+    std::vector<FlowRec> frec;                 // DATAFLOW edge loop: per position
     int32_t gather = 0;                        // HIER, DATAFLOW: um_gather
     int32_t wave_groups = 0;                   // HIER: colour groups padded to waves
     int32_t max_tcol = 0;
@@ -191,7 +207,7 @@ struct DevicePlan {
     Run *crun = nullptr, *nrun = nullptr;
     uint32_t *loc = nullptr;
     int32_t *pred_off = nullptr, *preds = nullptr;  // DATAFLOW
-    int32_t *preds8 = nullptr;                      // DATAFLOW: [nb][8]
+    FlowRec *frec = nullptr;                        // DATAFLOW edge loop: per position
     int32_t *flags = nullptr;                       // DATAFLOW: completion epochs per block
     int32_t *err = nullptr;                         // DATAFLOW: [timeouts, epoch of the
                                                     //  last timeout, unused x2]

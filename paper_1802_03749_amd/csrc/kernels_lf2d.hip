@@ -533,20 +533,20 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
 // DATAFLOW schedule with the gather done by LDS DMA (UM_GATHER_LDS_DMA, AoS
 // data): the loads of the staged q, adt, x and residuals write LDS directly
 // (buffer loads with the LDS bit: lane i of a wavefront lands at the
-// wavefront's LDS base + i * size), so no registers hold staged data and the
-// block waits on memory once for all of it.  The block's order of work:
-//   1. scalar loads: block descriptor, predecessor count and (up to 8)
-//      predecessor positions;
-//   2. one round trip: the block's own flag (its epoch), the predecessors'
-//      flags (every wavefront reads them itself), the run descriptors of the
-//      staged lists and this lane's local index words;
-//   3. one round trip: q, adt and x of the staged points, and the staged
-//      cells' residuals when this wavefront saw every predecessor published
-//      in step 2 (the residual loads are issued after that observation);
-//   4. fluxes from LDS; a wavefront that was not ready polls its
-//      predecessors' flags now (bounded wait) and then fetches its cells'
-//      residuals;
-//   5. thread-colour rounds into the residual accumulators, write-back with
+// wavefront's LDS base + i * size), so no registers hold staged data.  The
+// block's order of work:
+//   1. scalar loads of its 256-byte record (FlowRec): ranges, counts,
+//      predecessors and the run descriptors of its staged lists;
+//   2. one round trip: its own flag (its epoch), the predecessors' flags
+//      (every wavefront reads them itself), this lane's local index words,
+//      and the DMA of q, adt and x of the staged points (addresses from the
+//      run descriptors in scalar registers; a block with an explicit list
+//      loads its ids first);
+//   3. a wavefront that saw every predecessor published issues the DMA of
+//      its cells' residuals, then every lane evaluates its fluxes from LDS
+//      while those arrive; a wavefront that was not ready polls its
+//      predecessors (bounded wait) after its fluxes and fetches then;
+//   4. thread-colour rounds into the residual accumulators, write-back with
 //      device-scope stores, completion flag (as hier_flow_kernel).
 // LDS layout (each staged record split so that every DMA lands in 16-byte
 // lanes): residual accumulators as two arrays of (res0, res1) and (res2, res3)
@@ -574,53 +574,80 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const void *p, int64_t
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, int32_t(bytes), 0x00020000);
 }
 
+// Id at staged position t from the record's run descriptors (scalar
+// registers); nr >= 1.
+__device__ __forceinline__ int32_t run_id(const Run (&runs)[MAX_RUNS], int32_t nr, int t) {
+    int32_t g = runs[0].start + t;
+#pragma unroll
+    for (int r = 1; r < MAX_RUNS; ++r)
+        if (r < nr && t >= runs[r].local) g = runs[r].start + (t - runs[r].local);
+    return g;
+}
+
+// Id at staged position t: from the runs, or from the explicit list when the
+// record has none.  The kernel calls the list form only on code paths of
+// blocks with an explicit list: a load on a path merged with the DMA issue
+// would make every later DMA wait for all earlier ones.
+__device__ __forceinline__ int32_t rec_id(const Run (&runs)[MAX_RUNS], int32_t nr,
+                                          const int32_t *__restrict__ list, int t) {
+    return nr == 0 ? list[t] : run_id(runs, nr, t);
+}
+
 template <int TCMODE, int EPT, typename Real>
 __global__ __launch_bounds__(1024)
 __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_dma_kernel(
-    const BlockInfo *__restrict__ binfo, const int32_t *__restrict__ stg_c,
-    const int32_t *__restrict__ stg_n, const Run *__restrict__ crun, const Run *__restrict__ nrun,
-    const uint32_t *__restrict__ loc, int64_t n_slots, Dats<Real> d, double gm1d, double epsd,
-    const int32_t *__restrict__ pred_off, const int32_t *__restrict__ preds,
-    const int32_t *__restrict__ preds8, int32_t *flags, int32_t *ctl, uint64_t wait_ticks) {
+    const FlowRec *__restrict__ frec, const int32_t *__restrict__ stg_c,
+    const int32_t *__restrict__ stg_n, const uint32_t *__restrict__ loc, int64_t n_slots,
+    Dats<Real> d, double gm1d, double epsd, const int32_t *__restrict__ preds, int32_t *flags,
+    int32_t *ctl, uint64_t wait_ticks) {
     constexpr bool F64 = sizeof(Real) == 8;
     extern __shared__ double lds[];
     const int32_t pos = int32_t(blockIdx.x);
     const Real gm1 = Real(gm1d), eps = Real(epsd);
-    const BlockInfo bi = binfo[pos], bn = binfo[pos + 1];
-    const int ne = bn.slot_off - bi.slot_off;
-    const int nc = bn.cell_off - bi.cell_off;
-    const int nn = bn.node_off - bi.node_off;
-    const int ncr = bn.crun_off - bi.crun_off, nnr = bn.nrun_off - bi.nrun_off;
-    const int p0 = pred_off[pos], np = pred_off[pos + 1] - p0;
+    // ---- 1. the block's record (uniform: scalar loads)
+    const FlowRec &rec = frec[pos];
+    const int ne = rec.ne, nc = rec.nc, nn = rec.nn, np = rec.np;
+    const int ncr = rec.ncr, nnr = rec.nnr;
+    Run cruns[MAX_RUNS], nruns[MAX_RUNS];
+#pragma unroll
+    for (int k = 0; k < MAX_RUNS; ++k) {
+        cruns[k] = rec.cruns[k];
+        nruns[k] = rec.nruns[k];
+    }
+    const int32_t *__restrict__ clist = stg_c + rec.cell_off;
+    const int32_t *__restrict__ nlist = stg_n + rec.node_off;
     const int tid = int(threadIdx.x), T = int(blockDim.x), lane = tid & 63;
 
-    // ---- round trip 1: flags, run descriptors, local index words
-    const int32_t epoch =
-        __hip_atomic_load(flags + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-    int32_t pr = 0;
+    // ---- 2. flags, local index words and the gather, one round trip.  No
+    // value of these loads is used before every one of them is issued: a
+    // use makes the wavefront wait for all loads issued before it.
+    int32_t ep0 = __hip_atomic_load(flags + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int32_t pf;
     if (np <= 8) {
-        const int32_t *__restrict__ p8 = preds8 + 8 * pos;
-        pr = p8[0];
+        // predecessors from scalar registers (selecting values, not
+        // addresses: the selected address would be a vector load to wait for)
+        int32_t pk[8];
 #pragma unroll
-        for (int k = 1; k < 8; ++k) pr = lane == k ? p8[k] : pr;
-    } else if (lane < np) {
-        pr = preds[p0 + lane];
+        for (int k = 0; k < 8; ++k) {
+            pk[k] = rec.preds[k];
+            asm volatile("" : "+s"(pk[k]));
+        }
+        int32_t pr = pos;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pr = lane == k && k < np ? pk[k] : pr;
+        pf = __hip_atomic_load(flags + pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        const int32_t pr = lane < np ? preds[rec.p0 + lane] : pos;
+        pf = __hip_atomic_load(flags + pr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    const int32_t pf = lane < np ? __hip_atomic_load(flags + pr, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT)
-                                 : epoch;
-    StagedIds cell_id, node_id;
-    cell_id.init(crun, bi.crun_off, ncr, stg_c + bi.cell_off);
-    node_id.init(nrun, bi.nrun_off, nnr, stg_n + bi.node_off);
     const uint16_t *__restrict__ loc16 = reinterpret_cast<const uint16_t *>(loc + n_slots);
     uint32_t wa[EPT], wb[EPT];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const int s = tid + j * T;
-        wa[j] = s < ne ? loc[bi.slot_off + s] : 0u;
-        wb[j] = s < ne ? uint32_t(loc16[bi.slot_off + s]) : 0u;
+        wa[j] = s < ne ? loc[rec.slot_off + s] : 0u;
+        wb[j] = s < ne ? uint32_t(loc16[rec.slot_off + s]) : 0u;
     }
-    const bool ready = __all(pf == epoch);  // this wavefront's view
 
     // LDS regions
     double *r_lo = lds;                 // [nc] x (res0, res1)
@@ -635,40 +662,69 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_dma_ke
     const __amdgpu_buffer_rsrc_t rx = rsrc_of(d.x, 2 * sizeof(Real) * d.N);
     const __amdgpu_buffer_rsrc_t rres = res_rsrc(d.res, d.C);
 
-    // ---- round trip 2: staged data (and residuals when ready) into LDS
-    const int npass = nc > nn ? nc : nn;
-    for (int t0 = __builtin_amdgcn_readfirstlane(tid - lane); t0 < npass; t0 += T) {
-        const int t = t0 + lane;
-        if (t < nc) {
-            const int32_t g = cell_id(t);
-            if constexpr (F64) {
-                dma<16>(rq, q_a + 2 * t0, 32 * g);
-                dma<16>(rq, q_b + 2 * t0, 32 * g + 16);
-                dma<4>(ra, adt_w + t0, 8 * g);
-                dma<4>(ra, adt_w + nc + t0, 8 * g + 4);
-            } else {
-                dma<16>(rq, q_a + 4 * t0, 16 * g);
-                dma<4>(ra, adt_w + t0, 4 * g);
-            }
-            if (ready) {
-                dma<16, CPOL_SC1>(rres, r_lo + 2 * t0, 32 * g);
-                dma<16, CPOL_SC1>(rres, r_hi + 2 * t0, 32 * g + 16);
-            }
+    auto cell_dma = [&](int t0, int32_t g) {
+        if constexpr (F64) {
+            dma<16>(rq, q_a + 2 * t0, 32 * g);
+            dma<16>(rq, q_b + 2 * t0, 32 * g + 16);
+            dma<4>(ra, adt_w + t0, 8 * g);
+            dma<4>(ra, adt_w + nc + t0, 8 * g + 4);
+        } else {
+            dma<16>(rq, q_a + 4 * t0, 16 * g);
+            dma<4>(ra, adt_w + t0, 4 * g);
         }
-        if (t < nn) {
-            const int32_t g = node_id(t);
-            if constexpr (F64) {
-                dma<16>(rx, x_a + 2 * t0, 16 * g);
-            } else {
-                dma<4>(rx, x_a + t0, 8 * g);
-                dma<4>(rx, x_b + t0, 8 * g + 4);
-            }
+    };
+    auto node_dma = [&](int t0, int32_t g) {
+        if constexpr (F64) {
+            dma<16>(rx, x_a + 2 * t0, 16 * g);
+        } else {
+            dma<4>(rx, x_a + t0, 8 * g);
+            dma<4>(rx, x_b + t0, 8 * g + 4);
+        }
+    };
+    const int npass = nc > nn ? nc : nn;
+    const int tw = __builtin_amdgcn_readfirstlane(tid - lane);  // first position of the wave
+    if (ncr > 0 && nnr > 0) {
+        // both lists as runs: addresses from scalar registers, no loads
+        for (int t0 = tw; t0 < npass; t0 += T) {
+            const int t = t0 + lane;
+            if (t < nc) cell_dma(t0, run_id(cruns, ncr, t));
+            if (t < nn) node_dma(t0, run_id(nruns, nnr, t));
+        }
+    } else {
+        // an explicit list: each pass loads its ids, then issues its DMAs
+        for (int t0 = tw; t0 < npass; t0 += T) {
+            const int t = t0 + lane;
+            const int32_t gc = t < nc ? rec_id(cruns, ncr, clist, t) : 0;
+            const int32_t gn = t < nn ? rec_id(nruns, nnr, nlist, t) : 0;
+            if (t < nc) cell_dma(t0, gc);
+            if (t < nn) node_dma(t0, gn);
         }
     }
+    asm volatile("" : "+v"(ep0), "+v"(pf));  // every load above is issued by now
+    const int32_t epoch = ep0 + 1;
+    const bool ready = __all(lane >= np || pf == epoch);  // this wavefront's view
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    // ---- fluxes of this lane's edges from LDS into registers
+    // ---- 3. residuals of the ready wavefronts in flight during the fluxes
+    auto fetch_res = [&]() {
+        auto res_dma = [&](int t0, int32_t g) {
+            dma<16, CPOL_SC1>(rres, r_lo + 2 * t0, 32 * g);
+            dma<16, CPOL_SC1>(rres, r_hi + 2 * t0, 32 * g + 16);
+        };
+        if (ncr > 0) {
+            for (int t0 = tw; t0 < nc; t0 += T)
+                if (t0 + lane < nc) res_dma(t0, run_id(cruns, ncr, t0 + lane));
+        } else {
+            for (int t0 = tw; t0 < nc; t0 += T) {
+                const int t = t0 + lane;
+                const int32_t g = t < nc ? clist[t] : 0;
+                if (t < nc) res_dma(t0, g);
+            }
+        }
+    };
+    if (ready) fetch_res();
+
     int lL[EPT], lR[EPT], col[EPT];
     Real f[EPT][4];
 #pragma unroll
@@ -709,27 +765,30 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_dma_ke
             lf2d_flux(xa0, xa1, xb0, xb1, qL, qR, aL, aR, gm1, eps, f[j]);
         }
     }
-
-    // ---- a wavefront that was not ready waits for the earlier-coloured
-    // neighbours now, then fetches its cells' residuals
     if (!ready) {
-        if (lane < np) dev::bounded_wait(flags + pr, epoch, ctl, wait_ticks);
-        for (int t0 = __builtin_amdgcn_readfirstlane(tid - lane); t0 < nc; t0 += T) {
-            const int t = t0 + lane;
-            if (t < nc) {
-                const int32_t g = cell_id(t);
-                dma<16, CPOL_SC1>(rres, r_lo + 2 * t0, 32 * g);
-                dma<16, CPOL_SC1>(rres, r_hi + 2 * t0, 32 * g + 16);
-            }
+        // this wavefront waits for the earlier-coloured neighbours now
+        if (lane < np) {
+            int32_t pr = rec.preds[0];
+#pragma unroll
+            for (int k = 1; k < 8; ++k) pr = lane == k ? rec.preds[k] : pr;
+            if (np > 8) pr = preds[rec.p0 + lane];
+            dev::bounded_wait(flags + pr, epoch, ctl, wait_ticks);
         }
-        __builtin_amdgcn_s_waitcnt(0);
+        fetch_res();
     }
+    // the fluxes are complete before the wait for the residual DMA (an
+    // empty asm statement per value orders them before the s_waitcnt)
+#pragma unroll
+    for (int j = 0; j < EPT; ++j)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) asm volatile("" ::"v"(f[j][k]));
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
 
-    // ---- thread-colour rounds into the accumulators
+    // ---- 4. thread-colour rounds into the accumulators
     auto acc = [&](int l, int k) -> double * { return (k < 2 ? r_lo : r_hi) + 2 * l + (k & 1); };
     if constexpr (TCMODE == UM_TC_BARRIER) {
-        const int ncol = bi.ncol;
+        const int ncol = rec.ncol;
         for (int c = 0; c < ncol; ++c) {
 #pragma unroll
             for (int j = 0; j < EPT; ++j) {
@@ -758,12 +817,26 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_dma_ke
     }
 
     // ---- write-back: lane pairs store the two 16-byte halves of a cell
-    for (int u = tid; u < 2 * nc; u += T) {
-        const int t = u >> 1, h = u & 1;
+    auto store_half = [&](int t, int h, int32_t g) {
         const f64x2 v = *reinterpret_cast<const f64x2 *>((h ? r_hi : r_lo) + 2 * t);
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rres,
-                                               int32_t(32 * int64_t(cell_id(t)) + 16 * h), 0,
-                                               CPOL_SC1);
+                                               int32_t(32 * int64_t(g) + 16 * h), 0, CPOL_SC1);
+    };
+    if (ncr > 0) {
+        for (int u = tid; u < 2 * nc; u += T) store_half(u >> 1, u & 1, run_id(cruns, ncr, u >> 1));
+    } else {
+        // the ids of all this lane's cells first (a list load after a store
+        // would wait for the store)
+        int32_t g[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int u = tid + i * T;
+            g[i] = u < 2 * nc ? clist[u >> 1] : 0;
+        }
+        for (int u = tid, i = 0; u < 2 * nc; u += T, ++i) {
+            const int32_t gi = i < 4 ? g[i] : clist[u >> 1];
+            store_half(u >> 1, u & 1, gi);
+        }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
@@ -885,9 +958,8 @@ hipError_t launch_dma_one(const LaunchArgs &la, int32_t nblocks, int64_t lds,
         allow_lds(reinterpret_cast<const void *>(hier_dma_kernel<TC, EPT, Real>), lds);
     if (ea != hipSuccess) return ea;
     hipLaunchKernelGGL((hier_dma_kernel<TC, EPT, Real>), dim3(nblocks), dim3(la.block_size),
-                       size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n, la.crun, la.nrun,
-                       la.loc, la.n_slots, d, la.gm1, la.eps, la.pred_off, la.preds, la.preds8,
-                       la.flags, la.err, la.wait_ticks);
+                       size_t(lds), la.stream, la.frec, la.stg_c, la.stg_n, la.loc, la.n_slots, d,
+                       la.gm1, la.eps, la.preds, la.flags, la.err, la.wait_ticks);
     return hipGetLastError();
 }
 

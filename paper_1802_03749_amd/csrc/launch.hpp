@@ -30,7 +30,7 @@ struct LaunchArgs {
     double *out;  // debug fluxes
     int32_t schedule;
     const int32_t *pred_off, *preds;
-    const int32_t *preds8;    // DATAFLOW: [positions][8] first predecessors
+    const FlowRec *frec;      // DATAFLOW edge loop: per launch position
     int32_t gather;           // HIER, DATAFLOW: um_gather
     int32_t *flags, *err;  // DATAFLOW: completion flags; err = control words [4]
     uint64_t wait_ticks;   // DATAFLOW: longest wait for one neighbour (100 MHz ticks)

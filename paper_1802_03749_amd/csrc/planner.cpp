@@ -394,12 +394,7 @@ int32_t plan_blocks(const Ctx &ctx, int32_t iter_set, const int32_t *wt, int ari
             if (hp.pred_off[pos + 1] - hp.pred_off[pos] > 64)
                 fail(UM_ERR_UNSUPPORTED, "dataflow schedule: block %d waits on more than 64 blocks", b);
         }
-        // the first 8 predecessors of every position in a fixed-size table,
-        // read by the block with scalar loads before anything else
-        hp.preds8.assign(size_t(nb) * 8, 0);
-        for (int32_t pos = 0; pos < nb; ++pos)
-            for (int32_t i = hp.pred_off[pos], k = 0; i < hp.pred_off[pos + 1] && k < 8; ++i, ++k)
-                hp.preds8[size_t(pos) * 8 + k] = hp.preds[i];
+
     }
 
     return nbcol;
@@ -615,6 +610,27 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     hp.staged_total = int64_t(hp.stg_c.size() + hp.stg_n.size());
     hp.reuse = hp.stg_c.empty() ? 0.0 : double(2 * E) / double(hp.stg_c.size());
     hp.avg_tcol = nb ? double(tcol_sum) / nb : 0.0;
+    if (hp.schedule == UM_SCHED_DATAFLOW) {
+        hp.frec.assign(nb, FlowRec{});
+        for (int32_t pos = 0; pos < nb; ++pos) {
+            const BlockInfo &a = hp.binfo[pos], &z = hp.binfo[pos + 1];
+            FlowRec &r = hp.frec[pos];
+            r.slot_off = a.slot_off;
+            r.cell_off = a.cell_off;
+            r.node_off = a.node_off;
+            r.ncol = a.ncol;
+            r.ne = z.slot_off - a.slot_off;
+            r.nc = z.cell_off - a.cell_off;
+            r.nn = z.node_off - a.node_off;
+            r.p0 = hp.pred_off[pos];
+            r.np = hp.pred_off[pos + 1] - hp.pred_off[pos];
+            for (int32_t k = 0; k < r.np && k < 8; ++k) r.preds[k] = hp.preds[r.p0 + k];
+            r.ncr = z.crun_off - a.crun_off;
+            r.nnr = z.nrun_off - a.nrun_off;
+            for (int32_t k = 0; k < r.ncr; ++k) r.cruns[k] = hp.crun[a.crun_off + k];
+            for (int32_t k = 0; k < r.nnr; ++k) r.nruns[k] = hp.nrun[a.nrun_off + k];
+        }
+    }
 }
 
 }  // namespace um
