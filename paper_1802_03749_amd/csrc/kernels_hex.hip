@@ -113,28 +113,29 @@ __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restr
     double *s_acc = lds;           // [3][nn] force accumulators
     double *s_x = s_acc + 3 * nn;  // [3][nn]
     double *s_v = s_x + 3 * nn;    // [3][nn]
+    int32_t *s_id = reinterpret_cast<int32_t *>(s_v + 3 * nn);  // [nn] staged node ids
     const int tid = int(threadIdx.x), T = int(blockDim.x);
 
     const uint4 w = tid < ne ? loc[bi.slot_off + tid] : make_uint4(0, 0, 0, 0);
     // gather: two staged nodes per lane per pass (a block of S elements
-    // stages up to about 2 S nodes), all loads of a pass issued before its
-    // LDS stores
+    // stages up to about 2 S nodes); both ids first, then all loads of the
+    // pass, then its LDS stores (an id loaded after a data load would wait
+    // for it).  The ids stay in LDS for the write-back.
     for (int t0 = tid; t0 < nn; t0 += 2 * T) {
         const int t1 = t0 + T;
         const bool has1 = t1 < nn;
+        const int32_t g0 = staged_id(t0);
+        const int32_t g1 = has1 ? staged_id(t1) : 0;
         double xv[2][3], vv[2][3], fv[2][3];
-        {
-            const int64_t g = staged_id(t0);
-            load3<LAYOUT>(d.x, d.N, g, xv[0]);
-            load3<LAYOUT>(d.v, d.N, g, vv[0]);
-            load3<LAYOUT>(d.force, d.N, g, fv[0]);
-        }
+        load3<LAYOUT>(d.x, d.N, g0, xv[0]);
+        load3<LAYOUT>(d.v, d.N, g0, vv[0]);
+        load3<LAYOUT>(d.force, d.N, g0, fv[0]);
         if (has1) {
-            const int64_t g = staged_id(t1);
-            load3<LAYOUT>(d.x, d.N, g, xv[1]);
-            load3<LAYOUT>(d.v, d.N, g, vv[1]);
-            load3<LAYOUT>(d.force, d.N, g, fv[1]);
+            load3<LAYOUT>(d.x, d.N, g1, xv[1]);
+            load3<LAYOUT>(d.v, d.N, g1, vv[1]);
+            load3<LAYOUT>(d.force, d.N, g1, fv[1]);
         }
+        s_id[t0] = g0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             s_x[k * nn + t0] = xv[0][k];
@@ -142,6 +143,7 @@ __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restr
             s_acc[k * nn + t0] = fv[0][k];
         }
         if (has1) {
+            s_id[t1] = g1;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 s_x[k * nn + t1] = xv[1][k];
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restr
         __syncthreads();
     }
     for (int t = tid; t < nn; t += T) {
-        const int64_t g = staged_id(t);
+        const int64_t g = s_id[t];
 #pragma unroll
         for (int k = 0; k < 3; ++k) d.force[idx3<LAYOUT>(d.N, g, k)] = s_acc[k * nn + t];
     }
@@ -230,30 +232,33 @@ __global__ __launch_bounds__(1024) void hex_flow_kernel(
     double *s_acc = lds;           // [3][nn] force accumulators
     double *s_x = s_acc + 3 * nn;  // [3][nn]
     double *s_v = s_x + 3 * nn;    // [3][nn]
+    int32_t *s_id = reinterpret_cast<int32_t *>(s_v + 3 * nn);  // [nn] staged node ids
     const int tid = int(threadIdx.x), T = int(blockDim.x);
     const int p0 = pred_off[pos], np = pred_off[pos + 1] - p0;
 
     const uint4 w = tid < ne ? loc[bi.slot_off + tid] : make_uint4(0, 0, 0, 0);
+    // both ids of a pass first, then its loads (see hex_hier_kernel); the
+    // ids stay in LDS for the force accesses after the wait
     for (int t0 = tid; t0 < nn; t0 += 2 * T) {
         const int t1 = t0 + T;
         const bool has1 = t1 < nn;
+        const int32_t g0 = staged_id(t0);
+        const int32_t g1 = has1 ? staged_id(t1) : 0;
         double xv[2][3], vv[2][3];
-        {
-            const int64_t g = staged_id(t0);
-            load3<LAYOUT>(d.x, d.N, g, xv[0]);
-            load3<LAYOUT>(d.v, d.N, g, vv[0]);
-        }
+        load3<LAYOUT>(d.x, d.N, g0, xv[0]);
+        load3<LAYOUT>(d.v, d.N, g0, vv[0]);
         if (has1) {
-            const int64_t g = staged_id(t1);
-            load3<LAYOUT>(d.x, d.N, g, xv[1]);
-            load3<LAYOUT>(d.v, d.N, g, vv[1]);
+            load3<LAYOUT>(d.x, d.N, g1, xv[1]);
+            load3<LAYOUT>(d.v, d.N, g1, vv[1]);
         }
+        s_id[t0] = g0;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             s_x[k * nn + t0] = xv[0][k];
             s_v[k * nn + t0] = vv[0][k];
         }
         if (has1) {
+            s_id[t1] = g1;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 s_x[k * nn + t1] = xv[1][k];
@@ -293,7 +298,7 @@ __global__ __launch_bounds__(1024) void hex_flow_kernel(
     const __amdgpu_buffer_rsrc_t rf =
         __builtin_amdgcn_make_buffer_rsrc(d.force, 0, int32_t(24 * d.N), 0x00020000);
     auto foff = [&](int t, int k) {
-        const int64_t g = staged_id(t);
+        const int64_t g = s_id[t];
         return int32_t(8 * (LAYOUT == UM_AOS ? 3 * g + k : k * d.N + g));
     };
     for (int u = tid; u < 3 * nn; u += T) {

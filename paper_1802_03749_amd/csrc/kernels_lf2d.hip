@@ -151,10 +151,14 @@ __global__ __launch_bounds__(1024) void hier_kernel(const BlockInfo *__restrict_
     for (int t = tid; t < npass; t += T) {
         const bool hc = t < nc;
         const bool hn = STAGING == UM_STAGE_ALL && t < nn;
+        // both ids before any load of the pass: an id read from an explicit
+        // list after a data load would wait for that load
+        const int32_t gc = hc ? cell_id(t) : 0;
+        const int32_t gn = hn ? node_id(t) : 0;
         CellRegs<Real> c;
         Real xa = Real(0), xb = Real(0);
-        if (hc) fetch_cell<LAYOUT, STAGING>(d, cell_id(t), c);
-        if (hn) load2<LAYOUT>(d.x, d.N, node_id(t), xa, xb);
+        if (hc) fetch_cell<LAYOUT, STAGING>(d, gc, c);
+        if (hn) load2<LAYOUT>(d.x, d.N, gn, xa, xb);
         if (hc) put_cell<STAGING>(s_inc, s_q, s_adt, nc, t, c);
         if (hn) {
             s_x[t] = xa;
@@ -375,8 +379,19 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
     // store, so a block with more staged points than lanes still waits on
     // memory once per iteration
     const int npass = nc > nn ? nc : nn;
+    int32_t gfirst[EPT];  // cell ids of the first pass, reused for the residuals
     for (int t0 = tid; t0 < npass; t0 += EPT * T) {
         Real qv[EPT][4], av[EPT], xa[EPT], xb[EPT];
+        // all ids of the pass before any of its loads (an id read from an
+        // explicit list after a data load would wait for that load)
+        int32_t gc[EPT], gn[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int t = t0 + j * T;
+            gc[j] = t < nc ? cell_id(t) : 0;
+            gn[j] = t < nn ? node_id(t) : 0;
+            if (t0 == tid) gfirst[j] = gc[j];
+        }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             const int t = t0 + j * T;
@@ -384,11 +399,10 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
             for (int k = 0; k < 4; ++k) qv[j][k] = Real(0);
             av[j] = xa[j] = xb[j] = Real(0);
             if (t < nc) {
-                const int64_t g = cell_id(t);
-                load4<LAYOUT>(d.q, d.C, g, qv[j]);
-                av[j] = d.adt[g];
+                load4<LAYOUT>(d.q, d.C, gc[j], qv[j]);
+                av[j] = d.adt[gc[j]];
             }
-            if (t < nn) load2<LAYOUT>(d.x, d.N, node_id(t), xa[j], xb[j]);
+            if (t < nn) load2<LAYOUT>(d.x, d.N, gn[j], xa[j], xb[j]);
         }
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
@@ -415,7 +429,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
     for (int j = 0; j < EPT; ++j) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) r0[j][k] = 0.0;
-        if (ready && tid + j * T < nc) load4_dev<LAYOUT>(rres, d.C, cell_id(tid + j * T), r0[j]);
+        if (ready && tid + j * T < nc) load4_dev<LAYOUT>(rres, d.C, gfirst[j], r0[j]);
     }
 
     // fluxes of this lane's edges into registers

@@ -11,7 +11,8 @@
 
 namespace um {
 
-int64_t hex_lds_bytes(int64_t nn) { return nn * 9 * 8; }  // x[3], v[3], force acc[3]
+// x[3], v[3], force acc[3] and the staged node id
+int64_t hex_lds_bytes(int64_t nn) { return nn * (9 * 8 + 4); }
 
 int64_t lf2d_lds_bytes(int32_t staging, int32_t dtype, int64_t nc, int64_t nn) {
     const int64_t inc = nc * 4 * 8;  // FP64 increments (res preloaded)
