@@ -97,7 +97,7 @@ def workload(args) -> int:
     else:
         m = hex_mesh(args.n, seed=1)
         L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=args.block_size,
-                    layout=args.layout)
+                    layout=args.layout, point_reorder=args.point_order)
         p = L.plan("hier", args.block_size, block_colouring="min", schedule=args.schedule,
                    tcmode=args.tcmode)
     for _ in range(args.launches):
@@ -280,7 +280,8 @@ def driver(args, passthrough) -> int:
         "loop": args.loop,
         "kernel_source_sha256": source_sha(args.loop),
         "block_size": args.block_size, "layout": args.layout, "staging": args.staging,
-        "schedule": args.schedule, "elems_per_thread": args.ept, "tcmode": args.tcmode,
+        "schedule": args.schedule, "elems_per_thread": args.ept if args.loop == "edge" else 1,
+        "tcmode": args.tcmode,
         "gather": args.gather if args.loop == "edge" and args.schedule == "dataflow" else "registers",
         "mesh": f"{args.nx}x{args.ny}" if args.loop == "edge" else f"{args.n}^3",
         "point_order": args.point_order,
