@@ -48,8 +48,10 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def time_steps(torch, run, steps: int, warmup: int) -> float:
-    """Seconds per step over `steps` timed steps after `warmup` untimed."""
+def time_steps(torch, run, steps: int, warmup: int, settle_s: float = 0.05) -> float:
+    """Seconds per step over `steps` timed steps after `warmup` untimed (and,
+    before those, untimed executions for about settle_s seconds)."""
+    settle(torch, run, settle_s)
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()
@@ -61,6 +63,16 @@ def time_steps(torch, run, steps: int, warmup: int) -> float:
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) * 1e-3 / steps
+
+
+def settle(torch, run, seconds: float) -> None:
+    """Untimed executions for about `seconds`, so that timing does not start
+    on a GPU that idled through host-side setup (plan builds, uploads)."""
+    until = time.perf_counter() + seconds
+    while time.perf_counter() < until:
+        for _ in range(20):
+            run()
+        torch.cuda.synchronize()
 
 
 def copy_probe(torch, nbytes: int = 512 << 20, reps: int = 20):
@@ -162,7 +174,7 @@ def run_sweep(torch, args, U):
         log(f"sweep {order} done")
     for S in sizes:
         L = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0,
-                         order="rcm+partition", block_size=S)
+                         order="rcm+partition", block_size=S, point_reorder=args.point_order)
         for strat in ("atomic", "global"):
             ent[f"rcm+partition/{strat}/S{S}"] = timed(L, L.plan(strat, S))
         hier_entries(L, "rcm+partition", S, (cl, df))
@@ -215,7 +227,7 @@ def run_ablations(torch, mesh, S, args, useful, E):
     for name, order, kw in parts:
         for layout in ("aos", "soa"):
             L = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0, order=order,
-                             block_size=S, layout=layout, **kw)
+                             block_size=S, layout=layout, point_reorder=args.point_order, **kw)
             kw0 = dict(base)
             if layout == "soa" and "gather" in kw0:
                 kw0["gather"] = "registers"   # the LDS-DMA gather reads AoS records
@@ -239,6 +251,13 @@ def run_ablations(torch, mesh, S, args, useful, E):
                     except Exception as e:  # an unsupported combination
                         out[f"hier_partition_{knob}_{val}"] = {"error": str(e)}
             L.close()
+            if name == "recursive_bisection" and layout == args.layout:
+                # the other point order (a property of the renumbered mesh)
+                po = 3 - args.point_order
+                L = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0,
+                                 order=order, block_size=S, layout=layout, point_reorder=po)
+                out[f"hier_partition_point_order_{po}"] = entry(L, L.plan("hier", S, **base))
+                L.close()
             log(f"ablation {name} {layout} done")
     for order in ("none", "rcm", "gps", "rcm+partition"):
         for layout in ("aos", "soa"):
@@ -327,13 +346,7 @@ def main() -> int:
         f"block colours={st['n_block_colours']} thread colours<={st['max_thread_colours']} "
         f"reuse={st['reuse_factor']:.3f} lds={st['lds_bytes_max']} launches={st['n_launches']}")
     run = lambda: hier.run(plan)
-    # settle: about 0.3 s of untimed executions first, so that the timed
-    # steps do not start on a GPU that idled through the host-side setup
-    settle_until = time.perf_counter() + 0.3
-    while time.perf_counter() < settle_until:
-        for _ in range(100):
-            run()
-        torch.cuda.synchronize()
+    settle(torch, run, 0.3)
     sec = time_steps(torch, run, args.steps, args.warmup)
     if U.um_plan_errors(plan.handle) != 0:
         log("a dataflow wait timed out: the timed results are invalid")
