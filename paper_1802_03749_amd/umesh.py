@@ -152,8 +152,8 @@ def lib() -> ct.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1802_03749_amd.build` "
-                               "(or __graft_entry__.build())")
+            raise RuntimeError(f"{LIB_PATH} is not built: run "
+                               "`python -m paper_1802_03749_amd.build`")
         L = ct.CDLL(LIB_PATH)
         for name, argtypes in _SIGNATURES.items():
             fn = getattr(L, name)
