@@ -13,7 +13,10 @@ against the CPU oracle:
   time step in binary64 and binary32 storage, every mesh against its own
   oracle step;
 * the dataflow schedule's error path: waits forced to give up are counted,
-  every kernel exits, and later executions wait normally again.
+  every kernel exits, and later executions wait normally again;
+* the LDS-DMA gather, wave-pure colour groups and the smallest-block-first
+  point order, and the benchmark's plan on empty, single-edge, ragged and
+  free-stream meshes.
 
 Bar as elsewhere: relative L2 <= 1e-12 in binary64, 1e-6 for binary32
 storage against the oracle's binary32 evaluation.
@@ -307,4 +310,44 @@ def test_point_order_smallest_block_first(nx, ny, S):
         p = L.plan("hier", S, schedule="dataflow", elems_per_thread=2, block_colouring="recolour",
                    gather=gather)
         assert rel_l2(run_once(L, p), ref) <= TOL, gather
+    L.close()
+
+
+# ------------------------------------- the benchmark's plan on edge cases
+HEADLINE = dict(schedule="dataflow", elems_per_thread=2, block_colouring="recolour",
+                gather="lds_dma")
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 2), (3, 1), (7, 5), (33, 17), (129, 65)])
+def test_headline_plan_tiny_and_ragged(nx, ny):
+    """The benchmark's plan options (512-edge blocks, smallest-block-first
+    point order, dataflow schedule, two edges per lane, LDS-DMA gather) on
+    meshes with no interior edge, a single edge, and edge counts that are not
+    a multiple of anything: a single partly filled block, ragged passes."""
+    m = quad_mesh(nx, ny, seed=7)
+    ref = native.edge_loop(m.e2n, m.e2c, m.x, m.q, m.adt)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
+                     block_size=512, point_reorder=2)
+    for tcmode in ("barrier", "lds_atomic"):
+        p = L.plan("hier", 512, tcmode=tcmode, **HEADLINE)
+        r = run_once(L, p)
+        if m.e2n.shape[0] == 0:
+            assert np.all(r == 0.0)
+        else:
+            assert rel_l2(r, ref) <= TOL, tcmode
+    L.close()
+
+
+def test_headline_plan_free_stream_exact_zero():
+    """A uniform dyadic state gives exactly 0.0 interior residuals with the
+    benchmark's plan too, whatever the order of additions."""
+    from meshgen import free_stream_state
+    m = quad_mesh(150, 90, seed=3, state=free_stream_state("p1"))
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
+                     block_size=512, point_reorder=2)
+    p = L.plan("hier", 512, **HEADLINE)
+    r = run_once(L, p)
+    i, j = m.cell_nat % m.nx, m.cell_nat // m.nx
+    inner = (i > 0) & (i < m.nx - 1) & (j > 0) & (j < m.ny - 1)
+    assert np.all(r[inner] == 0.0)
     L.close()
