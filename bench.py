@@ -253,7 +253,7 @@ def run_ablations(torch, mesh, S, args, useful, E):
             L.close()
             if name == "recursive_bisection" and layout == args.layout:
                 # the other point order (a property of the renumbered mesh)
-                po = 3 - args.point_order
+                po = 1 if args.point_order != 1 else 2
                 L = EdgeFluxLoop(mesh.x, mesh.q, mesh.adt, mesh.e2n, mesh.e2c, device=0,
                                  order=order, block_size=S, layout=layout, point_reorder=po)
                 out[f"hier_partition_point_order_{po}"] = entry(L, L.plan("hier", S, **base))
@@ -285,9 +285,11 @@ def main() -> int:
     ap.add_argument("--bcol", default="recolour", choices=["first_fit", "recolour"])
     ap.add_argument("--ept", type=int, default=2, choices=[1, 2],
                     help="edges per lane (the workgroup has block_size / ept lanes)")
-    ap.add_argument("--point-order", type=int, default=2, choices=[1, 2],
+    ap.add_argument("--point-order", type=int, default=2, choices=[1, 2, 3],
                     help="1: the paper's block-signature order of points; 2: smallest "
-                         "accessing block first")
+                         "accessing block first; 3: accessing blocks from the largest down")
+    ap.add_argument("--hex-point-order", type=int, default=3, choices=[1, 2, 3],
+                    help="point order of the hex loop's hierarchical plans")
     ap.add_argument("--gather", default="lds_dma", choices=["registers", "lds_dma"],
                     help="dataflow gather: through registers, or loads that write LDS directly")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -493,8 +495,8 @@ def main() -> int:
         hx = {"elements": hm.n_elems, "nodes": hm.n_nodes, "useful_bytes_per_step": hb}
         # hierarchical in the headline layout (dataflow schedule at 256
         # elements per block; one launch per block colour at 512 as a
-        # variant); the baselines in their best layout (atomics run far
-        # faster on SoA data)
+        # variant), points ordered by --hex-point-order; the baselines in
+        # their best layout (atomics run far faster on SoA data)
         for order, strat, hS, layouts in (("rcm+partition", "hier", 256, (args.layout,)),
                                           ("rcm+partition", "hier_colour_launches", 512,
                                            (args.layout,)),
@@ -503,7 +505,7 @@ def main() -> int:
             runs = {}
             for lay in layouts:
                 H = HexLoop(hm.x, hm.v, hm.e2n, device=0, order=order, block_size=hS,
-                            layout=lay)
+                            layout=lay, point_reorder=args.hex_point_order)
                 if strat == "hier":
                     p = H.plan("hier", hS, block_colouring="min", schedule="dataflow")
                 elif strat == "hier_colour_launches":
@@ -515,6 +517,7 @@ def main() -> int:
                     log("a hex dataflow wait timed out: the timed results are invalid")
                     return 3
                 runs[lay] = {"order": order, "layout": lay, "block_size": hS,
+                             "point_order": args.hex_point_order if "hier" in strat else None,
                              "elements_per_s": hm.n_elems / s, "ms_per_step": s * 1e3,
                              "useful_gbps": hb / s / 1e9, "launches": p.stats["n_launches"],
                              "block_colours": p.stats["n_block_colours"]}
@@ -656,7 +659,8 @@ def main() -> int:
             "cells": C, "nodes": N, "edges": E,
             "strategy": "hierarchical two-layer colouring",
             "order": "rcm+partition+point-reorder",
-            "point_order": "block signature" if args.point_order == 1 else "smallest block first",
+            "point_order": {1: "block signature", 2: "smallest block first",
+                            3: "blocks from the largest down"}[args.point_order],
             "block_size": S, "layout": args.layout, "staging": args.staging,
             "tcmode": args.tcmode, "schedule": args.schedule, "block_colouring": args.bcol,
             "edges_per_lane": args.ept,

@@ -268,7 +268,12 @@ typedef struct {
                               smallest accessing block first, then number
                               and list (an extension: each block's own
                               points and the halo it shares with later
-                              blocks form one run)                          */
+                              blocks form one run); 3 = by the list of
+                              accessing blocks taken from the largest down,
+                              element by element, a prefix first (an
+                              extension: halo groups whose last blocks
+                              agree lie side by side, so fewer cache lines
+                              hold points of unrelated blocks)              */
     int32_t coord_map;     /* PARTITION, optional: map from the partitioned set
                               whose to-set carries `coords`; -1 = none, then
                               a graph-distance embedding is used instead     */
@@ -445,8 +450,9 @@ um_status um_set_dat_ptr(um_ctx ctx, int32_t dat, void *device_ptr);
  *     blocks end up at most block_size.  Elements are renumbered block by
  *     block, keeping their previous relative order inside a block.  With
  *     point_reorder, every to-set of a map from the from-set is renumbered
- *     by (number of accessing blocks, list of accessing blocks), or with
- *     point_reorder = 2 by (smallest accessing block, number, list), ties
+ *     by (number of accessing blocks, list of accessing blocks), with
+ *     point_reorder = 2 by (smallest accessing block, number, list), or with
+ *     point_reorder = 3 by the accessing blocks from the largest down, ties
  *     keeping the previous order.  The blocks are remembered
  *     and used by HIER plans with the same block_size, or with a multiple
  *     k * block_size (k consecutive blocks form one plan block).

@@ -336,12 +336,16 @@ def first_touch(table_in_order, n_points: int) -> np.ndarray:
     return np.array(order, np.int64)
 
 
-def signature_order(block_of_elem, tables, n_points: int, by_first_block: bool = False) -> np.ndarray:
+def signature_order(block_of_elem, tables, n_points: int, by_first_block: bool = False,
+                    by_blocks_descending: bool = False) -> np.ndarray:
     """new->old: stable sort of points by (#accessing blocks, sorted block list)
     (Section 2.3.2's cache-line heuristic); with by_first_block, by (smallest
     accessing block, #accessing blocks, list), the extension that keeps each
-    block's points and the halo it shares with later blocks together.
-    Points no block accesses go last either way."""
+    block's points and the halo it shares with later blocks together; with
+    by_blocks_descending, by the list of accessing blocks taken from the
+    largest down, compared element by element (a list that is a prefix of
+    another comes first), a second extension.  Points no block accesses go
+    last in every case."""
     acc = [set() for _ in range(n_points)]
     blk = np.asarray(block_of_elem)
     for t in tables:
@@ -351,6 +355,8 @@ def signature_order(block_of_elem, tables, n_points: int, by_first_block: bool =
                 acc[p].add(int(blk[e]))
     def key(p):
         s = sorted(acc[p])
+        if by_blocks_descending:
+            return (0 if s else 1, list(reversed(s)))
         k = (len(s) if s else float("inf"), s)
         return ((s[0] if s else float("inf")),) + k if by_first_block else k
     return np.array(sorted(range(n_points), key=key), np.int64)

@@ -335,9 +335,9 @@ def main() -> int:
     ap.add_argument("--tcmode", default="barrier", choices=["barrier", "lds_atomic"])
     ap.add_argument("--schedule", default="dataflow", choices=["colour_launches", "dataflow"])
     ap.add_argument("--bcol", default="recolour", choices=["first_fit", "recolour", "min"])
-    ap.add_argument("--ept", type=int, default=2, choices=[1, 2])
+    ap.add_argument("--ept", type=int, default=2, choices=[1, 2, 3])
     ap.add_argument("--gather", default="lds_dma", choices=["registers", "lds_dma"])
-    ap.add_argument("--point-order", type=int, default=2, choices=[1, 2])
+    ap.add_argument("--point-order", type=int, default=2, choices=[1, 2, 3])
     ap.add_argument("--launches", type=int, default=20)
     ap.add_argument("--trace", action="store_true",
                     help="also run a kernel-trace pass with statistics (average launch time)")

@@ -70,12 +70,13 @@ std::vector<int32_t> partition_elements(const Ctx &ctx, int32_t drv, int32_t blo
                                         int32_t coord_map, int32_t coord_dim,
                                         const double *coords, std::vector<int32_t> &block_off,
                                         std::vector<int32_t> &block_code);
-// Points of to-set `set` sorted by (number of accessing blocks, list of
-// accessing blocks), stable; with by_first_block, by (smallest accessing
-// block, number, list); elements of `from` are in block order.
+// Points of to-set `set` sorted, stably, by key 1: (number of accessing
+// blocks, list of accessing blocks); key 2: (smallest accessing block,
+// number, list); key 3: the accessing blocks from the largest down, element
+// by element (a prefix first).  Unaccessed points last; elements of `from`
+// are in block order.
 std::vector<int32_t> signature_order(const Ctx &ctx, int32_t from, int32_t set,
-                                     const std::vector<int32_t> &block_of_elem,
-                                     bool by_first_block);
+                                     const std::vector<int32_t> &block_of_elem, int32_t key);
 // Renumber `set` by new->old `perm`: rewrites every map from or into it.
 void apply_set_perm(Ctx &ctx, int32_t set, const std::vector<int32_t> &perm);
 

@@ -399,8 +399,7 @@ std::vector<int32_t> partition_elements(const Ctx &ctx, int32_t drv, int32_t blo
 }
 
 std::vector<int32_t> signature_order(const Ctx &ctx, int32_t from, int32_t set,
-                                     const std::vector<int32_t> &block_of_elem,
-                                     bool by_first_block) {
+                                     const std::vector<int32_t> &block_of_elem, int32_t key) {
     const int64_t n = ctx.sets[set].size;
     const int64_t ne = ctx.sets[from].size;
     // accessing blocks per point; elements are visited in block order so each
@@ -429,7 +428,18 @@ std::vector<int32_t> signature_order(const Ctx &ctx, int32_t from, int32_t set,
     std::vector<int32_t> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        if (by_first_block) {
+        if (key == 3) {
+            // the accessing blocks from the largest down, element by element
+            // (a prefix first); unaccessed points last
+            if (!len[a] || !len[b]) return len[a] != 0 && len[b] == 0;
+            const int64_t m = std::min(len[a], len[b]);
+            for (int64_t i = 1; i <= m; ++i) {
+                const int32_t x = lst[cnt[a] + len[a] - i], y = lst[cnt[b] + len[b] - i];
+                if (x != y) return x < y;
+            }
+            return len[a] < len[b];
+        }
+        if (key == 2) {
             // smallest accessing block first; unaccessed points last
             const int64_t fa = len[a] ? lst[cnt[a]] : INT64_MAX;
             const int64_t fb = len[b] ? lst[cnt[b]] : INT64_MAX;
@@ -510,8 +520,8 @@ void reorder_mesh(Ctx &ctx, const um_reorder_opts &o) {
     ctx.sets[F].part_block_size = o.block_size;
     ctx.sets[F].part_off = off;
     ctx.sets[F].part_code = code;
-    if (o.point_reorder < 0 || o.point_reorder > 2)
-        fail(UM_ERR_ARG, "reorder: point_reorder %d not in 0..2", o.point_reorder);
+    if (o.point_reorder < 0 || o.point_reorder > 3)
+        fail(UM_ERR_ARG, "reorder: point_reorder %d not in 0..3", o.point_reorder);
     if (o.point_reorder) {
         std::vector<int32_t> blk(ctx.sets[F].size);
         for (size_t b = 0; b + 1 < off.size(); ++b)
@@ -521,7 +531,7 @@ void reorder_mesh(Ctx &ctx, const um_reorder_opts &o) {
             const Map &m = ctx.maps[i];
             if (m.from != F || std::find(done.begin(), done.end(), m.to) != done.end()) continue;
             done.push_back(m.to);
-            apply_set_perm(ctx, m.to, signature_order(ctx, F, m.to, blk, o.point_reorder == 2));
+            apply_set_perm(ctx, m.to, signature_order(ctx, F, m.to, blk, o.point_reorder));
         }
     }
 }

@@ -455,14 +455,16 @@ def test_hex_lds_atomic_rounds(layout):
     assert rel_l2(L.force_user(), ref) <= TOL
 
 
+@pytest.mark.parametrize("po", [1, 3])
 @pytest.mark.parametrize("layout", ["aos", "soa"])
 @pytest.mark.parametrize("tcmode", ["barrier", "lds_atomic"])
-def test_hex_dataflow(layout, tcmode):
+def test_hex_dataflow(layout, tcmode, po):
     """The hex loop's dataflow schedule: one launch, results equal to the
     colour-launch plan to rounding, reproducible, and replayable from a HIP
     graph (every replay adds one more loop's forces)."""
     m, ref = hexmesh(24)
-    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=256, layout=layout)
+    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=256, layout=layout,
+                point_reorder=po)
     p = L.plan("hier", 256, block_colouring="min", tcmode=tcmode, schedule="dataflow")
     assert p.stats["n_launches"] == 1
     outs = []
@@ -479,9 +481,11 @@ def test_hex_dataflow(layout, tcmode):
     assert U.um_plan_errors(p.handle) == 0
 
 
-def test_hex_dataflow_full_size():
+@pytest.mark.parametrize("po", [1, 3])
+def test_hex_dataflow_full_size(po):
     m, ref = hexmesh(128)
-    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=256)
+    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=256,
+                point_reorder=po)
     p = L.plan("hier", 256, block_colouring="min", schedule="dataflow")
     L.run(p)
     torch.cuda.synchronize()

@@ -189,3 +189,16 @@ def test_signature_order_hand_worked_both_keys():
     table = np.array([[2, 5], [1, 2], [0, 1], [4, 0]])
     assert list(plans.signature_order(blk, [table], 6)) == [2, 5, 0, 4, 1, 3]
     assert list(plans.signature_order(blk, [table], 6, by_first_block=True)) == [2, 5, 1, 0, 4, 3]
+
+
+def test_signature_order_hand_worked_three_keys():
+    """Five points, three blocks (one element each): p0 in {0, 2}, p1 in {1},
+    p2 in {0, 1}, p3 in {2}, p4 in no block.  The paper's key orders
+    1, 3, 2, 0, 4; smallest-block-first 2, 0, 1, 3, 4; the blocks from the
+    largest down ((1), (1, 0), (2), (2, 0)) give 1, 2, 3, 0, 4."""
+    blk = [0, 1, 2]
+    table = np.array([[0, 2], [1, 2], [0, 3]])
+    assert list(plans.signature_order(blk, [table], 5)) == [1, 3, 2, 0, 4]
+    assert list(plans.signature_order(blk, [table], 5, by_first_block=True)) == [2, 0, 1, 3, 4]
+    assert list(plans.signature_order(blk, [table], 5, by_blocks_descending=True)) == \
+        [1, 2, 3, 0, 4]

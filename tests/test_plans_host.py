@@ -139,13 +139,14 @@ def test_partition_is_valid_and_point_order_matches_oracle(S, geometric):
     assert np.array_equal(P.signature_order(blk, [e2n], L.N), np.arange(L.N))
 
 
-@pytest.mark.parametrize("point_reorder", [1, 2])
+@pytest.mark.parametrize("point_reorder", [1, 2, 3])
 def test_partition_signature_order_exact_from_previous_numbering(point_reorder):
     """Partition without RCM: the point permutation equals the oracle's
     signature order computed on the pre-reorder numbering (1: the paper's
-    key; 2: smallest accessing block first)."""
+    key; 2: smallest accessing block first; 3: blocks from the largest
+    down)."""
     m, L = make(order="partition", block_size=128, point_reorder=point_reorder)
-    first = point_reorder == 2
+    kw = dict(by_first_block=point_reorder == 2, by_blocks_descending=point_reorder == 3)
     off = L.part_blocks()
     pe = L.perm(L.s_edges)
     blk_user = np.empty(L.E, np.int64)
@@ -154,10 +155,10 @@ def test_partition_signature_order_exact_from_previous_numbering(point_reorder):
     # only depends on which block each edge went to
     e_in_block_order = pe  # current edge k is user edge pe[k]
     order_c = P.signature_order(blk_user[e_in_block_order], [m.e2c[e_in_block_order]], m.n_cells,
-                                by_first_block=first)
+                                **kw)
     assert np.array_equal(L.perm(L.s_cells), order_c)
     order_n = P.signature_order(blk_user[e_in_block_order], [m.e2n[e_in_block_order]], m.n_nodes,
-                                by_first_block=first)
+                                **kw)
     assert np.array_equal(L.perm(L.s_nodes), order_n)
 
 
