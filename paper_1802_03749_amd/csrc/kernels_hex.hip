@@ -202,13 +202,16 @@ __global__ __launch_bounds__(1024) void hex_hier_kernel(const BlockInfo *__restr
 
 // DATAFLOW schedule of the hex loop (the protocol of hier_flow_kernel in
 // kernels_lf2d.hip: one launch over all blocks in colour order; a block
-// gathers x and v and computes its forces, waits until the completion flags
-// of its earlier-coloured neighbours hold this execution's epoch (its own
-// flag + 1), then loads, updates and stores the force accumulators of its
-// staged nodes with device-scope (sc1) accesses and publishes its flag).
-// Force accesses go through a buffer resource over force (24 N bytes);
-// with AoS, consecutive lanes handle consecutive doubles, so one instruction
-// covers whole lines of a run of consecutive nodes.
+// gathers x and v, computes its forces and sums them per staged node in LDS
+// (thread-colour rounds or LDS atomics into zeroed accumulators), waits
+// until the completion flags of its earlier-coloured neighbours hold this
+// execution's epoch (its own flag + 1), then adds its sums to the force
+// values of its staged nodes with device-scope (sc1) loads and stores and
+// publishes its flag).  With 8 block colours the sweep is a chain of 8
+// blocks deep, so only the global read-add-write follows the wait.  Force
+// accesses go through a buffer resource over force (24 N bytes); with AoS,
+// consecutive lanes handle consecutive doubles, so one instruction covers
+// whole lines of a run of consecutive nodes.
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 constexpr int HEX_CPOL_SC1 = 16;
 
@@ -237,6 +240,7 @@ __global__ __launch_bounds__(1024) void hex_flow_kernel(
     const int p0 = pred_off[pos], np = pred_off[pos + 1] - p0;
 
     const uint4 w = tid < ne ? loc[bi.slot_off + tid] : make_uint4(0, 0, 0, 0);
+    for (int u = tid; u < 3 * nn; u += T) s_acc[u] = 0.0;
     // both ids of a pass first, then its loads (see hex_hier_kernel); the
     // ids stay in LDS for the force accesses after the wait
     for (int t0 = tid; t0 < nn; t0 += 2 * T) {
@@ -287,28 +291,7 @@ __global__ __launch_bounds__(1024) void hex_flow_kernel(
         hex_force(xe, ve, kappa, f);
     }
 
-    // wait for the earlier-coloured neighbours (np <= 64: first wavefront)
-    if (tid < np) {
-        const int32_t *fl = flags + preds[p0 + tid];
-        dev::bounded_wait(fl, epoch, ctl, wait_ticks);
-    }
-    __syncthreads();
-
-    // force accumulators: device-scope loads
-    const __amdgpu_buffer_rsrc_t rf =
-        __builtin_amdgcn_make_buffer_rsrc(d.force, 0, int32_t(24 * d.N), 0x00020000);
-    auto foff = [&](int t, int k) {
-        const int64_t g = s_id[t];
-        return int32_t(8 * (LAYOUT == UM_AOS ? 3 * g + k : k * d.N + g));
-    };
-    for (int u = tid; u < 3 * nn; u += T) {
-        const int t = LAYOUT == UM_AOS ? u / 3 : u % nn;
-        const int k = LAYOUT == UM_AOS ? u % 3 : u / nn;
-        s_acc[k * nn + t] = __builtin_bit_cast(
-            double, __builtin_amdgcn_raw_buffer_load_b64(rf, foff(t, k), 0, HEX_CPOL_SC1));
-    }
-    __syncthreads();
-
+    // the block's sums per staged node, before the wait
     if constexpr (TCMODE == UM_TC_BARRIER) {
         const int ncol = bi.ncol;
         for (int c = 0; c < ncol; ++c) {
@@ -330,12 +313,41 @@ __global__ __launch_bounds__(1024) void hex_flow_kernel(
         __syncthreads();
     }
 
-    // device-scope stores, consecutive lanes on consecutive doubles
-    for (int u = tid; u < 3 * nn; u += T) {
-        const int t = LAYOUT == UM_AOS ? u / 3 : u % nn;
-        const int k = LAYOUT == UM_AOS ? u % 3 : u / nn;
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, s_acc[k * nn + t]), rf,
-                                              foff(t, k), 0, HEX_CPOL_SC1);
+    // wait for the earlier-coloured neighbours (np <= 64: first wavefront)
+    if (tid < np) {
+        const int32_t *fl = flags + preds[p0 + tid];
+        dev::bounded_wait(fl, epoch, ctl, wait_ticks);
+    }
+    __syncthreads();
+
+    // force += sums: device-scope loads (up to 8 per lane in flight), adds,
+    // device-scope stores
+    const __amdgpu_buffer_rsrc_t rf =
+        __builtin_amdgcn_make_buffer_rsrc(d.force, 0, int32_t(24 * d.N), 0x00020000);
+    auto foff = [&](int t, int k) {
+        const int64_t g = s_id[t];
+        return int32_t(8 * (LAYOUT == UM_AOS ? 3 * g + k : k * d.N + g));
+    };
+    constexpr int FB = 8;
+    for (int u0 = tid; u0 < 3 * nn; u0 += FB * T) {
+        double g[FB];
+        int32_t off[FB], li[FB];
+#pragma unroll
+        for (int j = 0; j < FB; ++j) {
+            const int u = u0 + j * T;
+            const int t = LAYOUT == UM_AOS ? u / 3 : u % nn;
+            const int k = LAYOUT == UM_AOS ? u % 3 : u / nn;
+            li[j] = k * nn + t;
+            off[j] = u < 3 * nn ? foff(t, k) : 0;
+            g[j] = u < 3 * nn ? __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
+                                                              rf, off[j], 0, HEX_CPOL_SC1))
+                              : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < FB; ++j)
+            if (u0 + j * T < 3 * nn)
+                __builtin_amdgcn_raw_buffer_store_b64(
+                    __builtin_bit_cast(u32x2, g[j] + s_acc[li[j]]), rf, off[j], 0, HEX_CPOL_SC1);
     }
     // publish: every lane's stores complete, then one flag store
     __builtin_amdgcn_s_waitcnt(0);
