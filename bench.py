@@ -238,7 +238,7 @@ def run_ablations(torch, mesh, S, args, useful, E):
                                   ("schedule", "colour_launches"), ("schedule", "dataflow"),
                                   ("elems_per_thread", 1), ("elems_per_thread", 2),
                                   ("gather", "registers"), ("gather", "lds_dma"),
-                                  ("wave_colour_groups", True)):
+                                  ("wave_colour_groups", True), ("xcd_groups", 8)):
                     if base.get(knob) == val:
                         continue
                     o = dict(base); o[knob] = val

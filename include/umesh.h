@@ -314,7 +314,22 @@ typedef struct {
                                   part in one colour round only (more lanes
                                   per block: UM_ERR_ARG when the padded slots
                                   exceed 1024 * elems_per_thread)           */
-    int32_t reserved[2];
+    int32_t xcd_groups;        /* HIER, edge and hex loops: 0 or 1 = blocks
+                                  launched in colour order as planned;
+                                  G = 2..64: the blocks form G equal ranges
+                                  of block ids (regions of space in
+                                  partition order) and inside each block
+                                  colour the k-th workgroup of its launch
+                                  takes a block of range k mod G while that
+                                  range has blocks left in the colour.  With
+                                  G = 8 on MI355X, which hands consecutive
+                                  workgroups of a launch to its 8 XCDs in
+                                  turn, each region runs on one XCD and its
+                                  blocks share that XCD's L2.  Launch order
+                                  only: every block still follows the blocks
+                                  of smaller colour around it, so barrier
+                                  rounds give bitwise the same results      */
+    int32_t reserved[1];
 } um_plan_opts;
 
 typedef struct {

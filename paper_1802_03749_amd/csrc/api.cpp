@@ -622,6 +622,10 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
         if (o.wave_colour_groups != 0 &&
             (kernel != UM_K_EDGE_FLUX_LF2D || o.strategy != UM_STRAT_HIER))
             fail(UM_ERR_UNSUPPORTED, "wave-pure colour groups: HIER plans of the edge loop only");
+        if (o.xcd_groups < 0 || o.xcd_groups > 64)
+            fail(UM_ERR_ARG, "xcd_groups %d outside 0..64", o.xcd_groups);
+        if (o.xcd_groups > 1 && (is_step_kernel(kernel) || o.strategy != UM_STRAT_HIER))
+            fail(UM_ERR_UNSUPPORTED, "XCD groups: HIER plans of the edge and hex loops only");
         const auto t0 = std::chrono::steady_clock::now();
         auto *p = new um_plan_s();
         p->ctx = &c;

@@ -364,11 +364,50 @@ int32_t plan_blocks(const Ctx &ctx, int32_t iter_set, const int32_t *wt, int ari
     }
     hp.blk_order = counting_order(hp.blk_colour, nbcol, hp.bcol_off);
     hp.schedule = o.schedule;
+    // XCD groups: the blocks are split into G equal ranges of block ids
+    // (regions of space, since partition blocks are numbered in bisection
+    // order); inside each colour the k-th workgroup of its launch (k = the
+    // launch position for the one-launch dataflow schedule, the position
+    // within the colour for colour launches) takes the next block of group
+    // k mod G, or, once that group has none left in the colour, the next
+    // block of the group with most left.  A device that hands consecutive
+    // workgroups to its G last-level-cache domains in turn then runs each
+    // region on one domain, where a block finds halo lines its neighbours
+    // have read.
+    const int32_t G = o.xcd_groups;
+    std::vector<std::vector<int32_t>> glist(G > 1 ? G : 0);
+    std::vector<size_t> gnext(glist.size());
+    auto group_interleave = [&](int32_t c) {
+        const int32_t p0 = hp.bcol_off[c], p1 = hp.bcol_off[c + 1];
+        for (auto &l : glist) l.clear();
+        std::fill(gnext.begin(), gnext.end(), 0);
+        for (int32_t pos = p0; pos < p1; ++pos) {
+            const int32_t b = hp.blk_order[pos];
+            glist[int64_t(b) * G / nb].push_back(b);
+        }
+        const int32_t base = o.schedule == UM_SCHED_DATAFLOW ? 0 : p0;
+        for (int32_t pos = p0; pos < p1; ++pos) {
+            int32_t g = (pos - base) % G;
+            if (gnext[g] == glist[g].size()) {
+                size_t most = 0;
+                for (int32_t h = 0; h < G; ++h)
+                    if (glist[h].size() - gnext[h] > most) {
+                        most = glist[h].size() - gnext[h];
+                        g = h;
+                    }
+            }
+            hp.blk_order[pos] = glist[g][gnext[g]++];
+        }
+    };
+    if (G > 1 && o.schedule != UM_SCHED_DATAFLOW)
+        for (int32_t c = 0; c < nbcol; ++c) group_interleave(c);
     if (o.schedule == UM_SCHED_DATAFLOW) {
         // inside each colour after the first, launch first the blocks whose
         // earlier-coloured neighbours were launched earliest (stable sort by
         // the latest such neighbour's position), so that the blocks the
-        // dispatcher starts first rarely find a neighbour still running
+        // dispatcher starts first rarely find a neighbour still running;
+        // XCD groups are interleaved after that sort, colour by colour
+        if (G > 1 && nbcol > 0) group_interleave(0);
         std::vector<int32_t> pos_of(nb);
         for (int32_t pos = 0; pos < nb; ++pos) pos_of[hp.blk_order[pos]] = pos;
         std::vector<int32_t> key(nb, -1);
@@ -381,6 +420,7 @@ int32_t plan_blocks(const Ctx &ctx, int32_t iter_set, const int32_t *wt, int ari
             }
             std::stable_sort(hp.blk_order.begin() + p0, hp.blk_order.begin() + p1,
                              [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+            if (G > 1) group_interleave(c);
             for (int32_t pos = p0; pos < p1; ++pos) pos_of[hp.blk_order[pos]] = pos;
         }
         // predecessors of a launch position: its neighbours launched earlier,

@@ -198,7 +198,7 @@ class EdgeFluxLoop:
              allow_fallback: bool = True, elems_per_thread: int = 1,
              explicit_lists: bool = False, block_colouring: str = "first_fit",
              schedule: str = "colour_launches", gather: str = "registers",
-             wave_colour_groups: bool = False) -> Plan:
+             wave_colour_groups: bool = False, xcd_groups: int = 0) -> Plan:
         o = U.um_plan_opts()
         o.strategy = STRATEGIES[strategy]
         o.block_size = block_size
@@ -213,6 +213,7 @@ class EdgeFluxLoop:
         o.schedule = SCHEDULES[schedule]
         o.gather = GATHERS[gather]
         o.wave_colour_groups = 1 if wave_colour_groups else 0
+        o.xcd_groups = xcd_groups
         h = U.um_plan_build(self.ctx, U.UM_K_EDGE_FLUX_LF2D, self.args(), self.s_edges, o)
         p = Plan(h, strategy, block_size, U.um_plan_stats_get(h).as_dict())
         self._plans.append(p)

@@ -110,7 +110,7 @@ class HexLoop:
     def plan(self, strategy: str = "hier", block_size: int = 256, max_block_colours: int = 256,
              lds_limit_bytes: int = 0, explicit_lists: bool = False,
              block_colouring: str = "first_fit", tcmode: str = "barrier",
-             schedule: str = "colour_launches") -> Plan:
+             schedule: str = "colour_launches", xcd_groups: int = 0) -> Plan:
         o = U.um_plan_opts()
         o.strategy = STRATEGIES[strategy]
         o.block_size = block_size
@@ -121,6 +121,7 @@ class HexLoop:
         o.explicit_lists = 1 if explicit_lists else 0
         o.block_colouring = BCOLOURING[block_colouring]
         o.schedule = SCHEDULES[schedule]
+        o.xcd_groups = xcd_groups
         h = U.um_plan_build(self.ctx, U.UM_K_HEX_HOURGLASS_3D, self.args(), self.s_elems, o)
         p = Plan(h, strategy, block_size, U.um_plan_stats_get(h).as_dict())
         self._plans.append(p)

@@ -73,7 +73,7 @@ class um_plan_opts(ct.Structure):
                 ("elems_per_thread", ct.c_int32), ("explicit_lists", ct.c_int32),
                 ("block_colouring", ct.c_int32), ("schedule", ct.c_int32),
                 ("gather", ct.c_int32), ("wave_colour_groups", ct.c_int32),
-                ("reserved", ct.c_int32 * 2)]
+                ("xcd_groups", ct.c_int32), ("reserved", ct.c_int32 * 1)]
 
 
 class um_plan_stats(ct.Structure):

@@ -16,7 +16,8 @@ against the CPU oracle:
   every kernel exits, and later executions wait normally again;
 * the LDS-DMA gather, wave-pure colour groups and the smallest-block-first
   point order, and the benchmark's plan on empty, single-edge, ragged and
-  free-stream meshes.
+  free-stream meshes;
+* XCD groups (a launch order only): bitwise the results without them.
 
 Bar as elsewhere: relative L2 <= 1e-12 in binary64, 1e-6 for binary32
 storage against the oracle's binary32 evaluation.
@@ -350,4 +351,41 @@ def test_headline_plan_free_stream_exact_zero():
     i, j = m.cell_nat % m.nx, m.cell_nat // m.nx
     inner = (i > 0) & (i < m.nx - 1) & (j > 0) & (j < m.ny - 1)
     assert np.all(r[inner] == 0.0)
+    L.close()
+
+
+# ------------------------------------------------------------ XCD groups
+@pytest.mark.parametrize("plan", ["headline", "registers", "colour_launches"])
+def test_xcd_groups_same_results(plan):
+    """XCD groups (eight block-id ranges interleaved over the launch) change
+    the launch order only: with barrier rounds the residuals are bitwise those
+    of the plan without them, and within the bar of the oracle."""
+    m, ref = mesh(400, 200)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
+                     block_size=512, point_reorder=2)
+    kw = dict(HEADLINE) if plan != "colour_launches" else dict(block_colouring="recolour")
+    if plan == "registers":
+        kw["gather"] = "registers"
+    outs = [run_once(L, L.plan("hier", 512, xcd_groups=G, **kw)) for G in (0, 8)]
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    assert rel_l2(outs[1], ref) <= TOL
+    L.close()
+
+
+@pytest.mark.parametrize("schedule", ["colour_launches", "dataflow"])
+def test_xcd_groups_hex(schedule):
+    from meshgen import hex_mesh
+    from paper_1802_03749_amd.hexloop import HexLoop
+    m = hex_mesh(24, seed=1)
+    ref = native.hex_loop(m.e2n, m.x, m.v)
+    L = HexLoop(m.x, m.v, m.e2n, device=0, order="rcm+partition", block_size=256,
+                point_reorder=3)
+    outs = []
+    for G in (0, 8):
+        p = L.plan("hier", 256, block_colouring="min", schedule=schedule, xcd_groups=G)
+        L.zero_force(); L.run(p); torch.cuda.synchronize()
+        assert U.um_plan_errors(p.handle) == 0
+        outs.append(L.force_user())
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    assert rel_l2(outs[1], ref) <= TOL
     L.close()

@@ -638,3 +638,73 @@ def test_wave_colour_groups_refused_where_unsupported():
     with pytest.raises(U.UmeshError) as ei:
         L.plan("global", 256, wave_colour_groups=True)
     assert ei.value.status == U.UM_ERR_UNSUPPORTED
+
+
+def _xcd_interleave(blocks, G, nb, base, p0):
+    """The k-th workgroup of a launch (k = position - base) takes the next
+    block of group k mod G (group = block id * G // nb) while that group has
+    blocks left, else the next block of the group with most left (first such
+    group on a tie); blocks keep their order inside a group."""
+    lists = [[b for b in blocks if b * G // nb == g] for g in range(G)]
+    nxt = [0] * G
+    out = []
+    for pos in range(p0, p0 + len(blocks)):
+        g = (pos - base) % G
+        if nxt[g] == len(lists[g]):
+            left = [len(lists[h]) - nxt[h] for h in range(G)]
+            g = int(np.argmax(left))
+        out.append(lists[g][nxt[g]])
+        nxt[g] += 1
+    return out
+
+
+@pytest.mark.parametrize("schedule", ["colour_launches", "dataflow"])
+@pytest.mark.parametrize("G", [2, 8])
+def test_xcd_groups_launch_order(schedule, G):
+    """XCD groups change the launch order only: the same blocks, colours and
+    thread colours; colour by colour; inside a colour the interleave of the
+    block-id groups (after the dataflow schedule's sort by the latest
+    earlier-coloured neighbour); a dataflow block waits for exactly its
+    earlier-coloured neighbours."""
+    _, L = make(nx=90, ny=50, order="rcm+partition", block_size=128)
+    base = L.plan("hier", 128, schedule=schedule, block_colouring="recolour")
+    p = L.plan("hier", 128, schedule=schedule, block_colouring="recolour", xcd_groups=G)
+    for f in (U.UM_EXP_BLOCK_OFFSETS, U.UM_EXP_BLOCK_COLOURS, U.UM_EXP_THREAD_COLOURS):
+        assert np.array_equal(L.export(p, f), L.export(base, f))
+    off = L.export(p, U.UM_EXP_BLOCK_OFFSETS)
+    bcol = L.export(p, U.UM_EXP_BLOCK_COLOURS)
+    order = L.export(p, U.UM_EXP_BLOCK_ORDER)
+    nb = bcol.size
+    assert P.is_permutation(order, nb)
+    assert np.all(np.diff(bcol[order]) >= 0)
+    nbrs = P.block_neighbours(off, L.current_map("e2c"))
+    # re-derive the order colour by colour
+    want, pos_of = [], np.full(nb, -1)
+    for c in range(int(bcol.max()) + 1):
+        blocks = [b for b in range(nb) if bcol[b] == c]      # counting sort: id order
+        if schedule == "dataflow" and c > 0:
+            key = {b: max([pos_of[n] for n in nbrs[b] if bcol[n] < c], default=-1) for b in blocks}
+            blocks = sorted(blocks, key=lambda b: key[b])     # stable
+        p0 = len(want)
+        blocks = _xcd_interleave(blocks, G, nb, 0 if schedule == "dataflow" else p0, p0)
+        for k, b in enumerate(blocks):
+            pos_of[b] = p0 + k
+        want += blocks
+    assert np.array_equal(order, want)
+    if schedule == "dataflow":
+        po = L.export(p, U.UM_EXP_PRED_OFFSETS)
+        pr = L.export(p, U.UM_EXP_PREDS)
+        for k, b in enumerate(order):
+            assert sorted(pr[po[k]:po[k + 1]]) == sorted(pos_of[n] for n in nbrs[b] if bcol[n] < bcol[b])
+
+
+def test_xcd_groups_checked():
+    _, L = make(order="rcm+partition", block_size=256)
+    for G, status in ((65, U.UM_ERR_ARG), (-1, U.UM_ERR_ARG)):
+        with pytest.raises(U.UmeshError) as ei:
+            L.plan("hier", 256, xcd_groups=G)
+        assert ei.value.status == status
+    with pytest.raises(U.UmeshError) as ei:
+        L.plan("global", 256, xcd_groups=8)
+    assert ei.value.status == U.UM_ERR_UNSUPPORTED
+    assert L.plan("global", 256, xcd_groups=1).stats["n_launches"] >= 1
