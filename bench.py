@@ -150,7 +150,8 @@ def run_sweep(torch, args, U):
             raise RuntimeError("a dataflow wait timed out in the sweep")
         return {"us_per_sweep": s * 1e6, "edges_per_s": E / s, "useful_gbps": useful / s / 1e9,
                 "launches": p.stats["n_launches"], "block_colours": p.stats["n_block_colours"],
-                "global_colours": p.stats["n_global_colours"]}
+                "global_colours": p.stats["n_global_colours"],
+                "sum_first_blocks": p.stats["n_sum_first_blocks"]}
 
     def hier_entries(L, order, S, plans):
         for name, kw in plans:
@@ -177,7 +178,11 @@ def run_sweep(torch, args, U):
                          order="rcm+partition", block_size=S, point_reorder=args.point_order)
         for strat in ("atomic", "global"):
             ent[f"rcm+partition/{strat}/S{S}"] = timed(L, L.plan(strat, S))
-        hier_entries(L, "rcm+partition", S, (cl, df))
+        extra = ()
+        if args.gather == "lds_dma":
+            # every block loading its residuals early instead (none sums first)
+            extra = (("dataflow_no_sum_first", dict(df[1], sum_first="never")),)
+        hier_entries(L, "rcm+partition", S, (cl, df) + extra)
         L.close()
     log("sweep rcm+partition done")
     best = {}
@@ -238,7 +243,8 @@ def run_ablations(torch, mesh, S, args, useful, E):
                                   ("schedule", "colour_launches"), ("schedule", "dataflow"),
                                   ("elems_per_thread", 1), ("elems_per_thread", 2),
                                   ("gather", "registers"), ("gather", "lds_dma"),
-                                  ("wave_colour_groups", True), ("xcd_groups", 8)):
+                                  ("wave_colour_groups", True), ("xcd_groups", 8),
+                                  ("sum_first", "always")):
                     if base.get(knob) == val:
                         continue
                     o = dict(base); o[knob] = val

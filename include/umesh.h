@@ -328,8 +328,19 @@ typedef struct {
                                   blocks share that XCD's L2.  Launch order
                                   only: every block still follows the blocks
                                   of smaller colour around it, so barrier
-                                  rounds give bitwise the same results      */
-    int32_t reserved[1];
+                                  rounds give bitwise the same results where
+                                  every block takes the same sum_first path */
+    int32_t sum_first;         /* HIER, DATAFLOW, LDS-DMA gather: which blocks
+                                  sum their fluxes in LDS before waiting for
+                                  their earlier-coloured neighbours and then
+                                  only add the sums to the residuals, while
+                                  the others load their residuals early and
+                                  accumulate onto them.  0 = those whose
+                                  latest such neighbour is launched fewer
+                                  positions earlier than the blocks the
+                                  device holds at once; 1 = every block with
+                                  a neighbour to wait for; -1 = none.  The
+                                  results agree to rounding                 */
 } um_plan_opts;
 
 typedef struct {
@@ -349,7 +360,10 @@ typedef struct {
     int64_t lds_bytes_max;       /* HIER: largest per-block LDS footprint    */
     int64_t plan_device_bytes;   /* device memory owned by the plan          */
     double build_seconds;        /* host wall time of um_plan_build          */
-    int64_t reserved[4];
+    int64_t n_sum_first_blocks;  /* HIER, DATAFLOW, LDS-DMA gather: blocks that
+                                    sum their fluxes before their wait
+                                    (um_plan_opts.sum_first)                 */
+    int64_t reserved[3];
 } um_plan_stats;
 
 /* Plan contents that can be copied out for verification (um_plan_export). */

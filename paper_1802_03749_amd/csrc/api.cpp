@@ -362,6 +362,7 @@ LaunchArgs launch_args(Plan &p, const double *params, int32_t nparams, void *str
     la.preds = p.dp.preds;
     la.frec = p.dp.frec;
     la.gather = p.hp.gather;
+    la.sum_first = p.hp.n_sum_first > 0;
     la.flags = p.dp.flags;
     la.err = p.dp.err;
     la.wait_ticks = p.wait_ticks;
@@ -408,6 +409,8 @@ um_status um_create(int32_t device, um_ctx *out) {
                 fail(UM_ERR_HIP, "cannot query HIP device %d", device);
             }
             c->lds_limit = int32_t(prop.sharedMemPerBlock);
+            c->n_cu = prop.multiProcessorCount;
+            c->lds_per_cu = int64_t(prop.maxSharedMemoryPerMultiProcessor);
             try {
                 DeviceGuard g(device);
                 (void)scratch_address(device);
@@ -624,6 +627,8 @@ um_status um_plan_build(um_ctx ctx, int32_t kernel, const um_arg *args, int32_t 
             fail(UM_ERR_UNSUPPORTED, "wave-pure colour groups: HIER plans of the edge loop only");
         if (o.xcd_groups < 0 || o.xcd_groups > 64)
             fail(UM_ERR_ARG, "xcd_groups %d outside 0..64", o.xcd_groups);
+        if (o.sum_first < -1 || o.sum_first > 1)
+            fail(UM_ERR_ARG, "sum_first %d not in {-1, 0, 1}", o.sum_first);
         if (o.xcd_groups > 1 && (is_step_kernel(kernel) || o.strategy != UM_STRAT_HIER))
             fail(UM_ERR_UNSUPPORTED, "XCD groups: HIER plans of the edge and hex loops only");
         const auto t0 = std::chrono::steady_clock::now();
@@ -719,6 +724,7 @@ um_status um_plan_stats_get(um_plan plan, um_plan_stats *out) {
             out->reuse_factor = hp.reuse;
             out->staged_points = hp.staged_total;
             out->lds_bytes_max = hp.lds_max;
+            out->n_sum_first_blocks = hp.n_sum_first;
             out->n_launches = 0;
             for (int32_t c = 0; c + 1 < int32_t(hp.bcol_off.size()); ++c)
                 out->n_launches += hp.bcol_off[c + 1] > hp.bcol_off[c];

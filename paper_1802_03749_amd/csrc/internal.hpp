@@ -40,6 +40,8 @@ struct Plan;
 struct Ctx {
     int32_t device = -1;             // -1: host-only
     int32_t lds_limit = 65536;       // per-workgroup LDS limit in bytes
+    int32_t n_cu = 256;              // compute units (host-only: MI355X's)
+    int64_t lds_per_cu = 163840;     // LDS bytes per compute unit
     std::vector<Set> sets;
     std::vector<Map> maps;
     std::vector<Dat> dats;
@@ -131,13 +133,14 @@ constexpr int32_t MAX_RUNS = 8;
 
 // Everything a DATAFLOW block of the edge loop's LDS-DMA kernel needs before
 // its first memory round trip, one record per launch position, read with
-// scalar loads: its ranges and counts, its (first 8) predecessors and the
-// run descriptors of its staged cell and node lists (ncr / nnr = 0: the
-// block reads its explicit list instead).
+// scalar loads: its ranges and counts, its (first 8) predecessors, whether
+// it sums its fluxes before waiting (sum_first), and the run descriptors of
+// its staged cell and node lists (ncr / nnr = 0: the block reads its
+// explicit list instead).
 struct FlowRec {
     int32_t slot_off, cell_off, node_off, ncol;
     int32_t ne, nc, nn, np;
-    int32_t ncr, nnr, p0, pad0;
+    int32_t ncr, nnr, p0, sum_first;
     int32_t preds[8];
     Run cruns[MAX_RUNS];
     Run nruns[MAX_RUNS];
@@ -171,6 +174,7 @@ struct HostPlan {
     std::vector<int64_t> lds_per_colour;       // max LDS bytes per block colour
     std::vector<int32_t> pred_off, preds;      // DATAFLOW: earlier neighbours per position
     std::vector<FlowRec> frec;                 // DATAFLOW edge loop: per position
+    int64_t n_sum_first = 0;                   // DATAFLOW edge loop: blocks with sum_first
     int32_t gather = 0;                        // HIER, DATAFLOW: um_gather
     int32_t wave_groups = 0;                   // HIER: colour groups padded to waves
     int32_t max_tcol = 0;

@@ -562,6 +562,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
 //      predecessors (bounded wait) after its fluxes and fetches then;
 //   4. thread-colour rounds into the residual accumulators, write-back with
 //      device-scope stores, completion flag (as hier_flow_kernel).
+// A block whose record says sum_first (its latest awaited neighbour was
+// launched so shortly before it that it is likely still running) instead
+// zeroes the accumulators, runs the rounds on them, then waits, then adds
+// them to its cells' residuals with device-scope loads and stores: a chain
+// of such blocks carries only that read-add-write between neighbours.
 // LDS layout (each staged record split so that every DMA lands in 16-byte
 // lanes): residual accumulators as two arrays of (res0, res1) and (res2, res3)
 // pairs, then q (binary64: two arrays of pairs; binary32: one float4 array),
@@ -607,7 +612,7 @@ __device__ __forceinline__ int32_t rec_id(const Run (&runs)[MAX_RUNS], int32_t n
     return nr == 0 ? list[t] : run_id(runs, nr, t);
 }
 
-template <int TCMODE, int EPT, typename Real>
+template <int TCMODE, int EPT, typename Real, bool SUM_FIRST>
 __global__ __launch_bounds__(1024)
 __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_dma_kernel(
     const FlowRec *__restrict__ frec, const int32_t *__restrict__ stg_c,
@@ -622,6 +627,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_dma_ke
     const FlowRec &rec = frec[pos];
     const int ne = rec.ne, nc = rec.nc, nn = rec.nn, np = rec.np;
     const int ncr = rec.ncr, nnr = rec.nnr;
+    // a plan without sum-first blocks runs the instantiation without that path
+    const bool sum_first = SUM_FIRST && rec.sum_first != 0;
     Run cruns[MAX_RUNS], nruns[MAX_RUNS];
 #pragma unroll
     for (int k = 0; k < MAX_RUNS; ++k) {
@@ -737,7 +744,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_dma_ke
             }
         }
     };
-    if (ready) fetch_res();
+    if (sum_first) {
+        for (int u = tid; u < 4 * nc; u += T) lds[u] = 0.0;
+    } else if (ready) {
+        fetch_res();
+    }
 
     int lL[EPT], lR[EPT], col[EPT];
     Real f[EPT][4];
@@ -779,7 +790,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_dma_ke
             lf2d_flux(xa0, xa1, xb0, xb1, qL, qR, aL, aR, gm1, eps, f[j]);
         }
     }
-    if (!ready) {
+    if (!ready && !sum_first) {
         // this wavefront waits for the earlier-coloured neighbours now
         if (lane < np) {
             int32_t pr = rec.preds[0];
@@ -830,26 +841,66 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_dma_ke
         __syncthreads();
     }
 
-    // ---- write-back: lane pairs store the two 16-byte halves of a cell
-    auto store_half = [&](int t, int h, int32_t g) {
-        const f64x2 v = *reinterpret_cast<const f64x2 *>((h ? r_hi : r_lo) + 2 * t);
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rres,
-                                               int32_t(32 * int64_t(g) + 16 * h), 0, CPOL_SC1);
-    };
-    if (ncr > 0) {
-        for (int u = tid; u < 2 * nc; u += T) store_half(u >> 1, u & 1, run_id(cruns, ncr, u >> 1));
-    } else {
-        // the ids of all this lane's cells first (a list load after a store
-        // would wait for the store)
-        int32_t g[4];
+    if (sum_first) {
+        // wait for the earlier-coloured neighbours, then res += sums, lane
+        // pairs on the two 16-byte halves of a cell, 4 halves per lane in flight
+        if (tid < np) {
+            int32_t pr = rec.preds[0];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int u = tid + i * T;
-            g[i] = u < 2 * nc ? clist[u >> 1] : 0;
+            for (int k = 1; k < 8; ++k) pr = lane == k ? rec.preds[k] : pr;
+            if (np > 8) pr = preds[rec.p0 + lane];
+            dev::bounded_wait(flags + pr, epoch, ctl, wait_ticks);
         }
-        for (int u = tid, i = 0; u < 2 * nc; u += T, ++i) {
-            const int32_t gi = i < 4 ? g[i] : clist[u >> 1];
-            store_half(u >> 1, u & 1, gi);
+        __syncthreads();
+        for (int u0 = tid; u0 < 2 * nc; u0 += 4 * T) {
+            int32_t off[4];
+            f64x2 a[4];
+            u32x4 v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = u0 + i * T < 2 * nc ? u0 + i * T : 0;
+                const int32_t g = rec_id(cruns, ncr, clist, u >> 1);
+                off[i] = int32_t(32 * int64_t(g) + 16 * (u & 1));
+                a[i] = *reinterpret_cast<const f64x2 *>(((u & 1) ? r_hi : r_lo) + 2 * (u >> 1));
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                v[i] = u0 + i * T < 2 * nc
+                           ? __builtin_amdgcn_raw_buffer_load_b128(rres, off[i], 0, CPOL_SC1)
+                           : u32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (u0 + i * T < 2 * nc) {
+                    f64x2 r = __builtin_bit_cast(f64x2, v[i]);
+                    r.x += a[i].x;
+                    r.y += a[i].y;
+                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, r), rres,
+                                                           off[i], 0, CPOL_SC1);
+                }
+            }
+        }
+    } else {
+        // ---- write-back: lane pairs store the two 16-byte halves of a cell
+        auto store_half = [&](int t, int h, int32_t g) {
+            const f64x2 v = *reinterpret_cast<const f64x2 *>((h ? r_hi : r_lo) + 2 * t);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rres,
+                                                   int32_t(32 * int64_t(g) + 16 * h), 0, CPOL_SC1);
+        };
+        if (ncr > 0) {
+            for (int u = tid; u < 2 * nc; u += T) store_half(u >> 1, u & 1, run_id(cruns, ncr, u >> 1));
+        } else {
+            // the ids of all this lane's cells first (a list load after a store
+            // would wait for the store)
+            int32_t g[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = tid + i * T;
+                g[i] = u < 2 * nc ? clist[u >> 1] : 0;
+            }
+            for (int u = tid, i = 0; u < 2 * nc; u += T, ++i) {
+                const int32_t gi = i < 4 ? g[i] : clist[u >> 1];
+                store_half(u >> 1, u & 1, gi);
+            }
         }
     }
     __builtin_amdgcn_s_waitcnt(0);
@@ -964,17 +1015,24 @@ hipError_t launch_flow_one(const LaunchArgs &la, int32_t nblocks, int64_t lds,
     return hipGetLastError();
 }
 
-template <int TC, int EPT, typename Real>
-hipError_t launch_dma_one(const LaunchArgs &la, int32_t nblocks, int64_t lds,
-                          const Dats<Real> &d) {
+template <int TC, int EPT, typename Real, bool SF>
+hipError_t launch_dma_sf(const LaunchArgs &la, int32_t nblocks, int64_t lds,
+                         const Dats<Real> &d) {
     clear_stale_error();
     const hipError_t ea =
-        allow_lds(reinterpret_cast<const void *>(hier_dma_kernel<TC, EPT, Real>), lds);
+        allow_lds(reinterpret_cast<const void *>(hier_dma_kernel<TC, EPT, Real, SF>), lds);
     if (ea != hipSuccess) return ea;
-    hipLaunchKernelGGL((hier_dma_kernel<TC, EPT, Real>), dim3(nblocks), dim3(la.block_size),
+    hipLaunchKernelGGL((hier_dma_kernel<TC, EPT, Real, SF>), dim3(nblocks), dim3(la.block_size),
                        size_t(lds), la.stream, la.frec, la.stg_c, la.stg_n, la.loc, la.n_slots, d,
                        la.gm1, la.eps, la.preds, la.flags, la.err, la.wait_ticks);
     return hipGetLastError();
+}
+
+template <int TC, int EPT, typename Real>
+hipError_t launch_dma_one(const LaunchArgs &la, int32_t nblocks, int64_t lds,
+                          const Dats<Real> &d) {
+    return la.sum_first ? launch_dma_sf<TC, EPT, Real, true>(la, nblocks, lds, d)
+                        : launch_dma_sf<TC, EPT, Real, false>(la, nblocks, lds, d);
 }
 
 template <int LAYOUT, int TC, typename Real>

@@ -652,6 +652,18 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     hp.reuse = hp.stg_c.empty() ? 0.0 : double(2 * E) / double(hp.stg_c.size());
     hp.avg_tcol = nb ? double(tcol_sum) / nb : 0.0;
     if (hp.schedule == UM_SCHED_DATAFLOW) {
+        // LDS-DMA gather: blocks the device holds at once, by LDS per compute
+        // unit and by its 2048 lanes.  A block whose latest awaited neighbour was launched
+        // fewer positions earlier is likely to find it still running; it sums
+        // its fluxes in LDS before the wait (sum_first) and afterwards only
+        // adds the sums to its cells' residuals, so that a chain of waiting
+        // blocks carries only that read-add-write.  The other blocks load
+        // their residuals early and accumulate onto them.
+        const int64_t per_cu = std::max<int64_t>(
+            1, std::min<int64_t>(ctx.lds_per_cu / std::max<int64_t>(hp.lds_max, 1),
+                                 2048 / std::max(hp.threads, 64)));
+        const int64_t resident = int64_t(ctx.n_cu) * per_cu;
+        hp.n_sum_first = 0;
         hp.frec.assign(nb, FlowRec{});
         for (int32_t pos = 0; pos < nb; ++pos) {
             const BlockInfo &a = hp.binfo[pos], &z = hp.binfo[pos + 1];
@@ -666,6 +678,11 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
             r.p0 = hp.pred_off[pos];
             r.np = hp.pred_off[pos + 1] - hp.pred_off[pos];
             for (int32_t k = 0; k < r.np && k < 8; ++k) r.preds[k] = hp.preds[r.p0 + k];
+            int32_t latest = -1;
+            for (int32_t k = 0; k < r.np; ++k) latest = std::max(latest, hp.preds[r.p0 + k]);
+            r.sum_first = o.gather == UM_GATHER_LDS_DMA && latest >= 0 && o.sum_first >= 0 &&
+                          (o.sum_first == 1 || int64_t(pos) - latest < resident);
+            hp.n_sum_first += r.sum_first;
             r.ncr = z.crun_off - a.crun_off;
             r.nnr = z.nrun_off - a.nrun_off;
             for (int32_t k = 0; k < r.ncr; ++k) r.cruns[k] = hp.crun[a.crun_off + k];

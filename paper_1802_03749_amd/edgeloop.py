@@ -28,6 +28,7 @@ BCOLOURING = {"first_fit": U.UM_BCOL_FIRST_FIT, "recolour": U.UM_BCOL_RECOLOUR,
               "min": U.UM_BCOL_MIN}
 SCHEDULES = {"colour_launches": U.UM_SCHED_COLOUR_LAUNCHES, "dataflow": U.UM_SCHED_DATAFLOW}
 GATHERS = {"registers": U.UM_GATHER_REGISTERS, "lds_dma": U.UM_GATHER_LDS_DMA}
+SUM_FIRST = {"auto": 0, "always": 1, "never": -1}
 
 
 def parse_order(order: str):
@@ -198,7 +199,8 @@ class EdgeFluxLoop:
              allow_fallback: bool = True, elems_per_thread: int = 1,
              explicit_lists: bool = False, block_colouring: str = "first_fit",
              schedule: str = "colour_launches", gather: str = "registers",
-             wave_colour_groups: bool = False, xcd_groups: int = 0) -> Plan:
+             wave_colour_groups: bool = False, xcd_groups: int = 0,
+             sum_first: str = "auto") -> Plan:
         o = U.um_plan_opts()
         o.strategy = STRATEGIES[strategy]
         o.block_size = block_size
@@ -214,6 +216,7 @@ class EdgeFluxLoop:
         o.gather = GATHERS[gather]
         o.wave_colour_groups = 1 if wave_colour_groups else 0
         o.xcd_groups = xcd_groups
+        o.sum_first = SUM_FIRST[sum_first]
         h = U.um_plan_build(self.ctx, U.UM_K_EDGE_FLUX_LF2D, self.args(), self.s_edges, o)
         p = Plan(h, strategy, block_size, U.um_plan_stats_get(h).as_dict())
         self._plans.append(p)

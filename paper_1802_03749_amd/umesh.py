@@ -73,7 +73,7 @@ class um_plan_opts(ct.Structure):
                 ("elems_per_thread", ct.c_int32), ("explicit_lists", ct.c_int32),
                 ("block_colouring", ct.c_int32), ("schedule", ct.c_int32),
                 ("gather", ct.c_int32), ("wave_colour_groups", ct.c_int32),
-                ("xcd_groups", ct.c_int32), ("reserved", ct.c_int32 * 1)]
+                ("xcd_groups", ct.c_int32), ("sum_first", ct.c_int32)]
 
 
 class um_plan_stats(ct.Structure):
@@ -84,7 +84,7 @@ class um_plan_stats(ct.Structure):
                 ("reuse_factor", ct.c_double), ("n_elements", ct.c_int64),
                 ("staged_points", ct.c_int64), ("lds_bytes_max", ct.c_int64),
                 ("plan_device_bytes", ct.c_int64), ("build_seconds", ct.c_double),
-                ("reserved", ct.c_int64 * 4)]
+                ("n_sum_first_blocks", ct.c_int64), ("reserved", ct.c_int64 * 3)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -14,7 +14,9 @@ against the CPU oracle:
   oracle step;
 * the dataflow schedule's error path: waits forced to give up are counted,
   every kernel exits, and later executions wait normally again;
-* the LDS-DMA gather, wave-pure colour groups and the smallest-block-first
+* the LDS-DMA gather (blocks that sum their fluxes before waiting for
+  their neighbours, and blocks that load their residuals early), wave-pure
+  colour groups and the smallest-block-first
   point order, and the benchmark's plan on empty, single-edge, ragged and
   free-stream meshes;
 * XCD groups (a launch order only): bitwise the results without them.
@@ -209,18 +211,20 @@ def test_dataflow_forced_timeouts_are_per_execution():
 
 
 # ------------------------------------------------- LDS-DMA gather (dataflow)
+@pytest.mark.parametrize("sum_first", ["auto", "never"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("tcmode", ["barrier", "lds_atomic"])
 @pytest.mark.parametrize("ept", [1, 2])
-def test_lds_dma_gather_small(ept, tcmode, dtype):
+def test_lds_dma_gather_small(ept, tcmode, dtype, sum_first):
     """The dataflow kernel whose gather writes LDS directly: 200x100 cells,
     both edge-per-lane settings and colour-round modes, binary64 and
-    binary32 storage; bitwise reproducible with barrier rounds."""
+    binary32 storage, blocks summing before their wait or not; bitwise
+    reproducible with barrier rounds."""
     m, ref = mesh(200, 100)
     L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
                      block_size=256, dtype=dtype)
     p = L.plan("hier", 256, schedule="dataflow", elems_per_thread=ept, tcmode=tcmode,
-               block_colouring="recolour", gather="lds_dma")
+               block_colouring="recolour", gather="lds_dma", sum_first=sum_first)
     r1 = run_once(L, p)
     if dtype == "f64":
         assert rel_l2(r1, ref) <= TOL
@@ -233,30 +237,39 @@ def test_lds_dma_gather_small(ept, tcmode, dtype):
     L.close()
 
 
+@pytest.mark.parametrize("sum_first", ["auto", "never"])
 @pytest.mark.parametrize("explicit", [False, True])
 @pytest.mark.parametrize("S", [256, 512, 1024])
-def test_lds_dma_gather_medium(S, explicit):
-    """1200x600: most blocks start before their earlier-coloured neighbours
-    finish, so the wavefronts that were not ready take the late residual
-    fetch; explicit staged-id lists as well as run descriptors."""
+def test_lds_dma_gather_medium(S, explicit, sum_first):
+    """1200x600: every block is resident at once, so most start before
+    their earlier-coloured neighbours finish: by default they sum their
+    fluxes before the wait and add the sums afterwards; without that, the
+    wavefronts that were not ready take the late residual fetch.  Explicit
+    staged-id lists as well as run descriptors; bitwise reproducible."""
     m, ref = mesh(1200, 600)
-    print(f"1200x600 lds_dma S={S} explicit={explicit}", flush=True)
+    print(f"1200x600 lds_dma S={S} explicit={explicit} sum_first={sum_first}", flush=True)
     L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
                      block_size=S)
     p = L.plan("hier", S, schedule="dataflow", elems_per_thread=2, block_colouring="recolour",
-               gather="lds_dma", explicit_lists=explicit)
-    for _ in range(2):
-        assert rel_l2(run_once(L, p), ref) <= TOL
+               gather="lds_dma", explicit_lists=explicit, sum_first=sum_first)
+    n = p.stats["n_sum_first_blocks"]
+    assert (n > p.stats["n_blocks"] // 2) if sum_first == "auto" else n == 0
+    outs = [run_once(L, p) for _ in range(2)]
+    assert rel_l2(outs[0], ref) <= TOL
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
     L.close()
 
 
-def test_lds_dma_gather_full_size():
+@pytest.mark.parametrize("sum_first", ["auto", "always"])
+def test_lds_dma_gather_full_size(sum_first):
     m, ref = mesh(2400, 1200)
-    print("2400x1200 lds_dma", flush=True)
+    print(f"2400x1200 lds_dma sum_first={sum_first}", flush=True)
     L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
                      block_size=512)
     p = L.plan("hier", 512, schedule="dataflow", elems_per_thread=2, block_colouring="recolour",
-               gather="lds_dma")
+               gather="lds_dma", sum_first=sum_first)
+    if sum_first == "always":
+        assert p.stats["n_sum_first_blocks"] > p.stats["n_blocks"] // 2
     assert rel_l2(run_once(L, p), ref) <= TOL
     g = U.HipGraph(lambda stream: L.run(p, stream=stream))
     L.zero_res()
@@ -358,14 +371,17 @@ def test_headline_plan_free_stream_exact_zero():
 @pytest.mark.parametrize("plan", ["headline", "registers", "colour_launches"])
 def test_xcd_groups_same_results(plan):
     """XCD groups (eight block-id ranges interleaved over the launch) change
-    the launch order only: with barrier rounds the residuals are bitwise those
-    of the plan without them, and within the bar of the oracle."""
+    the launch order only: with barrier rounds, and every block of the LDS-DMA
+    plan summing before its wait in both orders, the residuals are bitwise
+    those of the plan without them, and within the bar of the oracle."""
     m, ref = mesh(400, 200)
     L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
                      block_size=512, point_reorder=2)
-    kw = dict(HEADLINE) if plan != "colour_launches" else dict(block_colouring="recolour")
+    kw = dict(HEADLINE, sum_first="always") if plan != "colour_launches" else \
+        dict(block_colouring="recolour")
     if plan == "registers":
         kw["gather"] = "registers"
+        del kw["sum_first"]
     outs = [run_once(L, L.plan("hier", 512, xcd_groups=G, **kw)) for G in (0, 8)]
     assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
     assert rel_l2(outs[1], ref) <= TOL

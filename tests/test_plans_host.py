@@ -708,3 +708,34 @@ def test_xcd_groups_checked():
         L.plan("global", 256, xcd_groups=8)
     assert ei.value.status == U.UM_ERR_UNSUPPORTED
     assert L.plan("global", 256, xcd_groups=1).stats["n_launches"] >= 1
+
+
+@pytest.mark.parametrize("nx,ny,S,ept", [(60, 40, 128, 1), (300, 200, 512, 2), (900, 500, 256, 2)])
+def test_sum_first_blocks_rule(nx, ny, S, ept):
+    """Dataflow plans with the LDS-DMA gather mark a block sum-first when its
+    latest awaited neighbour was launched fewer positions before it than the
+    blocks the device holds at once (a host-only context assumes 256 compute
+    units of 160 KiB LDS and 2048 lanes each); register-gather plans never."""
+    _, L = make(nx=nx, ny=ny, order="rcm+partition", block_size=S)
+    p = L.plan("hier", S, schedule="dataflow", block_colouring="recolour", elems_per_thread=ept,
+               gather="lds_dma")
+    po = L.export(p, U.UM_EXP_PRED_OFFSETS)
+    pr = L.export(p, U.UM_EXP_PREDS)
+    lanes = -(-S // ept // 64) * 64
+    resident = 256 * max(1, min(163840 // p.stats["lds_bytes_max"], 2048 // lanes))
+    want = 0
+    for k in range(po.size - 1):
+        if po[k + 1] > po[k] and k - pr[po[k]:po[k + 1]].max() < resident:
+            want += 1
+    assert p.stats["n_sum_first_blocks"] == want
+    kw = dict(schedule="dataflow", block_colouring="recolour", elems_per_thread=ept)
+    waiting = int(np.sum(np.diff(po) > 0))
+    assert L.plan("hier", S, gather="lds_dma", sum_first="always", **kw).stats[
+        "n_sum_first_blocks"] == waiting
+    assert L.plan("hier", S, gather="lds_dma", sum_first="never", **kw).stats[
+        "n_sum_first_blocks"] == 0
+    assert L.plan("hier", S, **kw).stats["n_sum_first_blocks"] == 0   # register gather
+    o = U.um_plan_opts(); o.strategy = U.UM_STRAT_HIER; o.block_size = S; o.sum_first = 2
+    with pytest.raises(U.UmeshError) as ei:
+        U.um_plan_build(L.ctx, U.UM_K_EDGE_FLUX_LF2D, L.args(), L.s_edges, o)
+    assert ei.value.status == U.UM_ERR_ARG
