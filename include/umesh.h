@@ -330,7 +330,7 @@ typedef struct {
                                   of smaller colour around it, so barrier
                                   rounds give bitwise the same results where
                                   every block takes the same sum_first path */
-    int32_t sum_first;         /* HIER, DATAFLOW, LDS-DMA gather: which blocks
+    int32_t sum_first;         /* HIER, DATAFLOW, edge loop: which blocks
                                   sum their fluxes in LDS before waiting for
                                   their earlier-coloured neighbours and then
                                   only add the sums to the residuals, while
@@ -360,7 +360,7 @@ typedef struct {
     int64_t lds_bytes_max;       /* HIER: largest per-block LDS footprint    */
     int64_t plan_device_bytes;   /* device memory owned by the plan          */
     double build_seconds;        /* host wall time of um_plan_build          */
-    int64_t n_sum_first_blocks;  /* HIER, DATAFLOW, LDS-DMA gather: blocks that
+    int64_t n_sum_first_blocks;  /* HIER, DATAFLOW, edge loop: blocks that
                                     sum their fluxes before their wait
                                     (um_plan_opts.sum_first)                 */
     int64_t reserved[3];

@@ -117,7 +117,8 @@ struct BlockInfo {
     int32_t ncol;       // thread colours used by the block
     int32_t crun_off;   // first run of the staged cells (into crun); a block
     int32_t nrun_off;   // with no runs reads its explicit list instead
-    int32_t pad0, pad1;
+    int32_t sum_first;  // DATAFLOW edge loop: sums its fluxes before its wait
+    int32_t pad1;
 };
 
 // A run of consecutive staged points: staged positions local, local+1, ...

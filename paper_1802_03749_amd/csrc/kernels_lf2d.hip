@@ -323,7 +323,7 @@ __device__ __forceinline__ void store4_dev(__amdgpu_buffer_rsrc_t r, int64_t C, 
 // (the kernel fits 64 VGPRs) but lets the compiler schedule for that
 // occupancy, measured faster (FP32, two edges per lane: S = 512 71.4 ->
 // 70.7 us, S = 1024 78.0 -> 71.4 us); the binary64 code is unchanged.
-template <int LAYOUT, int TCMODE, int EPT, typename Real>
+template <int LAYOUT, int TCMODE, int EPT, typename Real, bool SUM_FIRST>
 __global__ __launch_bounds__(1024)
 __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_kernel(
     const BlockInfo *__restrict__ binfo, const int32_t *__restrict__ stg_c,
@@ -352,6 +352,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
     Real *s_x = s_adt + nc;
     const int tid = int(threadIdx.x), T = int(blockDim.x);
     const int p0 = pred_off[pos], np = pred_off[pos + 1] - p0;
+    // a block likely to wait sums its fluxes from zero before its wait (a
+    // plan without such blocks runs the instantiation without that path)
+    const bool sum_first = SUM_FIRST && bi.sum_first != 0;
+    if (sum_first)
+        for (int u = tid; u < 4 * nc; u += T) s_inc[u] = 0.0;
 
     // local index words of this lane's slots tid, tid + T, ...
     const uint16_t *__restrict__ loc16 = reinterpret_cast<const uint16_t *>(loc + n_slots);
@@ -429,7 +434,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
     for (int j = 0; j < EPT; ++j) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) r0[j][k] = 0.0;
-        if (ready && tid + j * T < nc) load4_dev<LAYOUT>(rres, d.C, gfirst[j], r0[j]);
+        if (ready && !sum_first && tid + j * T < nc) load4_dev<LAYOUT>(rres, d.C, gfirst[j], r0[j]);
     }
 
     // fluxes of this lane's edges into registers
@@ -457,7 +462,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
         }
     }
 
-    if (ready) {  // uniform over the block
+    if (sum_first) {
+        // the accumulators were zeroed before the gather barrier
+    } else if (ready) {  // uniform over the block
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             const int t = tid + j * T;
@@ -519,23 +526,40 @@ __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 8 : 1))) void hier_flow_k
         __syncthreads();
     }
 
-    if constexpr (LAYOUT == UM_AOS) {
-        // write-through stores: lane pairs write the two 16-byte halves of a
-        // cell, so that one store instruction covers whole lines of a run of
-        // consecutive cells (a partly written line costs a second write)
-        for (int u = tid; u < 2 * nc; u += T) {
-            const int t = u >> 1, h = u & 1;
-            const f64x2 v = {s_inc[(2 * h) * nc + t], s_inc[(2 * h + 1) * nc + t]};
-            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rres,
-                                                   int32_t(32 * int64_t(cell_id(t)) + 16 * h), 0,
-                                                   CPOL_SC1);
+    if (sum_first) {
+        // wait for the earlier-coloured neighbours, then res += sums
+        if (tid < np) {
+            const int32_t *fl = flags + preds[p0 + tid];
+            dev::bounded_wait(fl, epoch, ctl, wait_ticks);
+        }
+        __syncthreads();
+        for (int t = tid; t < nc; t += T) {
+            const int32_t g = cell_id(t);
+            double r[4];
+            load4_dev<LAYOUT>(rres, d.C, g, r);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) r[k] += s_inc[k * nc + t];
+            store4_dev<LAYOUT>(rres, d.C, g, r);
         }
     } else {
-        for (int t = tid; t < nc; t += T) {
-            double r[4];
+        if constexpr (LAYOUT == UM_AOS) {
+            // write-through stores: lane pairs write the two 16-byte halves of a
+            // cell, so that one store instruction covers whole lines of a run of
+            // consecutive cells (a partly written line costs a second write)
+            for (int u = tid; u < 2 * nc; u += T) {
+                const int t = u >> 1, h = u & 1;
+                const f64x2 v = {s_inc[(2 * h) * nc + t], s_inc[(2 * h + 1) * nc + t]};
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rres,
+                                                       int32_t(32 * int64_t(cell_id(t)) + 16 * h), 0,
+                                                       CPOL_SC1);
+            }
+        } else {
+            for (int t = tid; t < nc; t += T) {
+                double r[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) r[k] = s_inc[k * nc + t];
-            store4_dev<LAYOUT>(rres, d.C, cell_id(t), r);
+                for (int k = 0; k < 4; ++k) r[k] = s_inc[k * nc + t];
+                store4_dev<LAYOUT>(rres, d.C, cell_id(t), r);
+            }
         }
     }
     // publish: every lane's stores complete, then one flag store
@@ -1001,18 +1025,25 @@ hipError_t launch_hier(const LaunchArgs &la, int32_t nblocks, int32_t base, int6
     return hipErrorInvalidValue;
 }
 
-template <int LAYOUT, int TC, int EPT, typename Real>
-hipError_t launch_flow_one(const LaunchArgs &la, int32_t nblocks, int64_t lds,
-                           const Dats<Real> &d) {
+template <int LAYOUT, int TC, int EPT, typename Real, bool SF>
+hipError_t launch_flow_sf(const LaunchArgs &la, int32_t nblocks, int64_t lds,
+                          const Dats<Real> &d) {
     clear_stale_error();
-    const hipError_t ea =
-        allow_lds(reinterpret_cast<const void *>(hier_flow_kernel<LAYOUT, TC, EPT, Real>), lds);
+    const hipError_t ea = allow_lds(
+        reinterpret_cast<const void *>(hier_flow_kernel<LAYOUT, TC, EPT, Real, SF>), lds);
     if (ea != hipSuccess) return ea;
-    hipLaunchKernelGGL((hier_flow_kernel<LAYOUT, TC, EPT, Real>), dim3(nblocks),
+    hipLaunchKernelGGL((hier_flow_kernel<LAYOUT, TC, EPT, Real, SF>), dim3(nblocks),
                        dim3(la.block_size), size_t(lds), la.stream, la.binfo, la.stg_c, la.stg_n,
                        la.crun, la.nrun, la.loc, la.n_slots, d, la.gm1, la.eps, la.pred_off,
                        la.preds, la.flags, la.err, la.wait_ticks);
     return hipGetLastError();
+}
+
+template <int LAYOUT, int TC, int EPT, typename Real>
+hipError_t launch_flow_one(const LaunchArgs &la, int32_t nblocks, int64_t lds,
+                           const Dats<Real> &d) {
+    return la.sum_first ? launch_flow_sf<LAYOUT, TC, EPT, Real, true>(la, nblocks, lds, d)
+                        : launch_flow_sf<LAYOUT, TC, EPT, Real, false>(la, nblocks, lds, d);
 }
 
 template <int TC, int EPT, typename Real, bool SF>

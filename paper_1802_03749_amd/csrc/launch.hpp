@@ -32,7 +32,7 @@ struct LaunchArgs {
     const int32_t *pred_off, *preds;
     const FlowRec *frec;      // DATAFLOW edge loop: per launch position
     int32_t gather;           // HIER, DATAFLOW: um_gather
-    int32_t sum_first;        // DATAFLOW LDS-DMA: 1 if any block sums before its wait
+    int32_t sum_first;        // DATAFLOW edge loop: 1 if any block sums before its wait
     int32_t *flags, *err;  // DATAFLOW: completion flags; err = control words [4]
     uint64_t wait_ticks;   // DATAFLOW: longest wait for one neighbour (100 MHz ticks)
     double qinf[4];        // BOUNDARY_FLUX: far-field state

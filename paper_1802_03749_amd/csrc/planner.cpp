@@ -652,8 +652,8 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     hp.reuse = hp.stg_c.empty() ? 0.0 : double(2 * E) / double(hp.stg_c.size());
     hp.avg_tcol = nb ? double(tcol_sum) / nb : 0.0;
     if (hp.schedule == UM_SCHED_DATAFLOW) {
-        // LDS-DMA gather: blocks the device holds at once, by LDS per compute
-        // unit and by its 2048 lanes.  A block whose latest awaited neighbour was launched
+        // Blocks the device holds at once, by LDS per compute unit and by its
+        // 2048 lanes.  A block whose latest awaited neighbour was launched
         // fewer positions earlier is likely to find it still running; it sums
         // its fluxes in LDS before the wait (sum_first) and afterwards only
         // adds the sums to its cells' residuals, so that a chain of waiting
@@ -680,8 +680,9 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
             for (int32_t k = 0; k < r.np && k < 8; ++k) r.preds[k] = hp.preds[r.p0 + k];
             int32_t latest = -1;
             for (int32_t k = 0; k < r.np; ++k) latest = std::max(latest, hp.preds[r.p0 + k]);
-            r.sum_first = o.gather == UM_GATHER_LDS_DMA && latest >= 0 && o.sum_first >= 0 &&
+            r.sum_first = latest >= 0 && o.sum_first >= 0 &&
                           (o.sum_first == 1 || int64_t(pos) - latest < resident);
+            hp.binfo[pos].sum_first = r.sum_first;
             hp.n_sum_first += r.sum_first;
             r.ncr = z.crun_off - a.crun_off;
             r.nnr = z.nrun_off - a.nrun_off;

@@ -260,6 +260,40 @@ def test_lds_dma_gather_medium(S, explicit, sum_first):
     L.close()
 
 
+@pytest.mark.parametrize("sum_first", ["auto", "never"])
+@pytest.mark.parametrize("layout", ["aos", "soa"])
+@pytest.mark.parametrize("S", [256, 512])
+def test_register_gather_sum_first(S, layout, sum_first):
+    """The register-gather dataflow kernel (the one SoA data uses) at
+    1200x600, where most blocks sum their fluxes before their wait by
+    default; bitwise reproducible."""
+    m, ref = mesh(1200, 600)
+    print(f"1200x600 registers S={S} {layout} sum_first={sum_first}", flush=True)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
+                     block_size=S, layout=layout)
+    p = L.plan("hier", S, schedule="dataflow", elems_per_thread=2, block_colouring="recolour",
+               sum_first=sum_first)
+    n = p.stats["n_sum_first_blocks"]
+    assert (n > p.stats["n_blocks"] // 2) if sum_first == "auto" else n == 0
+    outs = [run_once(L, p) for _ in range(2)]
+    assert rel_l2(outs[0], ref) <= TOL
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
+    L.close()
+
+
+@pytest.mark.parametrize("tcmode", ["barrier", "lds_atomic"])
+def test_register_gather_sum_first_fp32(tcmode):
+    m, _ = mesh(600, 300)
+    r32, _ = native.edge_loop_f32(m.e2n, m.e2c, m.x, m.q, m.adt)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=0, order="rcm+partition",
+                     block_size=256, dtype="f32")
+    p = L.plan("hier", 256, schedule="dataflow", elems_per_thread=2, tcmode=tcmode,
+               block_colouring="recolour", sum_first="always")
+    assert p.stats["n_sum_first_blocks"] > 0
+    assert rel_l2(run_once(L, p), r32) <= FP32_TOL
+    L.close()
+
+
 @pytest.mark.parametrize("sum_first", ["auto", "always"])
 def test_lds_dma_gather_full_size(sum_first):
     m, ref = mesh(2400, 1200)

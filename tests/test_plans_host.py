@@ -712,10 +712,11 @@ def test_xcd_groups_checked():
 
 @pytest.mark.parametrize("nx,ny,S,ept", [(60, 40, 128, 1), (300, 200, 512, 2), (900, 500, 256, 2)])
 def test_sum_first_blocks_rule(nx, ny, S, ept):
-    """Dataflow plans with the LDS-DMA gather mark a block sum-first when its
+    """Dataflow plans of the edge loop mark a block sum-first when its
     latest awaited neighbour was launched fewer positions before it than the
     blocks the device holds at once (a host-only context assumes 256 compute
-    units of 160 KiB LDS and 2048 lanes each); register-gather plans never."""
+    units of 160 KiB LDS and 2048 lanes each), with either gather; the option
+    forces it on for every block that waits, or off."""
     _, L = make(nx=nx, ny=ny, order="rcm+partition", block_size=S)
     p = L.plan("hier", S, schedule="dataflow", block_colouring="recolour", elems_per_thread=ept,
                gather="lds_dma")
@@ -734,7 +735,8 @@ def test_sum_first_blocks_rule(nx, ny, S, ept):
         "n_sum_first_blocks"] == waiting
     assert L.plan("hier", S, gather="lds_dma", sum_first="never", **kw).stats[
         "n_sum_first_blocks"] == 0
-    assert L.plan("hier", S, **kw).stats["n_sum_first_blocks"] == 0   # register gather
+    assert L.plan("hier", S, **kw).stats["n_sum_first_blocks"] == want   # register gather
+    assert L.plan("hier", S, schedule="colour_launches").stats["n_sum_first_blocks"] == 0
     o = U.um_plan_opts(); o.strategy = U.UM_STRAT_HIER; o.block_size = S; o.sum_first = 2
     with pytest.raises(U.UmeshError) as ei:
         U.um_plan_build(L.ctx, U.UM_K_EDGE_FLUX_LF2D, L.args(), L.s_edges, o)
