@@ -340,7 +340,9 @@ typedef struct {
                                   positions earlier than the blocks the
                                   device holds at once; 1 = every block with
                                   a neighbour to wait for; -1 = none.  The
-                                  results agree to rounding                 */
+                                  results agree to rounding.  (The hex
+                                  loop's dataflow blocks always sum first;
+                                  other plans ignore the field.)            */
 } um_plan_opts;
 
 typedef struct {
