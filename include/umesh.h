@@ -337,10 +337,10 @@ typedef struct {
                                   the others load their residuals early and
                                   accumulate onto them.  0 = those whose
                                   latest such neighbour is launched fewer
-                                  positions earlier than the blocks the
-                                  device holds at once; 1 = every block with
-                                  a neighbour to wait for; -1 = none.  The
-                                  results agree to rounding.  (The hex
+                                  positions earlier than 3/4 of the blocks
+                                  the device holds at once; 1 = every block
+                                  with a neighbour to wait for; -1 = none.
+                                  The results agree to rounding.  (The hex
                                   loop's dataflow blocks always sum first;
                                   other plans ignore the field.)            */
 } um_plan_opts;

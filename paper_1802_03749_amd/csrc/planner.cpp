@@ -654,11 +654,12 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
     if (hp.schedule == UM_SCHED_DATAFLOW) {
         // Blocks the device holds at once, by LDS per compute unit and by its
         // 2048 lanes.  A block whose latest awaited neighbour was launched
-        // fewer positions earlier is likely to find it still running; it sums
-        // its fluxes in LDS before the wait (sum_first) and afterwards only
-        // adds the sums to its cells' residuals, so that a chain of waiting
-        // blocks carries only that read-add-write.  The other blocks load
-        // their residuals early and accumulate onto them.
+        // fewer than 3/4 of that many positions earlier is likely to find it
+        // still running; it sums its fluxes in LDS before the wait (sum_first)
+        // and afterwards only adds the sums to its cells' residuals, so that
+        // a chain of waiting blocks carries only that read-add-write.  The
+        // other blocks load their residuals early and accumulate onto them
+        // (blocks closer to the whole resident count measured faster so).
         const int64_t per_cu = std::max<int64_t>(
             1, std::min<int64_t>(ctx.lds_per_cu / std::max<int64_t>(hp.lds_max, 1),
                                  2048 / std::max(hp.threads, 64)));
@@ -681,7 +682,7 @@ void build_host_plan(const Ctx &ctx, const EdgeArgs &ea, int32_t iter_set,
             int32_t latest = -1;
             for (int32_t k = 0; k < r.np; ++k) latest = std::max(latest, hp.preds[r.p0 + k]);
             r.sum_first = latest >= 0 && o.sum_first >= 0 &&
-                          (o.sum_first == 1 || int64_t(pos) - latest < resident);
+                          (o.sum_first == 1 || 4 * (int64_t(pos) - latest) < 3 * resident);
             hp.binfo[pos].sum_first = r.sum_first;
             hp.n_sum_first += r.sum_first;
             r.ncr = z.crun_off - a.crun_off;
