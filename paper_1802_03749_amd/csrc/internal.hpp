@@ -203,7 +203,7 @@ void build_host_plan_step(const Ctx &ctx, int32_t kernel, const StepArgs &sa, in
 
 // LDS bytes a block needs for the given counts.
 int64_t lf2d_lds_bytes(int32_t staging, int32_t dtype, int64_t n_cells, int64_t n_nodes);
-int64_t hex_lds_bytes(int64_t n_nodes);
+int64_t hex_lds_bytes(int64_t n_nodes, bool dataflow);
 
 // ----------------------------------------------------------------- device
 struct DevicePlan {

@@ -232,15 +232,21 @@ __global__ __launch_bounds__(1024) void hex_flow_kernel(
     const int32_t *__restrict__ sl = stg + bi.cell_off;
     dev::StagedIds staged_id;
     staged_id.init(runs, bi.crun_off, nr, sl);
-    double *s_acc = lds;           // [3][nn] force accumulators
-    double *s_x = s_acc + 3 * nn;  // [3][nn]
+    // force accumulators [3][nn16]: inside each aligned group of 16 nodes the
+    // index is swizzled (xor with the group number), so that the nodes one
+    // colour round updates (a regular sublattice of a brick) spread over the
+    // LDS banks instead of meeting in a few of them
+    const int nn16 = (nn + 15) & ~15;
+    auto ai = [nn16](int k, int l) { return k * nn16 + (l ^ ((l >> 4) & 15)); };
+    double *s_acc = lds;
+    double *s_x = s_acc + 3 * nn16;  // [3][nn]
     double *s_v = s_x + 3 * nn;    // [3][nn]
     int32_t *s_id = reinterpret_cast<int32_t *>(s_v + 3 * nn);  // [nn] staged node ids
     const int tid = int(threadIdx.x), T = int(blockDim.x);
     const int p0 = pred_off[pos], np = pred_off[pos + 1] - p0;
 
     const uint4 w = tid < ne ? loc[bi.slot_off + tid] : make_uint4(0, 0, 0, 0);
-    for (int u = tid; u < 3 * nn; u += T) s_acc[u] = 0.0;
+    for (int u = tid; u < 3 * nn16; u += T) s_acc[u] = 0.0;
     // both ids of a pass first, then its loads (see hex_hier_kernel); the
     // ids stay in LDS for the force accesses after the wait
     for (int t0 = tid; t0 < nn; t0 += 2 * T) {
@@ -299,7 +305,7 @@ __global__ __launch_bounds__(1024) void hex_flow_kernel(
 #pragma unroll
                 for (int a = 0; a < 8; ++a)
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) lds_add(&s_acc[k * nn + l[a]], f[a][k]);
+                    for (int k = 0; k < 3; ++k) lds_add(&s_acc[ai(k, l[a])], f[a][k]);
             }
             __syncthreads();
         }
@@ -308,7 +314,7 @@ __global__ __launch_bounds__(1024) void hex_flow_kernel(
 #pragma unroll
             for (int a = 0; a < 8; ++a)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) lds_add(&s_acc[k * nn + l[a]], f[a][k]);
+                for (int k = 0; k < 3; ++k) lds_add(&s_acc[ai(k, l[a])], f[a][k]);
         }
         __syncthreads();
     }
@@ -337,7 +343,7 @@ __global__ __launch_bounds__(1024) void hex_flow_kernel(
             const int u = u0 + j * T;
             const int t = LAYOUT == UM_AOS ? u / 3 : u % nn;
             const int k = LAYOUT == UM_AOS ? u % 3 : u / nn;
-            li[j] = k * nn + t;
+            li[j] = ai(k, t);
             off[j] = u < 3 * nn ? foff(t, k) : 0;
             g[j] = u < 3 * nn ? __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(
                                                               rf, off[j], 0, HEX_CPOL_SC1))

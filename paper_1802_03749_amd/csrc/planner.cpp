@@ -12,7 +12,11 @@
 namespace um {
 
 // x[3], v[3], force acc[3] and the staged node id
-int64_t hex_lds_bytes(int64_t nn) { return nn * (9 * 8 + 4); }
+int64_t hex_lds_bytes(int64_t nn, bool dataflow) {
+    // x, v, force accumulators (3 doubles each) and a staged id per node; the
+    // dataflow kernel pads its accumulators to groups of 16 nodes
+    return nn * (9 * 8 + 4) + (dataflow ? 3 * 8 * (((nn + 15) & ~int64_t(15)) - nn) : 0);
+}
 
 int64_t lf2d_lds_bytes(int32_t staging, int32_t dtype, int64_t nc, int64_t nn) {
     const int64_t inc = nc * 4 * 8;  // FP64 increments (res preloaded)
@@ -799,7 +803,7 @@ void build_host_plan_hex(const Ctx &ctx, const HexArgs &ha, int32_t iter_set,
                         hp.crun.push_back(Run{hp.stg_c[n0 + i], i});
         }
         for (int32_t i = 0; i < nn; ++i) nloc[hp.stg_c[n0 + i]] = -1;
-        const int64_t lds = hex_lds_bytes(nn);
+        const int64_t lds = hex_lds_bytes(nn, hp.schedule == UM_SCHED_DATAFLOW);
         if (lds > limit)
             fail(UM_ERR_LDS, "hex block %d needs %lld bytes of LDS, limit %lld", b,
                  (long long)lds, (long long)limit);
