@@ -488,6 +488,24 @@ def test_hex_plan_matches_oracle(order, S):
     assert np.array_equal(gcol, P.first_fit_elements(e2n)[0])
 
 
+@pytest.mark.parametrize("S", [128, 256, 512])
+def test_hex_lds_request_covers_the_kernels_layout(S):
+    """The LDS a hex plan asks for covers the kernels' layout for its
+    largest block: x, v and force accumulators (3 doubles each) plus a staged
+    id per node, and for the dataflow kernel the accumulators padded to whole
+    groups of 16 nodes (their index is swizzled inside each group)."""
+    m = hex_mesh(16, seed=3)
+    L = HexLoop(m.x, m.v, m.e2n, device=-1, order="rcm+partition", block_size=S)
+    for schedule in ("colour_launches", "dataflow"):
+        p = L.plan("hier", S, block_colouring="min", schedule=schedule)
+        so = L.export(p, U.UM_EXP_STAGED_OFFSETS_B)
+        nn = np.diff(so).astype(np.int64)
+        need = nn * (9 * 8 + 4)
+        if schedule == "dataflow":
+            need = need + 3 * 8 * (((nn + 15) // 16) * 16 - nn)
+        assert p.stats["lds_bytes_max"] == need.max(), schedule
+
+
 def test_hex_args_checked():
     m = hex_mesh(3, seed=1)
     L = HexLoop(m.x, m.v, m.e2n, device=-1, order="rcm")
