@@ -420,6 +420,23 @@ def test_recolour_matches_oracle(S):
     assert counts.max() - counts.min() <= np.bincount(L.export(q, U.UM_EXP_BLOCK_COLOURS)).max()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("staging", ["all", "inc"])
+def test_edge_lds_request_covers_the_kernels_layout(dtype, staging):
+    """The LDS an edge-loop plan asks for is its largest block's: binary64
+    residual accumulators (4 doubles per staged cell), and with stage-all q
+    and adt per staged cell and x per staged node in the storage type."""
+    m = quad_mesh(90, 60, seed=2)
+    L = EdgeFluxLoop(m.x, m.q, m.adt, m.e2n, m.e2c, device=-1, order="rcm+partition",
+                     block_size=256, dtype=dtype)
+    p = L.plan("hier", 256, staging=staging, allow_fallback=False)
+    nc = np.diff(L.export(p, U.UM_EXP_STAGED_OFFSETS_B)).astype(np.int64)
+    nn = np.diff(L.export(p, U.UM_EXP_STAGED_OFFSETS_A)).astype(np.int64)
+    w = 8 if dtype == "f64" else 4
+    need = 32 * nc + ((5 * w * nc + 2 * w * nn) if staging == "all" else 0)
+    assert p.stats["lds_bytes_max"] == need.max()
+
+
 def test_dataflow_plan_options():
     _, L = make(nx=40, ny=30, order="rcm+partition", block_size=128)
     p = L.plan("hier", 128, schedule="dataflow")
